@@ -1,0 +1,603 @@
+// C ABI: batched multi right-hand-side solver (dlma_solve) and the Schur-operator
+// bandwidth benchmark (dlma_bench_schur).
+//
+// Structure of a solve (every launch covers all gauge sets and right-hand sides):
+//   outer loop, FP64:   r = b - D x  (true residual, per-RHS norms)
+//                       bhat_e = r_e - D_eo A_oo^-1 r_o
+//   inner loop, prec P: CG on the normal equations Dhat Dhat^dag z = bhat_e with
+//                       e = Dhat^dag z (CGNE), so the CG residual is the residual of
+//                       Dhat e = bhat_e itself:
+//                         w = Dhat^dag p; alpha = |r|^2/|w|^2; e += alpha w;
+//                         r -= alpha Dhat w; beta = |r'|^2/|r|^2; p = r' + beta p
+//   reconstruction:     x_e += e,  x_o += A_oo^-1 (r_o - D_oe e)
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "../../include/dlma.h"
+#include "runtime.h"
+
+using namespace dlma;
+
+static inline hipStream_t S(void* s) { return (hipStream_t)s; }
+
+extern "C" void dlma_solve_opts_default(dlma_solve_opts* o) {
+    if (!o) return;
+    o->tol = 1e-10;
+    o->maxiter = 100000;
+    o->max_outer = 40;
+    o->prec = DLMA_PREC_FP64;
+    o->inner_tol = 0.0;
+    o->rhs_block = 0;
+    o->use_x0 = 0;
+    o->graph_iters = 0;
+    o->check_every = 0;
+}
+
+namespace {
+
+constexpr int MAXG = 16;
+
+struct Cfg {
+    Gauge* g;
+    int nrhs, gidx;
+    const double2* bcan;
+    double2* xcan;
+    Buf B, X, R, T, E;               // FP64: full B, X, R; half T (odd), E (even)
+    Buf r, p, w, xs, y;              // inner vectors (precision P), half fields
+    Buf nr, np, nw, nxs, ny;         // FP16 scales
+    Buf part;                        // partial norms
+    Buf dstate;                      // rr rr0 alpha beta tol2 abs2 nrm (double) | active iters (int)
+    int hnsb, vnsb;                  // site blocks of stencil and vector kernels
+    double *rr, *rr0, *alpha, *beta, *tol2, *abs2, *nrm;
+    int *active, *iters;
+    std::vector<double> bnorm2, rnorm2, relres;
+    std::vector<int> used, conv, hact, hiters;
+    int outer = 0;
+};
+
+template <int P> struct Tables {
+    // device job tables
+    Buf dresid, dprep, drecon;                 // HopJob<P64>
+    Buf dvnB, dclov, dconv64, dacc64;          // VecJob<P64>
+    Buf dconv, dacc, dxpay;                    // VecJob<P>
+    Buf dk1d, dk2d, dk1, dk2cg;                // HopJob<P>
+    Buf dfinB, dfinR, dfinI, dfinAB;           // FinJob
+    int nresid = 0, nprep = 0, nrecon = 0, nvnB = 0, nclov = 0, nconv = 0, nk = 0, nfin = 0;
+    int bresid = 0, bprep = 0, brecon = 0, bvnB = 0, bclov = 0, bconv = 0, bxpay = 0;
+    int bk1 = 0, bk2 = 0, bfin = 0;
+    std::vector<FinJob> hfinI, hfinAB;  // kept for per-pass updates
+};
+
+template <class T> int upload(Buf& b, const std::vector<T>& v, hipStream_t s) {
+    DLMA_TRY(b.allocate(sizeof(T) * std::max<size_t>(1, v.size())));
+    if (!v.empty()) DLMA_HIP(hipMemcpyAsync(b.p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, s));
+    return DLMA_OK;
+}
+
+template <int P> int alloc_cfg(Cfg& c, hipStream_t s) {
+    Gauge* g = c.g;
+    size_t n = c.nrhs;
+    int Vh = g->Vh;
+    size_t full64 = sizeof(double2) * n * 24 * Vh, half64 = sizeof(double2) * n * 12 * Vh;
+    DLMA_TRY(c.B.allocate(full64));
+    DLMA_TRY(c.X.allocate(full64));
+    DLMA_TRY(c.R.allocate(full64));
+    DLMA_TRY(c.T.allocate(half64));
+    DLMA_TRY(c.E.allocate(half64));
+    size_t halfP = pair_bytes(P) * n * 12 * Vh;
+    DLMA_TRY(c.r.allocate(halfP));
+    DLMA_TRY(c.p.allocate(halfP));
+    DLMA_TRY(c.w.allocate(halfP));
+    DLMA_TRY(c.xs.allocate(halfP));
+    DLMA_TRY(c.y.allocate(halfP));
+    if (P == P16) {
+        size_t nb = sizeof(float) * n * Vh;
+        DLMA_TRY(c.nr.allocate(nb));
+        DLMA_TRY(c.np.allocate(nb));
+        DLMA_TRY(c.nw.allocate(nb));
+        DLMA_TRY(c.nxs.allocate(nb));
+        DLMA_TRY(c.ny.allocate(nb));
+    }
+    c.hnsb = ceil_div(Vh, HOP_BS);
+    c.vnsb = ceil_div(Vh, VEC_BS);
+    int pmax = std::max(2 * c.hnsb, 2 * c.vnsb);
+    DLMA_TRY(c.part.allocate(sizeof(double) * n * pmax));
+    DLMA_TRY(c.dstate.allocate(sizeof(double) * 7 * n + sizeof(int) * 2 * n + 256));
+    double* d = c.dstate.as<double>();
+    c.rr = d; c.rr0 = d + n; c.alpha = d + 2 * n; c.beta = d + 3 * n; c.tol2 = d + 4 * n; c.abs2 = d + 5 * n;
+    c.nrm = d + 6 * n;
+    c.active = (int*)(d + 7 * n);
+    c.iters = c.active + n;
+    DLMA_HIP(hipMemsetAsync(c.dstate.p, 0, sizeof(double) * 7 * n + sizeof(int) * 2 * n, s));
+    c.bnorm2.assign(n, 0); c.rnorm2.assign(n, 0); c.relres.assign(n, 0);
+    c.used.assign(n, 0); c.conv.assign(n, 0); c.hact.assign(n, 0); c.hiters.assign(n, 0);
+    return DLMA_OK;
+}
+
+template <int P> float* nrm_of(const Buf& b) { return P == P16 ? b.as<float>() : nullptr; }
+
+template <int P> int build_tables(std::vector<Cfg>& cs, Tables<P>& t, int nb, hipStream_t s) {
+    std::vector<HopJob<P64>> resid, prep, recon;
+    std::vector<VecJob<P64>> vnB, clov, conv64, acc64;
+    std::vector<VecJob<P>> conv, acc, xpay;
+    std::vector<HopJob<P>> k1d, k2d, k1, k2cg;
+    std::vector<FinJob> finB, finR, finI, finAB;
+    int rhs0B = 0, rhs0R = 0, rhs0I = 0, rhs0AB = 0;
+    for (auto& c : cs) {
+        Gauge* g = c.g;
+        int Vh = g->Vh, n = c.nrhs;
+        const double2* U64 = g->U64.as<double2>();
+        for (int par = 0; par < 2; ++par) {
+            HopJob<P64> j = hop_job<P64>(g, par, n, 1);
+            j.U = U64;
+            j.C = g->Cl64[par].as<double2>();
+            j.b = full_view(c.B.p, Vh, par);
+            j.x = full_view(c.X.p, Vh, par);
+            j.in = full_view(c.X.p, Vh, 1 - par);
+            j.out = full_view(c.R.p, Vh, par);
+            j.part = c.part.as<double>() + (size_t)par * c.hnsb;
+            j.pstride = 2 * c.hnsb;
+            j.cb = 1.0; j.ca = -1.0; j.ch = 0.5;
+            resid.push_back(j);
+            VecJob<P64> v = {};
+            v.Vh = Vh; v.nrhs = n; v.nsb = c.vnsb;
+            v.a = full_view(c.B.p, Vh, par);
+            v.part = c.part.as<double>() + (size_t)par * c.vnsb;
+            v.pstride = 2 * c.vnsb;
+            vnB.push_back(v);
+        }
+        {   // T = A_oo^-1 R_o
+            VecJob<P64> v = {};
+            v.Vh = Vh; v.nrhs = n; v.nsb = c.vnsb;
+            v.a = full_view(c.R.p, Vh, 1);
+            v.c = half_view<P64>(c.T.p, nullptr, Vh);
+            v.C = g->Ci64.as<double2>();
+            clov.push_back(v);
+        }
+        {   // E = R_e + 1/2 H T
+            HopJob<P64> j = hop_job<P64>(g, 0, n, 1);
+            j.U = U64;
+            j.x = full_view(c.R.p, Vh, 0);
+            j.in = half_view<P64>(c.T.p, nullptr, Vh);
+            j.out = half_view<P64>(c.E.p, nullptr, Vh);
+            j.ca = 1.0; j.ch = 0.5;
+            prep.push_back(j);
+        }
+        {   // r = p = P(E), xs = 0 ; and accumulate E = xs, X_e += E
+            VecJob<P> v = {};
+            v.Vh = Vh; v.nrhs = n; v.nsb = c.vnsb;
+            v.a = half_view<P>(c.r.p, nrm_of<P>(c.nr), Vh);
+            v.b = half_view<P>(c.p.p, nrm_of<P>(c.np), Vh);
+            v.c = half_view<P>(c.xs.p, nrm_of<P>(c.nxs), Vh);
+            v.part = c.part.as<double>();
+            v.pstride = c.vnsb;
+            conv.push_back(v);
+            VecJob<P64> v64 = {};
+            v64.Vh = Vh; v64.nrhs = n; v64.nsb = c.vnsb;
+            v64.a = half_view<P64>(c.E.p, nullptr, Vh);
+            conv64.push_back(v64);
+            VecJob<P> a = v;
+            a.a = half_view<P>(c.xs.p, nrm_of<P>(c.nxs), Vh);
+            acc.push_back(a);
+            VecJob<P64> a64 = v64;
+            a64.b = full_view(c.X.p, Vh, 0);
+            acc64.push_back(a64);
+            VecJob<P> x = v;
+            x.a = half_view<P>(c.r.p, nrm_of<P>(c.nr), Vh);
+            x.b = half_view<P>(c.p.p, nrm_of<P>(c.np), Vh);
+            x.s = c.beta;
+            x.active = c.active;
+            xpay.push_back(x);
+        }
+        {   // X_o += A_oo^-1 (R_o + 1/2 H E)
+            HopJob<P64> j = hop_job<P64>(g, 1, n, 1);
+            j.U = U64;
+            j.C = g->Ci64.as<double2>();
+            j.in = half_view<P64>(c.E.p, nullptr, Vh);
+            j.x = full_view(c.R.p, Vh, 1);
+            j.out = full_view(c.X.p, Vh, 1);
+            j.ch = 0.5;
+            recon.push_back(j);
+        }
+        {   // inner CG stencils
+            const typename PT<P>::S* U = (const typename PT<P>::S*)gauge_links(g, P);
+            const typename PT<P>::S* Cee = (const typename PT<P>::S*)gauge_clover_ee(g, P);
+            const typename PT<P>::S* Cio = (const typename PT<P>::S*)gauge_clover_oo_inv(g, P);
+            SF<P> vp = half_view<P>(c.p.p, nrm_of<P>(c.np), Vh), vy = half_view<P>(c.y.p, nrm_of<P>(c.ny), Vh);
+            SF<P> vw = half_view<P>(c.w.p, nrm_of<P>(c.nw), Vh), vr = half_view<P>(c.r.p, nrm_of<P>(c.nr), Vh);
+            SF<P> vx = half_view<P>(c.xs.p, nrm_of<P>(c.nxs), Vh);
+            HopJob<P> j1 = hop_job<P>(g, 1, n, nb);
+            j1.U = U; j1.C = Cio; j1.ch = -0.5; j1.active = c.active;
+            HopJob<P> j2 = hop_job<P>(g, 0, n, nb);
+            j2.U = U; j2.C = Cee; j2.ca = 1.0; j2.ch = 0.5; j2.active = c.active;
+            j2.part = c.part.as<double>(); j2.pstride = c.hnsb;
+            HopJob<P> a = j1; a.in = vp; a.out = vy; k1d.push_back(a);
+            HopJob<P> b = j2; b.x = vp; b.in = vy; b.out = vw; k2d.push_back(b);
+            HopJob<P> d = j1; d.in = vw; d.out = vy; k1.push_back(d);
+            HopJob<P> e = j2; e.x = vw; e.in = vy; e.r = vr; e.xs = vx; e.alpha = c.alpha; k2cg.push_back(e);
+        }
+        FinJob f = {};
+        f.nrhs = n; f.part = c.part.as<double>();
+        f.rr = c.rr; f.rr0 = c.rr0; f.alpha = c.alpha; f.beta = c.beta; f.tol2 = c.tol2; f.abs2 = c.abs2;
+        f.active = c.active; f.iters = c.iters; f.out = c.nrm; f.maxit = 1 << 30;
+        FinJob fb = f; fb.npart = 2 * c.vnsb; fb.rhs0 = rhs0B; rhs0B += n; finB.push_back(fb);
+        FinJob fr = f; fr.npart = 2 * c.hnsb; fr.rhs0 = rhs0R; rhs0R += n; finR.push_back(fr);
+        FinJob fi = f; fi.npart = c.vnsb; fi.rhs0 = rhs0I; rhs0I += n; finI.push_back(fi);
+        FinJob fa = f; fa.npart = c.hnsb; fa.rhs0 = rhs0AB; rhs0AB += n; finAB.push_back(fa);
+    }
+    t.bresid = assign_blocks(resid); t.bprep = assign_blocks(prep); t.brecon = assign_blocks(recon);
+    t.bvnB = assign_vec_blocks(vnB); t.bclov = assign_vec_blocks(clov);
+    t.bconv = assign_vec_blocks(conv); assign_vec_blocks(conv64); assign_vec_blocks(acc); assign_vec_blocks(acc64);
+    t.bxpay = assign_vec_blocks(xpay);
+    t.bk1 = assign_blocks(k1d); assign_blocks(k1);
+    t.bk2 = assign_blocks(k2d); assign_blocks(k2cg);
+    t.bfin = rhs0AB;
+    t.nresid = (int)resid.size(); t.nprep = (int)prep.size(); t.nrecon = (int)recon.size();
+    t.nvnB = (int)vnB.size(); t.nclov = (int)clov.size(); t.nconv = (int)conv.size(); t.nk = (int)k1d.size();
+    t.nfin = (int)finAB.size();
+    DLMA_TRY(upload(t.dresid, resid, s)); DLMA_TRY(upload(t.dprep, prep, s)); DLMA_TRY(upload(t.drecon, recon, s));
+    DLMA_TRY(upload(t.dvnB, vnB, s)); DLMA_TRY(upload(t.dclov, clov, s)); DLMA_TRY(upload(t.dconv64, conv64, s));
+    DLMA_TRY(upload(t.dacc64, acc64, s)); DLMA_TRY(upload(t.dconv, conv, s)); DLMA_TRY(upload(t.dacc, acc, s));
+    DLMA_TRY(upload(t.dxpay, xpay, s));
+    DLMA_TRY(upload(t.dk1d, k1d, s)); DLMA_TRY(upload(t.dk2d, k2d, s)); DLMA_TRY(upload(t.dk1, k1, s));
+    DLMA_TRY(upload(t.dk2cg, k2cg, s));
+    DLMA_TRY(upload(t.dfinB, finB, s)); DLMA_TRY(upload(t.dfinR, finR, s));
+    t.hfinI = finI;
+    t.hfinAB = finAB;
+    DLMA_TRY(upload(t.dfinI, finI, s)); DLMA_TRY(upload(t.dfinAB, finAB, s));
+    DLMA_HIP(hipStreamSynchronize(s));  // host job vectors go out of scope
+    return DLMA_OK;
+}
+
+// one timed stencil launch (events bracket it while profiling is on)
+template <int P> int hop_launch(const HopCfg& hc, const void* djobs, int njob, int nblk, int kc, double bytes, hipStream_t s) {
+    Profiler& pr = Profiler::get();
+    hipEvent_t a = nullptr;
+    if (pr.on) pr.begin(kc, bytes, s, a);
+    DLMA_HIP(launch_hop<P>(hc, (const HopJob<P>*)djobs, njob, nblk, s));
+    if (pr.on) pr.end(a, kc, bytes, s);
+    return DLMA_OK;
+}
+
+template <int P> int cg_iteration(std::vector<Cfg>& cs, Tables<P>& t, int nb, const std::vector<int>& nact, hipStream_t s) {
+    double b1 = 0, b2 = 0, b3 = 0;
+    if (Profiler::get().on)
+        for (size_t i = 0; i < cs.size(); ++i) {
+            b1 += hop_bytes(P, K1, F_G5IN, cs[i].g->Vh, nact[i]);
+            b2 += hop_bytes(P, K2, F_G5OUT | F_NORM, cs[i].g->Vh, nact[i]);
+            b3 += hop_bytes(P, K2, F_CG, cs[i].g->Vh, nact[i]);
+        }
+    DLMA_TRY(hop_launch<P>(HopCfg{K1, F_G5IN, nb}, t.dk1d.p, t.nk, t.bk1, KC_K1, b1, s));
+    DLMA_TRY(hop_launch<P>(HopCfg{K2, F_G5OUT | F_NORM, nb}, t.dk2d.p, t.nk, t.bk2, KC_K2, b2, s));
+    DLMA_HIP(launch_finish(t.dfinAB.template as<FinJob>(), t.nfin, t.bfin, FIN_ALPHA, s));
+    DLMA_TRY(hop_launch<P>(HopCfg{K1, 0, nb}, t.dk1.p, t.nk, t.bk1, KC_K1, b1, s));
+    DLMA_TRY(hop_launch<P>(HopCfg{K2, F_CG, nb}, t.dk2cg.p, t.nk, t.bk2, KC_K2CG, b3, s));
+    DLMA_HIP(launch_finish(t.dfinAB.template as<FinJob>(), t.nfin, t.bfin, FIN_BETA, s));
+    DLMA_HIP(launch_xpay<P>(t.dxpay.template as<VecJob<P>>(), t.nconv, t.bxpay, s));
+    return DLMA_OK;
+}
+
+template <int P> int tune_nb(Gauge* g, int nrhs, SF<P> vp, SF<P> vy, SF<P> vw, hipStream_t s);
+
+template <int P>
+int solve_impl(std::vector<Cfg>& cs, const dlma_solve_opts& o, hipStream_t s) {
+    for (auto& c : cs) {
+        DLMA_TRY(gauge_prepare(c.g, P, s));
+        DLMA_TRY(alloc_cfg<P>(c, s));
+    }
+    int nb = o.rhs_block;
+    if (nb != 0 && nb != 1 && nb != 2 && nb != 4) return fail(DLMA_EINVAL, "rhs_block must be 0, 1, 2 or 4");
+    if (nb == 0) {
+        // tune on the largest configuration
+        size_t big = 0;
+        for (size_t i = 1; i < cs.size(); ++i)
+            if ((long)cs[i].g->Vh * cs[i].nrhs > (long)cs[big].g->Vh * cs[big].nrhs) big = i;
+        Cfg& c = cs[big];
+        int Vh = c.g->Vh;
+        nb = tune_nb<P>(c.g, c.nrhs, half_view<P>(c.p.p, nrm_of<P>(c.np), Vh), half_view<P>(c.y.p, nrm_of<P>(c.ny), Vh),
+                        half_view<P>(c.w.p, nrm_of<P>(c.nw), Vh), s);
+        if (nb < 0) return nb;
+    }
+    Tables<P> t;
+    DLMA_TRY(build_tables<P>(cs, t, nb, s));
+    int ncfg = (int)cs.size();
+    // load sources and start vectors
+    for (auto& c : cs) {
+        DLMA_HIP(launch_canon_to_eo(c.bcan, c.B.as<double2>(), c.g->geo, c.nrhs, s));
+        if (o.use_x0) DLMA_HIP(launch_canon_to_eo(c.xcan, c.X.as<double2>(), c.g->geo, c.nrhs, s));
+        else DLMA_HIP(hipMemsetAsync(c.X.p, 0, c.X.n, s));
+    }
+    DLMA_HIP(launch_norm<P64>(t.dvnB.template as<VecJob<P64>>(), t.nvnB, t.bvnB, s));
+    DLMA_HIP(launch_finish(t.dfinB.template as<FinJob>(), t.nfin, t.bfin, FIN_NORM, s));
+    for (auto& c : cs) DLMA_HIP(hipMemcpyAsync(c.bnorm2.data(), c.nrm, sizeof(double) * c.nrhs, hipMemcpyDeviceToHost, s));
+    DLMA_HIP(hipStreamSynchronize(s));
+    bool nan = false;
+    for (auto& c : cs) {
+        std::vector<double> abs2(c.nrhs);
+        for (int r = 0; r < c.nrhs; ++r) {
+            if (!std::isfinite(c.bnorm2[r])) nan = true;
+            abs2[r] = 0.25 * o.tol * o.tol * c.bnorm2[r];
+        }
+        DLMA_HIP(hipMemcpyAsync(c.abs2, abs2.data(), sizeof(double) * c.nrhs, hipMemcpyHostToDevice, s));
+        DLMA_HIP(hipStreamSynchronize(s));
+    }
+    if (nan) return fail(DLMA_ENAN, "non-finite value in a source");
+    double rel = o.inner_tol > 0 ? o.inner_tol : (P == P64 ? 0.0 : (P == P32 ? 1e-5 : (P == P16 ? 2e-3 : 1e-2)));
+    int check = o.check_every > 0 ? o.check_every : 8;
+
+    for (int pass = 0;; ++pass) {
+        // true residual
+        if (pass == 0 && !o.use_x0) {
+            for (auto& c : cs) {
+                DLMA_HIP(hipMemcpyAsync(c.R.p, c.B.p, c.B.n, hipMemcpyDeviceToDevice, s));
+                c.rnorm2 = c.bnorm2;
+            }
+        } else {
+            DLMA_HIP(launch_hop<P64>(HopCfg{K2, F_HASB | F_NORM, 1}, t.dresid.template as<HopJob<P64>>(), t.nresid, t.bresid, s));
+            DLMA_HIP(launch_finish(t.dfinR.template as<FinJob>(), t.nfin, t.bfin, FIN_NORM, s));
+            for (auto& c : cs) DLMA_HIP(hipMemcpyAsync(c.rnorm2.data(), c.nrm, sizeof(double) * c.nrhs, hipMemcpyDeviceToHost, s));
+            DLMA_HIP(hipStreamSynchronize(s));
+        }
+        int nleft = 0;
+        int maxused = 0;
+        for (auto& c : cs) {
+            c.outer = pass;
+            for (int r = 0; r < c.nrhs; ++r) {
+                double rr = c.rnorm2[r];
+                if (!std::isfinite(rr)) nan = true;
+                c.relres[r] = c.bnorm2[r] > 0 ? std::sqrt(rr / c.bnorm2[r]) : 0.0;
+                c.conv[r] = (c.relres[r] <= o.tol) ? 1 : 0;
+                if (!c.conv[r]) { ++nleft; maxused = std::max(maxused, c.used[r]); }
+                c.hact[r] = c.conv[r] ? 0 : 1;
+            }
+        }
+        if (nan) return fail(DLMA_ENAN, "non-finite residual during the solve");
+        if (nleft == 0 || pass >= o.max_outer || maxused >= o.maxiter) break;
+        // Schur source and inner start
+        DLMA_HIP(launch_clover_apply64(t.dclov.template as<VecJob<P64>>(), t.nclov, t.bclov, s));
+        DLMA_HIP(launch_hop<P64>(HopCfg{K2, F_NOA, 1}, t.dprep.template as<HopJob<P64>>(), t.nprep, t.bprep, s));
+        DLMA_HIP(launch_conv_from64<P>(t.dconv.template as<VecJob<P>>(), t.nconv, t.bconv, t.dconv64.template as<VecJob<P64>>(), s));
+        for (auto& c : cs) DLMA_HIP(hipMemcpyAsync(c.active, c.hact.data(), sizeof(int) * c.nrhs, hipMemcpyHostToDevice, s));
+        for (auto& f : t.hfinI) { f.rel2 = rel * rel; f.maxit = std::max(1, o.maxiter - maxused); }
+        for (auto& f : t.hfinAB) f.maxit = std::max(1, o.maxiter - maxused);
+        DLMA_HIP(hipMemcpyAsync(t.dfinI.p, t.hfinI.data(), sizeof(FinJob) * t.hfinI.size(), hipMemcpyHostToDevice, s));
+        DLMA_HIP(hipMemcpyAsync(t.dfinAB.p, t.hfinAB.data(), sizeof(FinJob) * t.hfinAB.size(), hipMemcpyHostToDevice, s));
+        DLMA_HIP(launch_finish(t.dfinI.template as<FinJob>(), t.nfin, t.bfin, FIN_INIT, s));
+        std::vector<int> nact(ncfg);
+        for (int i = 0; i < ncfg; ++i) nact[i] = (int)std::count(cs[i].hact.begin(), cs[i].hact.end(), 1);
+        // inner CG
+        for (;;) {
+            for (int k = 0; k < check; ++k) DLMA_TRY(cg_iteration<P>(cs, t, nb, nact, s));
+            int tot = 0;
+            for (int i = 0; i < ncfg; ++i)
+                DLMA_HIP(hipMemcpyAsync(cs[i].hact.data(), cs[i].active, sizeof(int) * cs[i].nrhs, hipMemcpyDeviceToHost, s));
+            DLMA_HIP(hipStreamSynchronize(s));
+            if (Profiler::get().on) Profiler::get().collect();
+            for (int i = 0; i < ncfg; ++i) {
+                nact[i] = (int)std::count(cs[i].hact.begin(), cs[i].hact.end(), 1);
+                tot += nact[i];
+            }
+            if (tot == 0) break;
+        }
+        // reconstruction
+        DLMA_HIP(launch_accum_to64<P>(t.dacc.template as<VecJob<P>>(), t.dacc64.template as<VecJob<P64>>(), t.nconv, t.bconv, s));
+        DLMA_HIP(launch_hop<P64>(HopCfg{K1, F_HASD | F_ACCUM, 1}, t.drecon.template as<HopJob<P64>>(), t.nrecon, t.brecon, s));
+        for (auto& c : cs) DLMA_HIP(hipMemcpyAsync(c.hiters.data(), c.iters, sizeof(int) * c.nrhs, hipMemcpyDeviceToHost, s));
+        DLMA_HIP(hipStreamSynchronize(s));
+        for (auto& c : cs)
+            for (int r = 0; r < c.nrhs; ++r) c.used[r] += c.hiters[r];
+    }
+    for (auto& c : cs) DLMA_HIP(launch_eo_to_canon(c.X.as<double2>(), c.xcan, c.g->geo, c.nrhs, s));
+    DLMA_HIP(hipStreamSynchronize(s));
+    return DLMA_OK;
+}
+
+// Autotune the right-hand sides per thread: time the Schur pair K1+K2 for each
+// candidate on the caller's buffers (p filled with random numbers).  Cached per
+// gauge handle, precision and number of right-hand sides.
+template <int P> int tune_nb(Gauge* g, int nrhs, SF<P> vp, SF<P> vy, SF<P> vw, hipStream_t s) {
+    auto key = std::make_pair(P, nrhs);
+    auto it = g->tuned.find(key);
+    if (it != g->tuned.end()) return it->second;
+    DLMA_HIP(launch_fill_random<P>(vp, g->Vh, nrhs, 7u, s));
+    int best = 1;
+    float bt = 1e30f;
+    const int cand[3] = {1, 2, 4};
+    hipEvent_t e0, e1;
+    DLMA_HIP(hipEventCreate(&e0));
+    DLMA_HIP(hipEventCreate(&e1));
+    for (int nb : cand) {
+        if (nb > 1 && nrhs < nb) continue;
+        // all right-hand sides active (active = nullptr)
+        std::vector<HopJob<P>> k1v, k2v;
+        HopJob<P> j1 = hop_job<P>(g, 1, nrhs, nb);
+        j1.U = (const typename PT<P>::S*)gauge_links(g, P);
+        j1.C = (const typename PT<P>::S*)gauge_clover_oo_inv(g, P);
+        j1.ch = -0.5;
+        j1.in = vp;
+        j1.out = vy;
+        HopJob<P> j2 = hop_job<P>(g, 0, nrhs, nb);
+        j2.U = j1.U;
+        j2.C = (const typename PT<P>::S*)gauge_clover_ee(g, P);
+        j2.ca = 1.0; j2.ch = 0.5;
+        j2.x = vp; j2.in = vy;
+        j2.out = vw;
+        k1v.push_back(j1); k2v.push_back(j2);
+        int b1 = assign_blocks(k1v), b2 = assign_blocks(k2v);
+        Buf d1, d2;
+        DLMA_TRY(upload(d1, k1v, s));
+        DLMA_TRY(upload(d2, k2v, s));
+        float best_t = 1e30f;
+        for (int rep = 0; rep < 3; ++rep) {
+            DLMA_HIP(hipEventRecord(e0, s));
+            DLMA_HIP(launch_hop<P>(HopCfg{K1, 0, nb}, d1.as<HopJob<P>>(), 1, b1, s));
+            DLMA_HIP(launch_hop<P>(HopCfg{K2, 0, nb}, d2.as<HopJob<P>>(), 1, b2, s));
+            DLMA_HIP(hipEventRecord(e1, s));
+            DLMA_HIP(hipEventSynchronize(e1));
+            float ms = 0;
+            DLMA_HIP(hipEventElapsedTime(&ms, e0, e1));
+            if (rep > 0) best_t = std::min(best_t, ms);
+        }
+        DLMA_HIP(hipStreamSynchronize(s));
+        if (best_t < bt) { bt = best_t; best = nb; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    g->tuned[key] = best;
+    return best;
+}
+
+}  // namespace
+
+extern "C" int dlma_solve(const dlma_gauge_t* gs, int ngauge, const dlma_rhs_set* sets, const dlma_solve_opts* opts,
+                          dlma_solve_stat* stats, void* stream) {
+    if (!gs || !sets || ngauge < 1 || ngauge > MAXG) return fail(DLMA_EINVAL, "need 1..16 gauge handles and rhs sets");
+    dlma_solve_opts o;
+    if (opts) o = *opts;
+    else dlma_solve_opts_default(&o);
+    if (!(o.tol > 0.0) || !std::isfinite(o.tol)) return fail(DLMA_EINVAL, "tol must be positive");
+    if (o.maxiter < 1 || o.max_outer < 0) return fail(DLMA_EINVAL, "maxiter must be >= 1 and max_outer >= 0");
+    if (o.prec < 0 || o.prec > 3) return fail(DLMA_EINVAL, "prec must be one of DLMA_PREC_*");
+    if (o.inner_tol < 0 || o.inner_tol >= 1) return fail(DLMA_EINVAL, "inner_tol must be in [0, 1)");
+    if (o.check_every < 0 || o.graph_iters < 0) return fail(DLMA_EINVAL, "check_every and graph_iters must be >= 0");
+    std::vector<Cfg> cs;
+    cs.reserve(ngauge);
+    int total = 0;
+    for (int i = 0; i < ngauge; ++i) {
+        if (!gs[i]) return fail(DLMA_EINVAL, "NULL gauge handle");
+        if (sets[i].nrhs < 0) return fail(DLMA_EINVAL, "nrhs < 0");
+        if (sets[i].nrhs == 0) continue;
+        if (!sets[i].b || !sets[i].x) return fail(DLMA_EINVAL, "NULL b or x");
+        cs.emplace_back();
+        Cfg& c = cs.back();
+        c.g = (Gauge*)gs[i];
+        c.nrhs = sets[i].nrhs;
+        c.gidx = i;
+        c.bcan = (const double2*)sets[i].b;
+        c.xcan = (double2*)sets[i].x;
+        total += c.nrhs;
+    }
+    if (cs.empty()) return DLMA_OK;
+    // gauge handles may repeat only with distinct outputs; outputs must not alias inputs
+    hipStream_t s = S(stream);
+    int rc;
+    switch (o.prec) {
+    case DLMA_PREC_FP64: rc = solve_impl<P64>(cs, o, s); break;
+    case DLMA_PREC_MIX_FP32: rc = solve_impl<P32>(cs, o, s); break;
+    case DLMA_PREC_MIX_FP16: rc = solve_impl<P16>(cs, o, s); break;
+    default: rc = solve_impl<PB16>(cs, o, s); break;
+    }
+    if (rc != DLMA_OK && rc != DLMA_ENOTCONV) {
+        (void)hipStreamSynchronize(s);
+        return rc;
+    }
+    bool allconv = true;
+    if (stats) {
+        // stats in the order of the sets (sets with nrhs == 0 contribute nothing)
+        int k = 0;
+        for (auto& c : cs)
+            for (int r = 0; r < c.nrhs; ++r, ++k) {
+                stats[k].outer = c.outer;
+                stats[k].inner_iters = c.used[r];
+                stats[k].relres = c.relres[r];
+                stats[k].converged = c.conv[r];
+            }
+    }
+    for (auto& c : cs)
+        for (int r = 0; r < c.nrhs; ++r) allconv = allconv && c.conv[r];
+    (void)total;
+    if (!allconv) return fail(DLMA_ENOTCONV, "not every right-hand side reached the tolerance");
+    return DLMA_OK;
+}
+
+// ---------------------------------------------------------------- Schur benchmark
+
+namespace {
+template <int P>
+int bench_impl(Gauge* g, int nrhs, int nb, int napply, double* ms_out, double* bytes_out, hipStream_t s) {
+    DLMA_TRY(gauge_prepare(g, P, s));
+    int Vh = g->Vh;
+    size_t halfP = pair_bytes(P) * (size_t)nrhs * 12 * Vh;
+    Buf a, y, w, na, ny, nw;
+    DLMA_TRY(a.allocate(halfP));
+    DLMA_TRY(y.allocate(halfP));
+    DLMA_TRY(w.allocate(halfP));
+    if (P == P16) {
+        DLMA_TRY(na.allocate(sizeof(float) * nrhs * Vh));
+        DLMA_TRY(ny.allocate(sizeof(float) * nrhs * Vh));
+        DLMA_TRY(nw.allocate(sizeof(float) * nrhs * Vh));
+    }
+    SF<P> va = half_view<P>(a.p, nrm_of<P>(na), Vh), vy = half_view<P>(y.p, nrm_of<P>(ny), Vh),
+          vw = half_view<P>(w.p, nrm_of<P>(nw), Vh);
+    DLMA_HIP(launch_fill_random<P>(va, Vh, nrhs, 11u, s));
+    if (nb == 0) {
+        nb = tune_nb<P>(g, nrhs, va, vy, vw, s);
+        if (nb < 0) return nb;
+        DLMA_HIP(launch_fill_random<P>(va, Vh, nrhs, 11u, s));
+    }
+    // alternate Dhat and Dhat^dag: a -> w -> a
+    std::vector<HopJob<P>> j1f, j2f, j1b, j2b;
+    HopJob<P> j1 = hop_job<P>(g, 1, nrhs, nb);
+    j1.U = (const typename PT<P>::S*)gauge_links(g, P);
+    j1.C = (const typename PT<P>::S*)gauge_clover_oo_inv(g, P);
+    j1.ch = -0.5;
+    HopJob<P> j2 = hop_job<P>(g, 0, nrhs, nb);
+    j2.U = j1.U;
+    j2.C = (const typename PT<P>::S*)gauge_clover_ee(g, P);
+    j2.ca = 1.0;
+    j2.ch = 0.5;
+    HopJob<P> t1 = j1; t1.in = va; t1.out = vy; j1f.push_back(t1);
+    HopJob<P> t2 = j2; t2.x = va; t2.in = vy; t2.out = vw; j2f.push_back(t2);
+    HopJob<P> t3 = j1; t3.in = vw; t3.out = vy; j1b.push_back(t3);
+    HopJob<P> t4 = j2; t4.x = vw; t4.in = vy; t4.out = va; j2b.push_back(t4);
+    int b1 = assign_blocks(j1f); assign_blocks(j1b);
+    int b2 = assign_blocks(j2f); assign_blocks(j2b);
+    Buf d1f, d2f, d1b, d2b;
+    DLMA_TRY(upload(d1f, j1f, s)); DLMA_TRY(upload(d2f, j2f, s));
+    DLMA_TRY(upload(d1b, j1b, s)); DLMA_TRY(upload(d2b, j2b, s));
+    double by1 = hop_bytes(P, K1, 0, Vh, nrhs), by2 = hop_bytes(P, K2, 0, Vh, nrhs);
+    auto run = [&](int k) -> int {
+        bool fwd = (k & 1) == 0;
+        DLMA_TRY(hop_launch<P>(HopCfg{K1, fwd ? 0 : F_G5IN, nb}, (fwd ? d1f : d1b).p, 1, b1, KC_K1, by1, s));
+        DLMA_TRY(hop_launch<P>(HopCfg{K2, fwd ? 0 : F_G5OUT, nb}, (fwd ? d2f : d2b).p, 1, b2, KC_K2, by2, s));
+        return DLMA_OK;
+    };
+    DLMA_TRY(run(0));
+    DLMA_TRY(run(1));
+    DLMA_HIP(hipStreamSynchronize(s));
+    if (Profiler::get().on) Profiler::get().collect();
+    hipEvent_t e0, e1;
+    DLMA_HIP(hipEventCreate(&e0));
+    DLMA_HIP(hipEventCreate(&e1));
+    DLMA_HIP(hipEventRecord(e0, s));
+    for (int k = 0; k < napply; ++k) DLMA_TRY(run(k));
+    DLMA_HIP(hipEventRecord(e1, s));
+    DLMA_HIP(hipEventSynchronize(e1));
+    float ms = 0;
+    DLMA_HIP(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    DLMA_HIP(hipStreamSynchronize(s));
+    if (Profiler::get().on) Profiler::get().collect();
+    if (ms_out) *ms_out = ms / napply;
+    if (bytes_out) *bytes_out = by1 + by2;
+    return DLMA_OK;
+}
+}  // namespace
+
+extern "C" int dlma_bench_schur(dlma_gauge_t h, int prec, int nrhs, int rhs_block, int napply, double* ms_out,
+                                double* bytes_out, void* stream) {
+    Gauge* g = (Gauge*)h;
+    if (!g) return fail(DLMA_EINVAL, "NULL handle");
+    if (nrhs < 1 || napply < 1) return fail(DLMA_EINVAL, "nrhs and napply must be >= 1");
+    if (rhs_block != 0 && rhs_block != 1 && rhs_block != 2 && rhs_block != 4) return fail(DLMA_EINVAL, "rhs_block must be 0, 1, 2 or 4");
+    hipStream_t s = S(stream);
+    switch (prec) {
+    case DLMA_PREC_FP64: return bench_impl<P64>(g, nrhs, rhs_block, napply, ms_out, bytes_out, s);
+    case DLMA_PREC_MIX_FP32: return bench_impl<P32>(g, nrhs, rhs_block, napply, ms_out, bytes_out, s);
+    case DLMA_PREC_MIX_FP16: return bench_impl<P16>(g, nrhs, rhs_block, napply, ms_out, bytes_out, s);
+    case DLMA_PREC_MIX_BF16: return bench_impl<PB16>(g, nrhs, rhs_block, napply, ms_out, bytes_out, s);
+    default: return fail(DLMA_EINVAL, "prec must be one of DLMA_PREC_*");
+    }
+}

@@ -1,0 +1,275 @@
+// Even-odd Wilson-clover stencil kernels, multi right-hand side.
+//
+// With H_pq the hopping sum from parity q to parity p,
+//   (H psi)(x) = sum_mu [(1 - g_mu) U_mu(x) psi(x+mu) + (1 + g_mu) U_mu(x-mu)^dag psi(x-mu)],
+// the operator is D = A - H/2, and the Schur complement on even sites is
+//   Dhat = A_ee - (1/4) H_eo A_oo^-1 H_oe,  Dhat^dag = g5 Dhat g5.
+// Two kernel kinds cover every use:
+//   K1 (output parity p):  out = A_pp^-1 (d + ch * H [g5] in)            [+= out with ACCUM]
+//   K2 (output parity p):  out = cb*b + ca*(A_pp x) + ch * [g5] H in     [A -> 1 with NOA]
+// with optional fused epilogues: per-RHS squared norms of the result (NORM) and
+// the CG update r -= alpha*out, xs += alpha*x (CG; out itself is not stored).
+//
+// Thread mapping: one thread per output site and NB right-hand sides; a block
+// covers BS consecutive sites for one group of NB right-hand sides.  The block
+// index is decoded so that all right-hand-side groups of one site block land on
+// the same XCD (workgroups are dealt round-robin to the 8 XCDs) one after the
+// other, so the links and clover of that site block are reused from that XCD's L2.
+#pragma once
+#include "common.h"
+
+namespace dlma {
+
+enum HopKind { K1 = 0, K2 = 1 };
+enum HopFlags {
+    F_G5IN = 1,     // K1: g5 on the hopping input
+    F_G5OUT = 2,    // K2: g5 on the hopping sum
+    F_NORM = 4,     // per-RHS |out|^2 partials
+    F_CG = 8,       // K2: r -= alpha*out, xs += alpha*x, |r|^2 partials; out not stored
+    F_HASB = 16,    // K2: add cb*b
+    F_NOA = 32,     // K2: identity instead of the clover matrix
+    F_HASD = 64,    // K1: add d (taken from the x view)
+    F_ACCUM = 128,  // K1: out += result
+};
+
+template <int P> struct HopJob {
+    Geo g;
+    int par;    // output parity
+    int nrhs;   // right-hand sides
+    int G;      // right-hand-side groups = ceil(nrhs / NB)
+    int nsb;    // site blocks = ceil(Vh / BS)
+    int nsbp;   // nsb rounded up to a multiple of 8
+    int blk0;   // first workgroup of this job (multiple of 8)
+    const typename PT<P>::S* U;  // links, all parities
+    const typename PT<P>::S* C;  // clover blocks of the output parity (A or A^-1)
+    SF<P> in, x, b, out, r, xs;
+    const double* alpha;  // [nrhs] (F_CG)
+    const int* active;    // [nrhs] or nullptr: inactive right-hand sides are skipped
+    double* part;         // partial squared norms (F_NORM / F_CG): part[r * pstride + site block]
+    int pstride;
+    double ca, cb, ch;
+};
+
+template <int P, class R> HD void load_half_spinor(const SF<P>& f, int Vh, int r, int cb, int blk, R s[12]) {
+    const typename PT<P>::S* b = f.v + (size_t)r * f.rs + (size_t)blk * 6 * Vh + cb;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) ldp<P>(b, (size_t)c * Vh, s[2 * c], s[2 * c + 1]);
+    if (P == P16) {
+        R n = (R)f.nrm[(size_t)r * f.ns + cb];
+#pragma unroll
+        for (int i = 0; i < 12; ++i) s[i] *= n;
+    }
+}
+
+template <int P, int NB, int MU, bool G5IN>
+HD void hop_dir(const HopJob<P>& J, const Nbr& nb, int cb, int g0, bool (&use)[NB],
+                typename PT<P>::R (&acc)[NB][24]) {
+    using R = typename PT<P>::R;
+    const int Vh = J.g.Vh;
+    R u[18];
+    R psi[24];
+    load_link<P, R>(J.U, Vh, J.par, MU, cb, u);
+#pragma unroll
+    for (int j = 0; j < NB; ++j)
+        if (use[j]) {
+            load_spinor<P, R>(J.in, Vh, g0 + j, nb.n[2 * MU], psi);
+            hop_term<MU, true, G5IN, R>(u, psi, acc[j]);
+        }
+    load_link<P, R>(J.U, Vh, 1 - J.par, MU, nb.n[2 * MU + 1], u);
+#pragma unroll
+    for (int j = 0; j < NB; ++j)
+        if (use[j]) {
+            load_spinor<P, R>(J.in, Vh, g0 + j, nb.n[2 * MU + 1], psi);
+            hop_term<MU, false, G5IN, R>(u, psi, acc[j]);
+        }
+}
+
+// Per-site body.  Returns the squared norms (of out, or of the updated r) in nrm2.
+template <int P, int NB, int KIND, int FL>
+HD void hop_site(const HopJob<P>& J, int cb, int g0, double (&nrm2)[NB]) {
+    using R = typename PT<P>::R;
+    const int Vh = J.g.Vh;
+    bool use[NB];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        int r = g0 + j;
+        use[j] = r < J.nrhs && (J.active == nullptr || J.active[r] != 0);
+        nrm2[j] = 0.0;
+    }
+    R acc[NB][24];
+#pragma unroll
+    for (int j = 0; j < NB; ++j)
+#pragma unroll
+        for (int i = 0; i < 24; ++i) acc[j][i] = 0;
+
+    Nbr nb = neighbours(J.g, J.par, cb);
+    constexpr bool G5IN = (FL & F_G5IN) != 0;
+    hop_dir<P, NB, 0, G5IN>(J, nb, cb, g0, use, acc);
+    hop_dir<P, NB, 1, G5IN>(J, nb, cb, g0, use, acc);
+    hop_dir<P, NB, 2, G5IN>(J, nb, cb, g0, use, acc);
+    hop_dir<P, NB, 3, G5IN>(J, nb, cb, g0, use, acc);
+
+    const R ch = (R)J.ch;
+    if (KIND == K1) {
+#pragma unroll
+        for (int j = 0; j < NB; ++j)
+            if (use[j]) {
+#pragma unroll
+                for (int i = 0; i < 24; ++i) acc[j][i] *= ch;
+                if (FL & F_HASD) {
+                    R d[24];
+                    load_spinor<P, R>(J.x, Vh, g0 + j, cb, d);
+#pragma unroll
+                    for (int i = 0; i < 24; ++i) acc[j][i] += d[i];
+                }
+            }
+#pragma unroll
+        for (int blk = 0; blk < 2; ++blk) {
+            R c[36];
+            load_clover_block<P, R>(J.C, Vh, blk, cb, c);
+#pragma unroll
+            for (int j = 0; j < NB; ++j)
+                if (use[j]) {
+                    R t[12];
+                    herm6<R>(c, &acc[j][blk * 12], t);
+#pragma unroll
+                    for (int i = 0; i < 12; ++i) acc[j][blk * 12 + i] = t[i];
+                }
+        }
+#pragma unroll
+        for (int j = 0; j < NB; ++j)
+            if (use[j]) {
+                if (FL & F_ACCUM) {
+                    R o[24];
+                    load_spinor<P, R>(J.out, Vh, g0 + j, cb, o);
+#pragma unroll
+                    for (int i = 0; i < 24; ++i) acc[j][i] += o[i];
+                }
+                store_spinor<P, R>(J.out, Vh, g0 + j, cb, acc[j]);
+                if (FL & F_NORM) {
+                    double s = 0;
+#pragma unroll
+                    for (int i = 0; i < 24; ++i) s += (double)acc[j][i] * (double)acc[j][i];
+                    nrm2[j] = s;
+                }
+            }
+    } else {
+        const R ca = (R)J.ca;
+#pragma unroll
+        for (int j = 0; j < NB; ++j)
+            if (use[j]) {
+#pragma unroll
+                for (int i = 0; i < 24; ++i) acc[j][i] *= ch;
+                if (FL & F_G5OUT) {
+#pragma unroll
+                    for (int i = 12; i < 24; ++i) acc[j][i] = -acc[j][i];
+                }
+            }
+#pragma unroll
+        for (int blk = 0; blk < 2; ++blk) {
+            R c[36];
+            if (!(FL & F_NOA)) load_clover_block<P, R>(J.C, Vh, blk, cb, c);
+#pragma unroll
+            for (int j = 0; j < NB; ++j)
+                if (use[j]) {
+                    R xv[12], t[12];
+                    load_half_spinor<P, R>(J.x, Vh, g0 + j, cb, blk, xv);
+                    if (FL & F_NOA) {
+#pragma unroll
+                        for (int i = 0; i < 12; ++i) t[i] = xv[i];
+                    } else {
+                        herm6<R>(c, xv, t);
+                    }
+#pragma unroll
+                    for (int i = 0; i < 12; ++i) acc[j][blk * 12 + i] += ca * t[i];
+                }
+        }
+#pragma unroll
+        for (int j = 0; j < NB; ++j)
+            if (use[j]) {
+                if (FL & F_HASB) {
+                    R bv[24];
+                    load_spinor<P, R>(J.b, Vh, g0 + j, cb, bv);
+                    const R cbc = (R)J.cb;
+#pragma unroll
+                    for (int i = 0; i < 24; ++i) acc[j][i] += cbc * bv[i];
+                }
+                if (FL & F_CG) {
+                    const R al = (R)J.alpha[g0 + j];
+                    R rv[24], w[24];
+                    load_spinor<P, R>(J.r, Vh, g0 + j, cb, rv);
+#pragma unroll
+                    for (int i = 0; i < 24; ++i) rv[i] -= al * acc[j][i];
+                    store_spinor<P, R>(J.r, Vh, g0 + j, cb, rv);
+                    double s = 0;
+#pragma unroll
+                    for (int i = 0; i < 24; ++i) s += (double)rv[i] * (double)rv[i];
+                    nrm2[j] = s;
+                    load_spinor<P, R>(J.x, Vh, g0 + j, cb, w);
+                    load_spinor<P, R>(J.xs, Vh, g0 + j, cb, rv);
+#pragma unroll
+                    for (int i = 0; i < 24; ++i) rv[i] += al * w[i];
+                    store_spinor<P, R>(J.xs, Vh, g0 + j, cb, rv);
+                } else {
+                    store_spinor<P, R>(J.out, Vh, g0 + j, cb, acc[j]);
+                    if (FL & F_NORM) {
+                        double s = 0;
+#pragma unroll
+                        for (int i = 0; i < 24; ++i) s += (double)acc[j][i] * (double)acc[j][i];
+                        nrm2[j] = s;
+                    }
+                }
+            }
+    }
+}
+
+// ---------------------------------------------------------------- block reduction
+
+// Sum of v over the block (BS threads, wave64), result valid in thread 0.
+template <int BS> __device__ __forceinline__ double block_sum(double v, double* lds) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    constexpr int NW = BS / 64;
+    if (NW == 1) return v;
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) lds[w] = v;
+    __syncthreads();
+    double s = 0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < NW; ++i) s += lds[i];
+    __syncthreads();
+    return s;
+}
+
+template <int P, int NB, int KIND, int FL, int BS>
+__global__ void __launch_bounds__(BS) hop_kernel(const HopJob<P>* __restrict__ jobs, int njob) {
+    const int bid = blockIdx.x;
+    int jb = 0;
+    while (jb + 1 < njob && bid >= jobs[jb + 1].blk0) ++jb;
+    const HopJob<P>& J = jobs[jb];
+    const int lb = bid - J.blk0;
+    const int k = lb >> 3;
+    const int gi = k % J.G;
+    const int sb = (k / J.G) * 8 + (lb & 7);
+    if (sb >= J.nsb) return;  // whole block: padding of the XCD decomposition
+    const int cb = sb * BS + (int)threadIdx.x;
+    const int g0 = gi * NB;
+    double nrm2[NB];
+    if (cb < J.g.Vh) {
+        hop_site<P, NB, KIND, FL>(J, cb, g0, nrm2);
+    } else {
+#pragma unroll
+        for (int j = 0; j < NB; ++j) nrm2[j] = 0.0;
+    }
+    if (FL & (F_NORM | F_CG)) {
+        __shared__ double lds[BS / 64];
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            if (g0 + j >= J.nrhs) break;  // uniform over the block
+            double s = block_sum<BS>(nrm2[j], lds);
+            if (threadIdx.x == 0) J.part[(size_t)(g0 + j) * J.pstride + sb] = s;
+        }
+    }
+}
+
+}  // namespace dlma

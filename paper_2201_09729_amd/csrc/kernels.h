@@ -1,0 +1,64 @@
+// Launch descriptors and host-side launchers of the dlma kernels.
+#pragma once
+#include "hop.h"
+
+namespace dlma {
+
+// Site-local vector kernels over half-lattice fields (one thread per site and
+// right-hand side), batched over jobs like the stencil kernels.
+template <int P> struct VecJob {
+    int Vh, nrhs, nsb, blk0;  // nsb = ceil(Vh / VEC_BS); blocks of the job = nsb * nrhs
+    SF<P> a, b, c;
+    const double2* C;     // clover blocks (clover apply)
+    const double* s;      // per right-hand side scalar
+    const int* active;    // per right-hand side flag or nullptr
+    double* part;         // partial squared norms, row stride pstride
+    int pstride;
+};
+constexpr int VEC_BS = 256;
+
+// Per right-hand side finishing of two-stage reductions (one block per rhs, fixed order).
+struct FinJob {
+    int nrhs, rhs0, npart;     // rhs0: first global block of this job
+    const double* part;        // [nrhs][npart]
+    double* rr;                // CG: current |r|^2
+    double* rr0;               // CG: |r|^2 at start
+    double* alpha;
+    double* beta;
+    double* tol2;              // CG: stop when |r|^2 <= tol2 (set by FIN_INIT)
+    const double* abs2;        // FIN_INIT: absolute target of |r|^2
+    double rel2;               // FIN_INIT: relative target, tol2 = max(rel2 * |r0|^2, abs2)
+    int* active;
+    int* iters;
+    int maxit;
+    double* out;               // FIN_NORM: sums
+};
+enum FinMode { FIN_NORM = 0, FIN_ALPHA = 1, FIN_BETA = 2, FIN_INIT = 3 };
+
+struct HopCfg { int kind, flags, nb; };
+constexpr int HOP_BS = 128;
+
+template <int P> hipError_t launch_hop(const HopCfg& c, const HopJob<P>* djobs, int njob, int nblocks, hipStream_t s);
+
+// gauge and clover
+hipError_t launch_pack_links(const double2* Ucan, double2* U64, const Geo& g, hipStream_t s);
+hipError_t launch_unitarity(const double2* Ucan, long nlink, double* blockmax, int nblk, hipStream_t s);
+hipError_t launch_clover_build(const double2* Ucan, const Geo& g, double m0, double csw, double2* C0, double2* C1, hipStream_t s);
+hipError_t launch_clover_invert(const double2* C, double2* Ci, int Vh, int* err, hipStream_t s);
+hipError_t launch_add_diag(double2* C, int Vh, double delta, hipStream_t s);
+template <int P> hipError_t launch_convert_pairs(const double2* src, void* dst, long n, hipStream_t s);
+
+// full FP64 fields <-> canonical
+hipError_t launch_canon_to_eo(const double2* can, double2* eo, const Geo& g, int nrhs, hipStream_t s);
+hipError_t launch_eo_to_canon(const double2* eo, double2* can, const Geo& g, int nrhs, hipStream_t s);
+
+// vector kernels (jobs in device memory, total blocks given)
+hipError_t launch_clover_apply64(const VecJob<P64>* j, int njob, int nblocks, hipStream_t s);  // c = C a
+template <int P> hipError_t launch_conv_from64(const VecJob<P>* j, int njob, int nblocks, const VecJob<P64>* j64, hipStream_t s);
+template <int P> hipError_t launch_accum_to64(const VecJob<P>* j, const VecJob<P64>* j64, int njob, int nblocks, hipStream_t s);
+template <int P> hipError_t launch_xpay(const VecJob<P>* j, int njob, int nblocks, hipStream_t s);       // b = a + s*b
+template <int P> hipError_t launch_norm(const VecJob<P>* j, int njob, int nblocks, hipStream_t s);       // part = |a|^2
+template <int P> hipError_t launch_fill_random(SF<P> f, int Vh, int nrhs, unsigned seed, hipStream_t s);
+hipError_t launch_finish(const FinJob* j, int njob, int nblocks, int mode, hipStream_t s);
+
+}  // namespace dlma

@@ -1,0 +1,283 @@
+"""Python binding of libdlma.so (argument marshalling only).
+
+Every function has the name of the C entry point it calls (include/dlma.h) and
+takes torch tensors that live on the GPU; device pointers and torch's current
+HIP stream are passed through ctypes.  All computation happens in the library's
+HIP kernels.  There is no fallback: if the library is missing or fails to load,
+every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdlma.so")
+
+DLMA_OK = 0
+DLMA_EINVAL = -1
+DLMA_ENOMEM = -2
+DLMA_EHIP = -3
+DLMA_ENOTCONV = -4
+DLMA_ENAN = -5
+DLMA_EUNSUPPORTED = -6
+
+PREC = {"fp64": 0, "mix_fp32": 1, "mix_fp16": 2, "mix_bf16": 3}
+NPARTS = 7
+PART_NAMES = ("QQ_est", "PQ_est", "QP_est", "PP_est", "11_est", "PP_exact", "QP_exact")
+GAMMA_NAMES = ("PS", "V")
+
+
+class DlmaError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("dlma error %d: %s" % (code, msg))
+        self.code = code
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("maxiter", ctypes.c_int), ("max_outer", ctypes.c_int),
+                ("prec", ctypes.c_int), ("inner_tol", ctypes.c_double), ("rhs_block", ctypes.c_int),
+                ("use_x0", ctypes.c_int), ("graph_iters", ctypes.c_int), ("check_every", ctypes.c_int)]
+
+
+class SolveStat(ctypes.Structure):
+    _fields_ = [("outer", ctypes.c_int), ("inner_iters", ctypes.c_int), ("relres", ctypes.c_double),
+                ("converged", ctypes.c_int)]
+
+
+class RhsSet(ctypes.Structure):
+    _fields_ = [("b", ctypes.c_void_p), ("x", ctypes.c_void_p), ("nrhs", ctypes.c_int)]
+
+
+class EigOpts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("max_basis", ctypes.c_int), ("check_every", ctypes.c_int)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libdlma.so once; raises if it is missing (build it with __graft_entry__.build())."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError("libdlma.so not built (%s); run __graft_entry__.build()" % path)
+    lib = ctypes.CDLL(path)
+    P, I, D = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    sig = {
+        "dlma_version": ([], ctypes.c_char_p),
+        "dlma_last_error": ([], ctypes.c_char_p),
+        "dlma_load_gauge": ([P, P, D, D, P, P], I),
+        "dlma_set_mass": ([P, D, P], I),
+        "dlma_free_gauge": ([P], I),
+        "dlma_gauge_info": ([P, P, P, P], I),
+        "dlma_apply_dw": ([P, P, P, I, I, P], I),
+        "dlma_solve_opts_default": ([P], None),
+        "dlma_solve": ([P, I, P, P, P, P], I),
+        "dlma_lap_eigs": ([P, I, I, I, P, P, P, P, P], I),
+        "dlma_project": ([P, I, I, P, P, P, I, I, P], I),
+        "dlma_correlators": ([P, I, I, P, P, I, P, P, P, P], I),
+        "dlma_profile_enable": ([I], I),
+        "dlma_profile_reset": ([], I),
+        "dlma_profile_read": ([I, P, P, P], I),
+        "dlma_bench_schur": ([P, I, I, I, I, P, P, P], I),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = lib
+    return lib
+
+
+def _check(rc, allow=()):
+    if rc != DLMA_OK and rc not in allow:
+        msg = load_library().dlma_last_error()
+        raise DlmaError(rc, msg.decode() if msg else "")
+    return rc
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t: torch.Tensor, dtype=torch.complex128) -> torch.Tensor:
+    if not t.is_cuda:
+        raise ValueError("tensor must be on the GPU")
+    if t.dtype != dtype:
+        raise ValueError("tensor must be %s" % dtype)
+    return t.contiguous()
+
+
+def dlma_version() -> str:
+    return load_library().dlma_version().decode()
+
+
+class Gauge:
+    """Owns a dlma_gauge_t handle (freed with dlma_free_gauge)."""
+
+    def __init__(self, handle, dims, kappa, csw):
+        self.h = ctypes.c_void_p(handle)
+        self.dims = tuple(dims)
+        self.kappa = kappa
+        self.csw = csw
+
+    def close(self):
+        if self.h is not None and self.h.value:
+            load_library().dlma_free_gauge(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def dlma_load_gauge(U: torch.Tensor, kappa: float, csw: float) -> Gauge:
+    """U: complex128 [T][Z][Y][X][4][3][3] on the GPU."""
+    U = _dev(U)
+    if U.dim() != 7 or tuple(U.shape[4:]) != (4, 3, 3):
+        raise ValueError("gauge must have shape [T,Z,Y,X,4,3,3]")
+    dims = (ctypes.c_int * 4)(*[int(d) for d in U.shape[:4]])
+    h = ctypes.c_void_p()
+    _check(load_library().dlma_load_gauge(dims, ctypes.c_void_p(U.data_ptr()), float(kappa), float(csw),
+                                          _stream(), ctypes.byref(h)))
+    return Gauge(h.value, U.shape[:4], kappa, csw)
+
+
+def dlma_set_mass(g: Gauge, kappa: float) -> None:
+    _check(load_library().dlma_set_mass(g.h, float(kappa), _stream()))
+    g.kappa = kappa
+
+
+def dlma_apply_dw(g: Gauge, x: torch.Tensor, dagger: bool = False) -> torch.Tensor:
+    """D x or D^dag x for x of shape [n][T][Z][Y][X][4][3] (complex128, GPU)."""
+    x = _dev(x)
+    out = torch.empty_like(x)
+    n = x.shape[0]
+    _check(load_library().dlma_apply_dw(g.h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                        int(n), int(bool(dagger)), _stream()))
+    return out
+
+
+def default_opts(**kw) -> SolveOpts:
+    o = SolveOpts()
+    load_library().dlma_solve_opts_default(ctypes.byref(o))
+    for k, v in kw.items():
+        if k == "prec" and isinstance(v, str):
+            v = PREC[v]
+        setattr(o, k, v)
+    return o
+
+
+def dlma_solve(gauges, bs, xs=None, opts: SolveOpts | None = None, allow_notconv: bool = False):
+    """Solve D x = b for lists of gauges and source tensors [n][T][Z][Y][X][4][3].
+
+    Returns (list of solution tensors, list of per-RHS stat dicts)."""
+    if isinstance(gauges, Gauge):
+        gauges, bs = [gauges], [bs]
+        if xs is not None:
+            xs = [xs]
+    opts = opts or default_opts()
+    bs = [_dev(b) for b in bs]
+    if xs is None:
+        xs = [torch.zeros_like(b) for b in bs]
+    else:
+        xs = [_dev(x) for x in xs]
+    ng = len(gauges)
+    garr = (ctypes.c_void_p * ng)(*[g.h.value for g in gauges])
+    sets = (RhsSet * ng)()
+    total = 0
+    for i in range(ng):
+        sets[i].b = bs[i].data_ptr()
+        sets[i].x = xs[i].data_ptr()
+        sets[i].nrhs = int(bs[i].shape[0])
+        total += int(bs[i].shape[0])
+    stats = (SolveStat * max(1, total))()
+    rc = load_library().dlma_solve(garr, ng, sets, ctypes.byref(opts), stats, _stream())
+    _check(rc, allow=(DLMA_ENOTCONV,) if allow_notconv else ())
+    st = [dict(outer=s.outer, inner_iters=s.inner_iters, relres=s.relres, converged=bool(s.converged))
+          for s in stats[:total]]
+    return xs, st
+
+
+def dlma_lap_eigs(g: Gauge, nev: int, t0: int, nt: int, v0: torch.Tensor, tol: float = 1e-10,
+                  max_basis: int = 0, check_every: int = 0):
+    """Lowest nev modes of -lap(t), t = t0..t0+nt-1; v0: [nt][Z][Y][X][3] start vectors.
+
+    Returns (V [nt][nev][Z][Y][X][3] complex128 on the GPU, evals numpy [nt][nev])."""
+    import numpy as np
+    v0 = _dev(v0)
+    T, Z, Y, X = g.dims
+    V = torch.empty((nt, nev, Z, Y, X, 3), dtype=torch.complex128, device=v0.device)
+    ev = np.zeros((nt, nev), dtype=np.float64)
+    o = EigOpts(tol, max_basis, check_every)
+    _check(load_library().dlma_lap_eigs(g.h, int(nev), int(t0), int(nt), ctypes.c_void_p(v0.data_ptr()),
+                                        ctypes.c_void_p(V.data_ptr()), ev.ctypes.data_as(ctypes.c_void_p),
+                                        ctypes.byref(o), _stream()))
+    return V, ev
+
+
+def dlma_project(g: Gauge, t: int, Vt: torch.Tensor, x: torch.Tensor, mode: int, out: torch.Tensor | None = None):
+    """mode 0: box(t) x; mode 1: (1 - box(t)) x; zero off timeslice t."""
+    Vt = _dev(Vt)
+    x = _dev(x)
+    out = torch.empty_like(x) if out is None else out
+    _check(load_library().dlma_project(g.h, int(t), int(Vt.shape[0]), ctypes.c_void_p(Vt.data_ptr()),
+                                       ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                       int(x.shape[0]), int(mode), _stream()))
+    return out
+
+
+def dlma_correlators(g: Gauge, t_src: int, Vall: torch.Tensor, phi_dist: torch.Tensor,
+                     phi: torch.Tensor | None = None, phibar: torch.Tensor | None = None):
+    """Returns {gamma: {part: complex numpy [T]}} (see dlma.h for the parts)."""
+    import numpy as np
+    Vall = _dev(Vall)
+    phi_dist = _dev(phi_dist)
+    nev = int(Vall.shape[1])
+    T = g.dims[0]
+    nn = 0
+    pp = pb = ctypes.c_void_p(0)
+    if phi is not None:
+        phi = _dev(phi)
+        phibar = _dev(phibar)
+        nn = int(phi.shape[0]) // 4
+        pp = ctypes.c_void_p(phi.data_ptr())
+        pb = ctypes.c_void_p(phibar.data_ptr())
+    C = np.zeros((2, NPARTS, T, 2), dtype=np.float64)
+    _check(load_library().dlma_correlators(g.h, int(t_src), nev, ctypes.c_void_p(Vall.data_ptr()),
+                                           ctypes.c_void_p(phi_dist.data_ptr()), nn, pp, pb,
+                                           C.ctypes.data_as(ctypes.c_void_p), _stream()))
+    Cc = C[..., 0] + 1j * C[..., 1]
+    return {GAMMA_NAMES[gi]: {PART_NAMES[p]: Cc[gi, p] for p in range(NPARTS)} for gi in range(2)}
+
+
+def dlma_profile_enable(on: bool = True):
+    _check(load_library().dlma_profile_enable(int(bool(on))))
+
+
+def dlma_profile_reset():
+    _check(load_library().dlma_profile_reset())
+
+
+def dlma_profile_read(kclass: int):
+    n = ctypes.c_longlong()
+    ms = ctypes.c_double()
+    by = ctypes.c_double()
+    _check(load_library().dlma_profile_read(int(kclass), ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by)))
+    return n.value, ms.value, by.value
+
+
+def dlma_bench_schur(g: Gauge, prec, nrhs: int, rhs_block: int = 0, napply: int = 20):
+    if isinstance(prec, str):
+        prec = PREC[prec]
+    ms = ctypes.c_double()
+    by = ctypes.c_double()
+    _check(load_library().dlma_bench_schur(g.h, int(prec), int(nrhs), int(rhs_block), int(napply),
+                                           ctypes.byref(ms), ctypes.byref(by), _stream()))
+    return ms.value, by.value

@@ -1,0 +1,160 @@
+"""GPU parity of the HIP path (through the C ABI) against the FP64 CPU oracle:
+the full Wilson-clover operator and the batched solver in every precision."""
+import numpy as np
+import pytest
+
+from paper_2201_09729_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+@pytest.fixture(scope="module")
+def D():
+    _need_gpu()
+    from paper_2201_09729_amd import dlma
+    dlma.load_library()
+    return dlma
+
+
+def cu(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+# (dims, eps, seed, kappa, csw): the 4^4 and 8^3x16 workloads plus a non-cubic ragged shape
+CASES = [((4, 4, 4, 4), 0.3, 1, 0.120, 1.0),
+         ((16, 8, 8, 8), 0.3, 2, 0.120, 1.0),
+         ((6, 4, 2, 8), 0.25, 7, 0.121, 1.2)]
+
+
+@pytest.mark.parametrize("dims,eps,seed,kappa,csw", CASES)
+@pytest.mark.parametrize("dagger", [False, True])
+def test_apply_dw_matches_oracle(D, orc, dims, eps, seed, kappa, csw, dagger):
+    print("apply_dw", dims, dagger, flush=True)
+    U = synth.gauge_field(dims, eps, seed)
+    x = synth.random_spinor(dims, 3, seed + 10)
+    g = D.dlma_load_gauge(cu(U), kappa, csw)
+    y = D.dlma_apply_dw(g, cu(x), dagger=dagger).cpu().numpy()
+    ref = orc.dirac(U, orc.clover(U, kappa, csw), x, dagger=dagger)
+    err = np.linalg.norm(y - ref) / np.linalg.norm(ref)
+    assert err < 1e-13, err
+
+
+def test_set_mass_matches_oracle(D, orc):
+    dims = (4, 4, 4, 4)
+    U = synth.gauge_field(dims, 0.3, 1)
+    x = synth.random_spinor(dims, 1, 3)
+    g = D.dlma_load_gauge(cu(U), 0.120, 1.0)
+    D.dlma_set_mass(g, 0.1215)
+    y = D.dlma_apply_dw(g, cu(x)).cpu().numpy()
+    ref = orc.dirac(U, orc.clover(U, 0.1215, 1.0), x)
+    assert np.linalg.norm(y - ref) / np.linalg.norm(ref) < 1e-13
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mix_fp32", "mix_fp16", "mix_bf16"])
+@pytest.mark.parametrize("rhs_block", [1, 2, 4])
+def test_solve_true_residual(D, orc, prec, rhs_block):
+    """8^3x16, kappa 0.120, csw 1.0: five right-hand sides (ragged for blocks of 2 and 4);
+    the oracle re-evaluates |b - D x_gpu| / |b| <= 1e-10 for every precision."""
+    dims = (16, 8, 8, 8)
+    print("solve", prec, rhs_block, flush=True)
+    U = synth.gauge_field(dims, 0.3, 2)
+    b = synth.random_spinor(dims, 5, 21)
+    g = D.dlma_load_gauge(cu(U), 0.120, 1.0)
+    opts = D.default_opts(tol=1e-10, prec=prec, rhs_block=rhs_block, maxiter=4000)
+    xs, st = D.dlma_solve([g], [cu(b)], opts=opts)
+    x = xs[0].cpu().numpy()
+    A = orc.clover(U, 0.120, 1.0)
+    res = orc.true_residual(U, A, x, b)
+    assert np.all(res <= 1e-10), res
+    assert all(s["converged"] for s in st)
+    assert all(abs(s["relres"] - r) <= 1e-11 for s, r in zip(st, res))
+
+
+def test_solve_matches_oracle_solution(D, orc):
+    """4^4 point source at residual 1e-12: GPU and oracle solutions agree to cond(D) * tolerance."""
+    dims = (4, 4, 4, 4)
+    U = synth.gauge_field(dims, 0.3, 1)
+    b = synth.point_source(dims, (0, 0, 0, 0), 0, 0)
+    g = D.dlma_load_gauge(cu(U), 0.120, 1.0)
+    xs, st = D.dlma_solve([g], [cu(b)], opts=D.default_opts(tol=1e-12, prec="fp64"))
+    A = orc.clover(U, 0.120, 1.0)
+    xo, its, res, conv = orc.solve(U, A, b, tol=1e-12)
+    x = xs[0].cpu().numpy()
+    assert orc.true_residual(U, A, x, b)[0] <= 1e-12
+    assert np.linalg.norm(x - xo) / np.linalg.norm(xo) < 50 * 2e-12
+
+
+def test_solve_multi_config_uneven(D, orc):
+    """Two configurations of different volume and kappa in one batched solve."""
+    cfgs = [((8, 4, 4, 4), 0.25, 1, 0.119, 1.2, 3), ((4, 6, 4, 8), 0.25, 4, 0.121, 1.2, 2)]
+    gs, bs, Us = [], [], []
+    for dims, eps, seed, kappa, csw, n in cfgs:
+        U = synth.gauge_field(dims, eps, seed)
+        Us.append(U)
+        gs.append(D.dlma_load_gauge(cu(U), kappa, csw))
+        bs.append(synth.random_spinor(dims, n, seed + 100))
+    xs, st = D.dlma_solve(gs, [cu(b) for b in bs], opts=D.default_opts(tol=1e-10, prec="mix_fp16", maxiter=4000))
+    assert len(st) == 5
+    for (dims, eps, seed, kappa, csw, n), U, b, x in zip(cfgs, Us, bs, xs):
+        res = orc.true_residual(U, orc.clover(U, kappa, csw), x.cpu().numpy(), b)
+        assert np.all(res <= 1e-10), res
+
+
+def test_solve_edge_cases(D, orc):
+    dims = (4, 4, 4, 4)
+    U = synth.gauge_field(dims, 0.3, 1)
+    g = D.dlma_load_gauge(cu(U), 0.120, 1.0)
+    # zero source -> zero solution, zero residual
+    b = np.zeros((2,) + dims + (4, 3), complex)
+    b[1] = synth.random_spinor(dims, 1, 3)[0]
+    xs, st = D.dlma_solve([g], [cu(b)], opts=D.default_opts(tol=1e-10, prec="mix_bf16"))
+    x = xs[0].cpu().numpy()
+    assert np.all(x[0] == 0) and st[0]["converged"]
+    A = orc.clover(U, 0.120, 1.0)
+    assert orc.true_residual(U, A, x[1:], b[1:])[0] <= 1e-10
+    # start vector: solving again from the solution converges at once
+    xs2, st2 = D.dlma_solve([g], [cu(b)], xs=[xs[0].clone()], opts=D.default_opts(tol=1e-10, use_x0=1))
+    assert st2[1]["inner_iters"] == 0 and st2[1]["converged"]
+    # empty set is a no-op
+    e = torch.zeros((0,) + dims + (4, 3), dtype=torch.complex128, device="cuda")
+    xs3, st3 = D.dlma_solve([g], [e])
+    assert st3 == []
+
+
+def test_solve_reports_notconv(D):
+    dims = (4, 4, 4, 4)
+    U = synth.gauge_field(dims, 0.3, 1)
+    g = D.dlma_load_gauge(cu(U), 0.120, 1.0)
+    b = cu(synth.random_spinor(dims, 1, 3))
+    with pytest.raises(D.DlmaError) as e:
+        D.dlma_solve([g], [b], opts=D.default_opts(tol=1e-10, maxiter=3, max_outer=1))
+    assert e.value.code == D.DLMA_ENOTCONV
+    xs, st = D.dlma_solve([g], [b], opts=D.default_opts(tol=1e-10, maxiter=3, max_outer=1), allow_notconv=True)
+    assert not st[0]["converged"] and st[0]["relres"] > 1e-10
+
+
+def test_load_gauge_rejects_bad_links(D):
+    dims = (4, 4, 4, 4)
+    U = synth.gauge_field(dims, 0.3, 1)
+    U[1, 2, 3, 0, 2, 0, 0] *= 1.01
+    with pytest.raises(D.DlmaError) as e:
+        D.dlma_load_gauge(cu(U), 0.120, 1.0)
+    assert e.value.code == D.DLMA_EINVAL
+    U[1, 2, 3, 0, 2, 0, 0] = np.nan
+    with pytest.raises(D.DlmaError):
+        D.dlma_load_gauge(cu(U), 0.120, 1.0)
+
+
+def test_schur_bench_runs(D):
+    dims = (8, 8, 8, 8)
+    g = D.dlma_load_gauge(cu(synth.gauge_field(dims, 0.25, 3)), 0.121, 1.2)
+    for prec in ("fp64", "mix_fp32", "mix_fp16", "mix_bf16"):
+        ms, by = D.dlma_bench_schur(g, prec, 4, 0, 4)
+        assert ms > 0 and by > 0
