@@ -1,15 +1,402 @@
-// C ABI: Laplacian eigensolver, distillation projector and correlators.
+// C ABI: Laplacian eigenmodes per timeslice (dlma_lap_eigs), the distillation
+// projector (dlma_project) and the correlator pieces (dlma_correlators).
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <numeric>
+
 #include "../../include/dlma.h"
+#include "laplace.h"
 #include "runtime.h"
 
 using namespace dlma;
+using cplx = std::complex<double>;
 
-extern "C" int dlma_lap_eigs(dlma_gauge_t, int, int, int, const void*, void*, double*, const dlma_eig_opts*, void*) {
-    return fail(DLMA_EUNSUPPORTED, "dlma_lap_eigs: not built yet");
+static inline hipStream_t S(void* s) { return (hipStream_t)s; }
+
+namespace {
+
+// Eigenvalues (and optionally eigenvectors or their last row) of the real symmetric
+// tridiagonal matrix with diagonal d and off-diagonal e, by the implicit QL
+// algorithm: repeated QL sweeps with a shift from the trailing 2x2 block, applied
+// as a chase of plane rotations from the bottom of the unreduced block upwards,
+// with deflation when an off-diagonal element becomes negligible.
+//   Z (m x m, row-major) receives the eigenvector matrix (columns), last its last row.
+bool tridiag_ql(std::vector<double>& d, std::vector<double> e, std::vector<double>* Z, std::vector<double>* last) {
+    const int n = (int)d.size();
+    e.resize(n, 0.0);
+    e[n - 1] = 0.0;
+    if (Z) {
+        Z->assign((size_t)n * n, 0.0);
+        for (int i = 0; i < n; ++i) (*Z)[(size_t)i * n + i] = 1.0;
+    }
+    if (last) {
+        last->assign(n, 0.0);
+        (*last)[n - 1] = 1.0;
+    }
+    const double eps = 2.220446049250313e-16;
+    for (int l = 0; l < n; ++l) {
+        for (int iter = 0;; ++iter) {
+            int m = l;
+            for (; m < n - 1; ++m) {
+                double dd = std::fabs(d[m]) + std::fabs(d[m + 1]);
+                if (std::fabs(e[m]) <= eps * dd) break;
+            }
+            if (m == l) break;
+            if (iter >= 100) return false;
+            double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
+            double r = std::hypot(g, 1.0);
+            g = d[m] - d[l] + e[l] / (g + std::copysign(r, g));
+            double s = 1.0, c = 1.0, p = 0.0;
+            int i = m - 1;
+            bool early = false;
+            for (; i >= l; --i) {
+                double f = s * e[i], b = c * e[i];
+                r = std::hypot(f, g);
+                e[i + 1] = r;
+                if (r == 0.0) {
+                    d[i + 1] -= p;
+                    e[m] = 0.0;
+                    early = true;
+                    break;
+                }
+                s = f / r;
+                c = g / r;
+                g = d[i + 1] - p;
+                r = (d[i] - g) * s + 2.0 * c * b;
+                p = s * r;
+                d[i + 1] = g + p;
+                g = c * r - b;
+                if (Z) {
+                    for (int k = 0; k < n; ++k) {
+                        double* row = Z->data() + (size_t)k * n;
+                        double zf = row[i + 1];
+                        row[i + 1] = s * row[i] + c * zf;
+                        row[i] = c * row[i] - s * zf;
+                    }
+                }
+                if (last) {
+                    double zf = (*last)[i + 1];
+                    (*last)[i + 1] = s * (*last)[i] + c * zf;
+                    (*last)[i] = c * (*last)[i] - s * zf;
+                }
+            }
+            if (early) continue;
+            d[l] -= p;
+            e[l] = g;
+            e[m] = 0.0;
+        }
+    }
+    return true;
 }
-extern "C" int dlma_project(dlma_gauge_t, int, int, const void*, const void*, void*, int, int, void*) {
-    return fail(DLMA_EUNSUPPORTED, "dlma_project: not built yet");
+
+std::vector<int> argsort(const std::vector<double>& v) {
+    std::vector<int> idx(v.size());
+    std::iota(idx.begin(), idx.end(), 0);
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return v[a] < v[b]; });
+    return idx;
 }
-extern "C" int dlma_correlators(dlma_gauge_t, int, int, const void*, const void*, int, const void*, const void*, double*, void*) {
-    return fail(DLMA_EUNSUPPORTED, "dlma_correlators: not built yet");
+
+}  // namespace
+
+extern "C" int dlma_lap_eigs(dlma_gauge_t h, int nev, int t0, int nt, const void* v0, void* V_out, double* evals,
+                             const dlma_eig_opts* opts, void* stream) {
+    Gauge* g = (Gauge*)h;
+    if (!g) return fail(DLMA_EINVAL, "NULL handle");
+    if (!v0 || !V_out || !evals) return fail(DLMA_EINVAL, "NULL pointer");
+    const int T = g->dims[0];
+    const long L3 = (long)g->dims[1] * g->dims[2] * g->dims[3];
+    const long n = 3 * L3;
+    if (nt < 1 || t0 < 0 || t0 + nt > T) return fail(DLMA_EINVAL, "timeslices t0..t0+nt-1 must lie in [0, T)");
+    if (nev < 1 || nev > n) return fail(DLMA_EINVAL, "nev must be in [1, 3 L^3]");
+    double tol = (opts && opts->tol > 0) ? opts->tol : 1e-10;
+    int maxm = (opts && opts->max_basis > 0) ? opts->max_basis : (int)std::min<long>(n, 20L * nev + 200);
+    maxm = (int)std::min<long>(maxm, n);
+    if (maxm < nev) return fail(DLMA_EINVAL, "max_basis must be >= nev");
+    int check = (opts && opts->check_every > 0) ? opts->check_every : 10;
+    hipStream_t s = S(stream);
+    const long isq = n, tsq = (long)(maxm + 1) * n;
+    Buf Q, W, Hc, AB;
+    DLMA_TRY(Q.allocate(sizeof(double2) * tsq * nt));
+    DLMA_TRY(W.allocate(sizeof(double2) * n * nt));
+    DLMA_TRY(Hc.allocate(sizeof(double2) * (size_t)(maxm + 1) * nt));
+    DLMA_TRY(AB.allocate(sizeof(double) * 2 * (size_t)maxm * nt + 64));
+    double2* q = Q.as<double2>();
+    double2* w = W.as<double2>();
+    double* alpha = AB.as<double>();
+    double* beta = alpha + (size_t)maxm * nt;
+    // q_0 = v0 / |v0|  (norm stored in the beta slot of step 0, overwritten later)
+    DLMA_HIP(launch_normalize_into((const double2*)v0, n, q, tsq, n, beta, maxm, 0, nt, s));
+    std::vector<double> ha((size_t)maxm * nt), hb((size_t)maxm * nt);
+    {
+        std::vector<double> b0((size_t)maxm * nt);
+        DLMA_HIP(hipMemcpyAsync(b0.data(), beta, sizeof(double) * maxm * nt, hipMemcpyDeviceToHost, s));
+        DLMA_HIP(hipStreamSynchronize(s));
+        for (int t = 0; t < nt; ++t)
+            if (!(b0[(size_t)t * maxm] > 0) || !std::isfinite(b0[(size_t)t * maxm]))
+                return fail(DLMA_EINVAL, "start vector is zero or not finite");
+    }
+    int m = 0;
+    bool converged = false;
+    for (int j = 0; j < maxm; ++j) {
+        double2* qj = q + (long)j * isq;
+        DLMA_HIP(launch_neg_lap(g->U64.as<double2>(), g->geo, t0, qj, w, tsq, n, nt, s));
+        DLMA_HIP(launch_lanczos_three(q, tsq, isq, w, n, n, alpha, beta, maxm, j, nt, s));
+        for (int pass = 0; pass < 2; ++pass) {  // classical Gram-Schmidt, twice
+            DLMA_HIP(launch_dots(q, tsq, isq, w, n, n, Hc.as<double2>(), maxm + 1, j + 1, nt, s));
+            DLMA_HIP(launch_sub_combo(q, tsq, isq, Hc.as<double2>(), maxm + 1, j + 1, w, n, n, nt, s));
+        }
+        DLMA_HIP(launch_normalize_into(w, n, q + (long)(j + 1) * isq, tsq, n, beta, maxm, j, nt, s));
+        m = j + 1;
+        bool last_step = (m == maxm);
+        if (m >= nev && (m % check == 0 || last_step)) {
+            DLMA_HIP(hipMemcpyAsync(ha.data(), alpha, sizeof(double) * maxm * nt, hipMemcpyDeviceToHost, s));
+            DLMA_HIP(hipMemcpyAsync(hb.data(), beta, sizeof(double) * maxm * nt, hipMemcpyDeviceToHost, s));
+            DLMA_HIP(hipStreamSynchronize(s));
+            bool all = true, exhausted = false;
+            for (int t = 0; t < nt && all; ++t) {
+                std::vector<double> d(ha.begin() + (size_t)t * maxm, ha.begin() + (size_t)t * maxm + m);
+                std::vector<double> e(hb.begin() + (size_t)t * maxm, hb.begin() + (size_t)t * maxm + m - 1);
+                double bm = hb[(size_t)t * maxm + m - 1];
+                if (bm < 1e-12) exhausted = true;  // invariant subspace: Ritz values exact
+                std::vector<double> last;
+                if (!tridiag_ql(d, e, nullptr, &last)) return fail(DLMA_EHIP, "tridiagonal eigensolver did not converge");
+                std::vector<int> idx = argsort(d);
+                for (int k = 0; k < nev; ++k)
+                    if (std::fabs(bm * last[idx[k]]) > tol * 12.0 && !(bm < 1e-12)) { all = false; break; }
+            }
+            if (all || exhausted) { converged = true; break; }
+        }
+    }
+    // final Ritz pairs from the m-step tridiagonal matrices
+    if (m < nev) return fail(DLMA_ENOTCONV, "Krylov space smaller than nev");
+    DLMA_HIP(hipMemcpyAsync(ha.data(), alpha, sizeof(double) * maxm * nt, hipMemcpyDeviceToHost, s));
+    DLMA_HIP(hipMemcpyAsync(hb.data(), beta, sizeof(double) * maxm * nt, hipMemcpyDeviceToHost, s));
+    DLMA_HIP(hipStreamSynchronize(s));
+    std::vector<double> Sall((size_t)nt * m * nev);
+    for (int t = 0; t < nt; ++t) {
+        std::vector<double> d(ha.begin() + (size_t)t * maxm, ha.begin() + (size_t)t * maxm + m);
+        std::vector<double> e(hb.begin() + (size_t)t * maxm, hb.begin() + (size_t)t * maxm + m - 1);
+        std::vector<double> Z;
+        if (!tridiag_ql(d, e, &Z, nullptr)) return fail(DLMA_EHIP, "tridiagonal eigensolver did not converge");
+        std::vector<int> idx = argsort(d);
+        for (int k = 0; k < nev; ++k) {
+            evals[(size_t)t * nev + k] = -d[idx[k]];
+            for (int i = 0; i < m; ++i) Sall[((size_t)t * m + i) * nev + k] = Z[(size_t)i * m + idx[k]];
+        }
+    }
+    Buf Sd;
+    DLMA_TRY(Sd.allocate(sizeof(double) * Sall.size()));
+    DLMA_HIP(hipMemcpyAsync(Sd.p, Sall.data(), sizeof(double) * Sall.size(), hipMemcpyHostToDevice, s));
+    DLMA_HIP(launch_ritz(q, tsq, isq, Sd.as<double>(), m, nev, (double2*)V_out, (long)nev * n, n, nt, s));
+    DLMA_HIP(launch_phase_fix((double2*)V_out, n, nev * nt, s));
+    DLMA_HIP(hipStreamSynchronize(s));
+    if (!converged) return fail(DLMA_ENOTCONV, "Lanczos did not reach the tolerance within max_basis steps");
+    return DLMA_OK;
+}
+
+extern "C" int dlma_project(dlma_gauge_t h, int t, int nev, const void* V_t, const void* in, void* out, int nrhs, int mode,
+                            void* stream) {
+    Gauge* g = (Gauge*)h;
+    if (!g) return fail(DLMA_EINVAL, "NULL handle");
+    if (t < 0 || t >= g->dims[0]) return fail(DLMA_EINVAL, "timeslice out of range");
+    if (mode != 0 && mode != 1) return fail(DLMA_EINVAL, "mode must be 0 or 1");
+    if (nrhs < 0 || nev < 0) return fail(DLMA_EINVAL, "negative count");
+    if (nrhs == 0) return DLMA_OK;
+    if (!in || !out || (nev > 0 && !V_t)) return fail(DLMA_EINVAL, "NULL pointer");
+    hipStream_t s = S(stream);
+    Buf coef;
+    DLMA_TRY(coef.allocate(sizeof(double2) * std::max(1, nev) * 4 * (size_t)std::min(nrhs, 65535)));
+    DLMA_HIP(launch_project((const double2*)V_t, (const double2*)in, (double2*)out, g->geo, t, nev, nrhs, mode, coef.as<double2>(), s));
+    DLMA_HIP(hipStreamSynchronize(s));
+    return DLMA_OK;
+}
+
+// ---------------------------------------------------------------- correlators
+
+namespace {
+
+struct Gam {
+    cplx m[4][4];
+};
+
+Gam gmul(const Gam& a, const Gam& b) {
+    Gam c;
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) {
+            cplx s = 0;
+            for (int k = 0; k < 4; ++k) s += a.m[i][k] * b.m[k][j];
+            c.m[i][j] = s;
+        }
+    return c;
+}
+
+// chiral basis: g0 = [[0,-1],[-1,0]], gk = [[0,-i sk],[i sk,0]], g5 = diag(1,1,-1,-1)
+std::vector<Gam> gammas() {
+    std::vector<Gam> g(5);
+    for (auto& x : g)
+        for (int i = 0; i < 4; ++i)
+            for (int j = 0; j < 4; ++j) x.m[i][j] = 0;
+    const cplx I(0, 1);
+    cplx sig[3][2][2] = {{{0, 1}, {1, 0}}, {{0, -I}, {I, 0}}, {{1, 0}, {0, -1}}};
+    for (int i = 0; i < 2; ++i) {
+        g[0].m[i][i + 2] = -1;
+        g[0].m[i + 2][i] = -1;
+    }
+    for (int k = 0; k < 3; ++k)
+        for (int i = 0; i < 2; ++i)
+            for (int j = 0; j < 2; ++j) {
+                g[k + 1].m[i][j + 2] = -I * sig[k][i][j];
+                g[k + 1].m[i + 2][j] = I * sig[k][i][j];
+            }
+    g[4].m[0][0] = g[4].m[1][1] = 1;
+    g[4].m[2][2] = g[4].m[3][3] = -1;
+    return g;
+}
+
+}  // namespace
+
+extern "C" int dlma_correlators(dlma_gauge_t h, int t_src, int nev, const void* V_all, const void* phi_dist, int nnoise,
+                                const void* phi, const void* phibar, double* C_out, void* stream) {
+    Gauge* g = (Gauge*)h;
+    if (!g) return fail(DLMA_EINVAL, "NULL handle");
+    const int T = g->dims[0];
+    if (t_src < 0 || t_src >= T) return fail(DLMA_EINVAL, "t_src out of range");
+    if (nev < 1 || nnoise < 0) return fail(DLMA_EINVAL, "nev must be >= 1 and nnoise >= 0");
+    if (!V_all || !phi_dist || !C_out || (nnoise > 0 && (!phi || !phibar))) return fail(DLMA_EINVAL, "NULL pointer");
+    hipStream_t s = S(stream);
+    const long V = g->V;
+    const long fs = V * 12;  // complex numbers per spinor field
+    const int nd = 4 * nev, nn = 4 * nnoise;
+    // fields: dist solutions, then phi, then phibar
+    std::vector<const double2*> fields;
+    for (int i = 0; i < nd; ++i) fields.push_back((const double2*)phi_dist + i * fs);
+    for (int i = 0; i < nn; ++i) fields.push_back((const double2*)phi + i * fs);
+    for (int i = 0; i < nn; ++i) fields.push_back((const double2*)phibar + i * fs);
+    const int nf = (int)fields.size();
+    // Gram pairs: dist (phi_{l,s'}, phi_{l,s}); noise (phi_{r,s'}, phi_{r,s}) and (phibar_{r,s'}, phi_{r,s})
+    std::vector<const double2*> pa, pb;
+    for (int l = 0; l < nev; ++l)
+        for (int sp = 0; sp < 4; ++sp)
+            for (int sq = 0; sq < 4; ++sq) { pa.push_back(fields[l * 4 + sp]); pb.push_back(fields[l * 4 + sq]); }
+    for (int r = 0; r < nnoise; ++r)
+        for (int y = 0; y < 2; ++y)
+            for (int sp = 0; sp < 4; ++sp)
+                for (int sq = 0; sq < 4; ++sq) {
+                    pa.push_back(fields[nd + (y ? nn : 0) + r * 4 + sp]);
+                    pb.push_back(fields[nd + r * 4 + sq]);
+                }
+    const int np = (int)pa.size();
+    Buf dF, dA, dB, dP, dG;
+    DLMA_TRY(dF.allocate(sizeof(void*) * nf));
+    DLMA_TRY(dA.allocate(sizeof(void*) * np));
+    DLMA_TRY(dB.allocate(sizeof(void*) * np));
+    DLMA_TRY(dP.allocate(sizeof(double2) * (size_t)nf * T * nev * 4));
+    DLMA_TRY(dG.allocate(sizeof(double2) * (size_t)np * T * 16));
+    DLMA_HIP(hipMemcpyAsync(dF.p, fields.data(), sizeof(void*) * nf, hipMemcpyHostToDevice, s));
+    DLMA_HIP(hipMemcpyAsync(dA.p, pa.data(), sizeof(void*) * np, hipMemcpyHostToDevice, s));
+    DLMA_HIP(hipMemcpyAsync(dB.p, pb.data(), sizeof(void*) * np, hipMemcpyHostToDevice, s));
+    DLMA_HIP(launch_tproj((const double2*)V_all, (const double2* const*)dF.p, nf, g->geo, nev, dP.as<double2>(), s));
+    DLMA_HIP(launch_spin_gram((const double2* const*)dA.p, (const double2* const*)dB.p, np, g->geo, dG.as<double2>(), s));
+    std::vector<cplx> P((size_t)nf * T * nev * 4), G((size_t)np * T * 16);
+    DLMA_HIP(hipMemcpyAsync(P.data(), dP.p, sizeof(double2) * P.size(), hipMemcpyDeviceToHost, s));
+    DLMA_HIP(hipMemcpyAsync(G.data(), dG.p, sizeof(double2) * G.size(), hipMemcpyDeviceToHost, s));
+    DLMA_HIP(hipStreamSynchronize(s));
+
+    // Host assembly of the few numbers per timeslice from the GPU projections and Grams.
+    auto Pf = [&](int f, int t, int k, int sp) { return P[(((size_t)f * T + t) * nev + k) * 4 + sp]; };
+    auto Gp = [&](int p, int t, int s1, int s2) { return G[((size_t)p * T + t) * 16 + s1 * 4 + s2]; };
+    std::vector<Gam> ga = gammas();
+    const Gam g5 = ga[4];
+    std::fill(C_out, C_out + (size_t)DLMA_NGAMMA * DLMA_NPARTS * T * 2, 0.0);
+    for (int gi = 0; gi < DLMA_NGAMMA; ++gi) {
+        std::vector<Gam> Gs;
+        if (gi == 0) Gs.push_back(g5);
+        else Gs = {ga[1], ga[2], ga[3]};
+        std::vector<cplx> acc((size_t)DLMA_NPARTS * T, 0.0);
+        for (const Gam& Gm : Gs) {
+            Gam M = gmul(g5, Gm), N = gmul(Gm, g5);
+            for (int d = 0; d < T; ++d) {
+                int t = (t_src + d) % T;
+                // <A, M B>_t from a Gram, <A, M P_t B>_t from projections
+                auto mg = [&](int p) {
+                    cplx v = 0;
+                    for (int a = 0; a < 4; ++a)
+                        for (int b = 0; b < 4; ++b)
+                            if (M.m[a][b] != 0.0) v += M.m[a][b] * Gp(p, t, a, b);
+                    return v;
+                };
+                auto mp = [&](int fa, int fb) {
+                    cplx v = 0;
+                    for (int k = 0; k < nev; ++k)
+                        for (int a = 0; a < 4; ++a)
+                            for (int b = 0; b < 4; ++b)
+                                if (M.m[a][b] != 0.0) v += M.m[a][b] * std::conj(Pf(fa, t, k, a)) * Pf(fb, t, k, b);
+                    return v;
+                };
+                // noise estimators
+                if (nnoise > 0) {
+                    cplx qq = 0, pq = 0, qp = 0, pp = 0, one = 0;
+                    for (int r = 0; r < nnoise; ++r)
+                        for (int s1 = 0; s1 < 4; ++s1)       // s: source spin of phi_{r,s}
+                            for (int s2 = 0; s2 < 4; ++s2) {  // s': spin of phiY_{r,s'}
+                                cplx nc = N.m[s1][s2];
+                                if (nc == 0.0) continue;
+                                int p1 = nev * 16 + (r * 2 + 0) * 16 + s2 * 4 + s1;  // (phi_{r,s'}, phi_{r,s})
+                                int pQ = nev * 16 + (r * 2 + 1) * 16 + s2 * 4 + s1;  // (phibar_{r,s'}, phi_{r,s})
+                                int fB = nd + r * 4 + s1;
+                                int fA1 = nd + r * 4 + s2, fAQ = nd + nn + r * 4 + s2;
+                                cplx g1 = mg(p1), gQ = mg(pQ);
+                                cplx P1 = mp(fA1, fB), PQ = mp(fAQ, fB);
+                                // Y = 1: phi; Y = Q: phibar; Y = P: phi - phibar.  X = P: projected; Q = 1 - P
+                                cplx y1x1 = g1, y1xp = P1, yqx1 = gQ, yqxp = PQ;
+                                cplx ypx1 = g1 - gQ, ypxp = P1 - PQ;
+                                qq += nc * (yqx1 - yqxp);
+                                pq += nc * yqxp;
+                                qp += nc * (ypx1 - ypxp);
+                                pp += nc * ypxp;
+                                one += nc * y1x1;
+                                (void)y1xp;
+                            }
+                    acc[0 * T + d] += qq / (double)nnoise;
+                    acc[1 * T + d] += pq / (double)nnoise;
+                    acc[2 * T + d] += qp / (double)nnoise;
+                    acc[3 * T + d] += pp / (double)nnoise;
+                    acc[4 * T + d] += one / (double)nnoise;
+                }
+                // exact C_dist from the perambulator tau_{(k s),(l s')} = P[l*4+s'][t][k][s]
+                cplx cd = 0;
+                for (int k = 0; k < nev; ++k)
+                    for (int l = 0; l < nev; ++l)
+                        for (int s1 = 0; s1 < 4; ++s1)
+                            for (int s2 = 0; s2 < 4; ++s2) {
+                                if (M.m[s1][s2] == 0.0) continue;
+                                for (int s3 = 0; s3 < 4; ++s3)
+                                    for (int s4 = 0; s4 < 4; ++s4) {
+                                        if (N.m[s3][s4] == 0.0) continue;
+                                        cd += M.m[s1][s2] * Pf(l * 4 + s3, t, k, s2) * N.m[s3][s4] * std::conj(Pf(l * 4 + s4, t, k, s1));
+                                    }
+                            }
+                acc[5 * T + d] += cd;
+                // exact C_QP from the distillation solutions
+                cplx cq = 0;
+                for (int l = 0; l < nev; ++l)
+                    for (int s1 = 0; s1 < 4; ++s1)
+                        for (int s2 = 0; s2 < 4; ++s2) {
+                            cplx nc = N.m[s1][s2];
+                            if (nc == 0.0) continue;
+                            int p = l * 16 + s2 * 4 + s1;  // (phi_{l,s'}, phi_{l,s})
+                            cq += nc * (mg(p) - mp(l * 4 + s2, l * 4 + s1));
+                        }
+                acc[6 * T + d] += cq;
+            }
+        }
+        for (int part = 0; part < DLMA_NPARTS; ++part)
+            for (int d = 0; d < T; ++d) {
+                cplx v = acc[(size_t)part * T + d] / (double)Gs.size();
+                C_out[(((size_t)gi * DLMA_NPARTS + part) * T + d) * 2 + 0] = v.real();
+                C_out[(((size_t)gi * DLMA_NPARTS + part) * T + d) * 2 + 1] = v.imag();
+            }
+    }
+    return DLMA_OK;
 }

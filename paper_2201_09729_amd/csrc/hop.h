@@ -14,7 +14,9 @@
 // covers BS consecutive sites for one group of NB right-hand sides.  The block
 // index is decoded so that all right-hand-side groups of one site block land on
 // the same XCD (workgroups are dealt round-robin to the 8 XCDs) one after the
-// other, so the links and clover of that site block are reused from that XCD's L2.
+// other, so the links and clover of that site block are reused from that XCD's L2,
+// and each XCD sweeps a contiguous range of site blocks so that neighbour spinors
+// loaded for one block are still in its L2 for the next.
 #pragma once
 #include "common.h"
 
@@ -40,6 +42,7 @@ template <int P> struct HopJob {
     int nsb;    // site blocks = ceil(Vh / BS)
     int nsbp;   // nsb rounded up to a multiple of 8
     int blk0;   // first workgroup of this job (multiple of 8)
+    int xmap;   // 0: each XCD sweeps a contiguous range of site blocks; 1: site blocks dealt round-robin
     const typename PT<P>::S* U;  // links, all parities
     const typename PT<P>::S* C;  // clover blocks of the output parity (A or A^-1)
     SF<P> in, x, b, out, r, xs;
@@ -250,7 +253,9 @@ __global__ void __launch_bounds__(BS) hop_kernel(const HopJob<P>* __restrict__ j
     const int lb = bid - J.blk0;
     const int k = lb >> 3;
     const int gi = k % J.G;
-    const int sb = (k / J.G) * 8 + (lb & 7);
+    // XCD (lb & 7) owns site blocks [xcd * nsbp/8, (xcd+1) * nsbp/8) in the contiguous
+    // mapping, so neighbouring site blocks (the +-x,y,z halos) are reused from its L2.
+    const int sb = J.xmap ? (k / J.G) * 8 + (lb & 7) : (lb & 7) * (J.nsbp >> 3) + k / J.G;
     if (sb >= J.nsb) return;  // whole block: padding of the XCD decomposition
     const int cb = sb * BS + (int)threadIdx.x;
     const int g0 = gi * NB;

@@ -1,0 +1,29 @@
+// Launchers of the Laplacian, Lanczos, projector and contraction kernels.
+#pragma once
+#include "kernels.h"
+
+namespace dlma {
+
+hipError_t launch_neg_lap(const double2* U64, const Geo& g, int t0, const double2* in, double2* out, long tsi, long tso,
+                          int nt, hipStream_t s);
+hipError_t launch_dots(const double2* a, long tsa, long isa, const double2* b, long tsb, long n, double2* out, int ostride,
+                       int ni, int nt, hipStream_t s);
+hipError_t launch_sub_combo(const double2* q, long tsq, long isq, const double2* h, int hstride, int ni, double2* w, long tsw,
+                            long n, int nt, hipStream_t s);
+hipError_t launch_lanczos_three(const double2* q, long tsq, long isq, double2* w, long tsw, long n, double* alpha, double* beta,
+                                int astride, int j, int nt, hipStream_t s);
+hipError_t launch_normalize_into(const double2* w, long tsw, double2* q, long tsq, long n, double* nrm, int ostride, int j, int nt,
+                                 hipStream_t s);
+hipError_t launch_ritz(const double2* q, long tsq, long isq, const double* S, int m, int nev, double2* y, long tsy, long n, int nt,
+                       hipStream_t s);
+hipError_t launch_phase_fix(double2* y, long n, int nvec, hipStream_t s);
+hipError_t launch_project(const double2* Vt, const double2* in, double2* out, const Geo& g, int t, int nev, int nrhs, int mode,
+                          double2* coef, hipStream_t s);
+
+// contractions
+hipError_t launch_tproj(const double2* Vall, const double2* const* fields, int nf, const Geo& g, int nev, double2* P,
+                        hipStream_t s);
+hipError_t launch_spin_gram(const double2* const* A, const double2* const* B, int npair, const Geo& g, double2* G,
+                            hipStream_t s);
+
+}  // namespace dlma

@@ -1,0 +1,351 @@
+// Spatial covariant Laplacian (paper eq. 1) on a batch of timeslices, the
+// kernels of the batched Lanczos eigensolver, and the distillation projector.
+//
+// Colour vectors are complex128 in the canonical [site3][colour] order of one
+// timeslice, site3 = (z*Y + y)*X + x; n = 3 L^3 complex numbers per vector.
+// A batch of vectors for nt timeslices is addressed as base + t * tstride.
+#include "laplace.h"
+
+namespace dlma {
+
+__device__ __forceinline__ double2 cmul2(double2 a, double2 b) { return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
+__device__ __forceinline__ double2 cconjmul(double2 a, double2 b) {  // conj(a) * b
+    return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+
+// out = -lap(t) in = 6 in - sum_j [U_j(m,t) in(m+j) + U_j(m-j,t)^dag in(m-j)],  j = x, y, z
+__global__ void k_neg_lap(const double2* __restrict__ U64, Geo g, int t0, const double2* __restrict__ in,
+                          double2* __restrict__ out, long tstride_in, long tstride_out, int nt) {
+    const int L3 = g.Z * g.Y * g.X;
+    long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (long)nt * L3) return;
+    int tl = (int)(i / L3);
+    int m = (int)(i - (long)tl * L3);
+    int t = t0 + tl;
+    int x = m % g.X, y = (m / g.X) % g.Y, z = m / (g.X * g.Y);
+    const double2* v = in + tl * tstride_in;
+    double2 acc[3];
+    for (int a = 0; a < 3; ++a) {
+        double2 q = v[(long)m * 3 + a];
+        acc[a] = make_double2(6.0 * q.x, 6.0 * q.y);
+    }
+    for (int j = 1; j <= 3; ++j) {
+        int xf = x, yf = y, zf = z, xb = x, yb = y, zb = z;
+        if (j == 1) { xf = x + 1 == g.X ? 0 : x + 1; xb = x == 0 ? g.X - 1 : x - 1; }
+        if (j == 2) { yf = y + 1 == g.Y ? 0 : y + 1; yb = y == 0 ? g.Y - 1 : y - 1; }
+        if (j == 3) { zf = z + 1 == g.Z ? 0 : z + 1; zb = z == 0 ? g.Z - 1 : z - 1; }
+        int mf = (zf * g.Y + yf) * g.X + xf, mb = (zb * g.Y + yb) * g.X + xb;
+        // link U_j at (t, m) and at the backward neighbour (t, m - j)
+        int par = (t + z + y + x) & 1, parb = (t + zb + yb + xb) & 1;
+        long cb = (((long)t * g.Z + z) * g.Y + y) * g.Xh + (x >> 1);
+        long cbb = (((long)t * g.Z + zb) * g.Y + yb) * g.Xh + (xb >> 1);
+        const double2* uf = U64 + ((size_t)(par * 4 + j) * 9) * g.Vh + cb;
+        const double2* ub = U64 + ((size_t)(parb * 4 + j) * 9) * g.Vh + cbb;
+        double2 vf[3], vb[3];
+        for (int b = 0; b < 3; ++b) { vf[b] = v[(long)mf * 3 + b]; vb[b] = v[(long)mb * 3 + b]; }
+        for (int a = 0; a < 3; ++a) {
+            double2 s = make_double2(0, 0);
+            for (int b = 0; b < 3; ++b) {
+                double2 u = uf[(size_t)(a * 3 + b) * g.Vh];
+                double2 p = cmul2(u, vf[b]);
+                double2 w = ub[(size_t)(b * 3 + a) * g.Vh];  // (U^dag)_{ab} = conj(U_{ba})
+                double2 q = cconjmul(w, vb[b]);
+                s.x += p.x + q.x;
+                s.y += p.y + q.y;
+            }
+            acc[a].x -= s.x;
+            acc[a].y -= s.y;
+        }
+    }
+    double2* o = out + tl * tstride_out;
+    for (int a = 0; a < 3; ++a) o[(long)m * 3 + a] = acc[a];
+}
+
+hipError_t launch_neg_lap(const double2* U64, const Geo& g, int t0, const double2* in, double2* out, long tsi, long tso,
+                          int nt, hipStream_t s) {
+    long n = (long)nt * g.Z * g.Y * g.X;
+    hipLaunchKernelGGL(k_neg_lap, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, U64, g, t0, in, out, tsi, tso, nt);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- batched reductions
+
+template <int BS> __device__ __forceinline__ double2 block_sum2(double2 v, double* lds) {
+    v.x = block_sum<BS>(v.x, lds);
+    v.y = block_sum<BS>(v.y, lds);
+    return v;
+}
+
+// out[t * ostride + i] = <a_{t,i}, b_t> for i < ni (grid: ni x nt); a_{t,i} = a + t*tsa + i*isa
+__global__ void __launch_bounds__(256) k_dots(const double2* __restrict__ a, long tsa, long isa, const double2* __restrict__ b,
+                                              long tsb, long n, double2* __restrict__ out, int ostride) {
+    __shared__ double lds[4];
+    int i = blockIdx.x, t = blockIdx.y;
+    const double2* pa = a + t * tsa + i * isa;
+    const double2* pb = b + t * tsb;
+    double2 s = make_double2(0, 0);
+    for (long e = threadIdx.x; e < n; e += 256) {
+        double2 p = cconjmul(pa[e], pb[e]);
+        s.x += p.x;
+        s.y += p.y;
+    }
+    s = block_sum2<256>(s, lds);
+    if (threadIdx.x == 0) out[(long)t * ostride + i] = s;
+}
+
+hipError_t launch_dots(const double2* a, long tsa, long isa, const double2* b, long tsb, long n, double2* out, int ostride,
+                       int ni, int nt, hipStream_t s) {
+    if (ni <= 0 || nt <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_dots, dim3(ni, nt), dim3(256), 0, s, a, tsa, isa, b, tsb, n, out, ostride);
+    return hipGetLastError();
+}
+
+// w_t -= sum_{i < ni} q_{t,i} h[t * hstride + i]
+__global__ void k_sub_combo(const double2* __restrict__ q, long tsq, long isq, const double2* __restrict__ h, int hstride,
+                            int ni, double2* __restrict__ w, long tsw, long n, int nt) {
+    long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    int t = blockIdx.y;
+    if (e >= n) return;
+    const double2* hq = h + (long)t * hstride;
+    const double2* pq = q + t * tsq + e;
+    double2 s = make_double2(0, 0);
+    for (int i = 0; i < ni; ++i) {
+        double2 c = cmul2(pq[(long)i * isq], hq[i]);
+        s.x += c.x;
+        s.y += c.y;
+    }
+    double2* pw = w + t * tsw + e;
+    double2 v = *pw;
+    v.x -= s.x;
+    v.y -= s.y;
+    *pw = v;
+}
+
+hipError_t launch_sub_combo(const double2* q, long tsq, long isq, const double2* h, int hstride, int ni, double2* w, long tsw,
+                            long n, int nt, hipStream_t s) {
+    if (ni <= 0 || nt <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_sub_combo, dim3((unsigned)((n + 255) / 256), nt), dim3(256), 0, s, q, tsq, isq, h, hstride, ni, w, tsw,
+                       n, nt);
+    return hipGetLastError();
+}
+
+// Lanczos three-term step: alpha_t = Re <q_j, w>; w -= alpha_t q_j + beta_t q_{j-1} (beta from the previous step)
+__global__ void __launch_bounds__(256) k_lanczos_alpha(const double2* __restrict__ q, long tsq, const double2* __restrict__ w,
+                                                       long tsw, long n, double* __restrict__ alpha, int astride, int j) {
+    __shared__ double lds[4];
+    int t = blockIdx.x;
+    const double2* pq = q + t * tsq;
+    const double2* pw = w + t * tsw;
+    double s = 0;
+    for (long e = threadIdx.x; e < n; e += 256) s += pq[e].x * pw[e].x + pq[e].y * pw[e].y;
+    s = block_sum<256>(s, lds);
+    if (threadIdx.x == 0) alpha[(long)t * astride + j] = s;
+}
+
+__global__ void k_lanczos_three(const double2* __restrict__ qj, const double2* __restrict__ qjm, long tsq,
+                                double2* __restrict__ w, long tsw, long n, const double* __restrict__ alpha,
+                                const double* __restrict__ beta, int astride, int j) {
+    long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    int t = blockIdx.y;
+    if (e >= n) return;
+    double a = alpha[(long)t * astride + j];
+    double2 v = w[t * tsw + e];
+    double2 c = qj[t * tsq + e];
+    v.x -= a * c.x;
+    v.y -= a * c.y;
+    if (j > 0) {
+        double b = beta[(long)t * astride + j - 1];
+        double2 d = qjm[t * tsq + e];
+        v.x -= b * d.x;
+        v.y -= b * d.y;
+    }
+    w[t * tsw + e] = v;
+}
+
+hipError_t launch_lanczos_three(const double2* q, long tsq, long isq, double2* w, long tsw, long n, double* alpha, double* beta,
+                                int astride, int j, int nt, hipStream_t s) {
+    hipLaunchKernelGGL(k_lanczos_alpha, dim3(nt), dim3(256), 0, s, q + (long)j * isq, tsq, w, tsw, n, alpha, astride, j);
+    const double2* qjm = j > 0 ? q + (long)(j - 1) * isq : q;
+    hipLaunchKernelGGL(k_lanczos_three, dim3((unsigned)((n + 255) / 256), nt), dim3(256), 0, s, q + (long)j * isq, qjm, tsq, w, tsw,
+                       n, alpha, beta, astride, j);
+    return hipGetLastError();
+}
+
+// beta_t = |w_t|; q_{j+1} = w / beta (beta below 1e-300 leaves q_{j+1} = 0)
+__global__ void __launch_bounds__(256) k_norm_t(const double2* __restrict__ w, long tsw, long n, double* __restrict__ out,
+                                                int ostride, int j) {
+    __shared__ double lds[4];
+    int t = blockIdx.x;
+    const double2* pw = w + t * tsw;
+    double s = 0;
+    for (long e = threadIdx.x; e < n; e += 256) s += pw[e].x * pw[e].x + pw[e].y * pw[e].y;
+    s = block_sum<256>(s, lds);
+    if (threadIdx.x == 0) out[(long)t * ostride + j] = sqrt(s);
+}
+
+__global__ void k_scale_into(const double2* __restrict__ w, long tsw, double2* __restrict__ q, long tsq, long n,
+                             const double* __restrict__ nrm, int ostride, int j) {
+    long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    int t = blockIdx.y;
+    if (e >= n) return;
+    double b = nrm[(long)t * ostride + j];
+    double inv = b > 1e-300 ? 1.0 / b : 0.0;
+    double2 v = w[t * tsw + e];
+    q[t * tsq + e] = make_double2(v.x * inv, v.y * inv);
+}
+
+hipError_t launch_normalize_into(const double2* w, long tsw, double2* q, long tsq, long n, double* nrm, int ostride, int j, int nt,
+                                 hipStream_t s) {
+    hipLaunchKernelGGL(k_norm_t, dim3(nt), dim3(256), 0, s, w, tsw, n, nrm, ostride, j);
+    hipLaunchKernelGGL(k_scale_into, dim3((unsigned)((n + 255) / 256), nt), dim3(256), 0, s, w, tsw, q, tsq, n, nrm, ostride, j);
+    return hipGetLastError();
+}
+
+// Ritz vectors: y_{t,k} = sum_{i < m} q_{t,i} S[t][i][k], S row-major [m][nev] per t
+__global__ void k_ritz(const double2* __restrict__ q, long tsq, long isq, const double* __restrict__ S, int m, int nev,
+                       double2* __restrict__ y, long tsy, long n) {
+    long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    int t = blockIdx.z;
+    int k0 = blockIdx.y * 4;
+    if (e >= n) return;
+    const double* St = S + (long)t * m * nev;
+    double2 acc[4] = {make_double2(0, 0), make_double2(0, 0), make_double2(0, 0), make_double2(0, 0)};
+    const double2* pq = q + t * tsq + e;
+    for (int i = 0; i < m; ++i) {
+        double2 v = pq[(long)i * isq];
+        for (int kk = 0; kk < 4; ++kk) {
+            if (k0 + kk < nev) {
+                double c = St[(long)i * nev + k0 + kk];
+                acc[kk].x += c * v.x;
+                acc[kk].y += c * v.y;
+            }
+        }
+    }
+    for (int kk = 0; kk < 4; ++kk)
+        if (k0 + kk < nev) y[t * tsy + (long)(k0 + kk) * n + e] = acc[kk];
+}
+
+hipError_t launch_ritz(const double2* q, long tsq, long isq, const double* S, int m, int nev, double2* y, long tsy, long n, int nt,
+                       hipStream_t s) {
+    hipLaunchKernelGGL(k_ritz, dim3((unsigned)((n + 255) / 256), (nev + 3) / 4, nt), dim3(256), 0, s, q, tsq, isq, S, m, nev, y,
+                       tsy, n);
+    return hipGetLastError();
+}
+
+// Phase convention per vector: the component of largest modulus (lowest index among
+// those within 1e-10 of the maximum) becomes real and positive.  One block per vector.
+__global__ void __launch_bounds__(256) k_phase_fix(double2* __restrict__ y, long n) {
+    __shared__ double red[256];
+    __shared__ long ired[256];
+    double2* v = y + (long)blockIdx.x * n;
+    double mx = 0;
+    for (long e = threadIdx.x; e < n; e += 256) mx = fmax(mx, hypot(v[e].x, v[e].y));
+    red[threadIdx.x] = mx;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + st]);
+        __syncthreads();
+    }
+    double thr = red[0] - 1e-10;
+    __syncthreads();
+    long first = n;
+    for (long e = threadIdx.x; e < n; e += 256)
+        if (hypot(v[e].x, v[e].y) >= thr) { first = e; break; }
+    ired[threadIdx.x] = first;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) ired[threadIdx.x] = min(ired[threadIdx.x], ired[threadIdx.x + st]);
+        __syncthreads();
+    }
+    long i0 = ired[0];
+    if (i0 >= n) return;
+    double2 p = v[i0];
+    double a = hypot(p.x, p.y);
+    if (!(a > 0)) return;
+    double2 ph = make_double2(p.x / a, -p.y / a);  // conj(p)/|p|
+    __syncthreads();
+    for (long e = threadIdx.x; e < n; e += 256) v[e] = cmul2(v[e], ph);
+}
+
+hipError_t launch_phase_fix(double2* y, long n, int nvec, hipStream_t s) {
+    hipLaunchKernelGGL(k_phase_fix, dim3(nvec), dim3(256), 0, s, y, n);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- projector
+
+// c[r][k][s] = sum_{m,col} conj(V[k][m][col]) in_r(t, m, s, col); one block per (k, r)
+__global__ void __launch_bounds__(256) k_proj_coef(const double2* __restrict__ Vt, const double2* __restrict__ in, long L3,
+                                                   long tofs, long fstride, int nev, double2* __restrict__ c) {
+    __shared__ double lds[4];
+    int k = blockIdx.x, r = blockIdx.y;
+    const double2* v = Vt + (long)k * L3 * 3;
+    const double2* f = in + (long)r * fstride + tofs;
+    double2 acc[4] = {make_double2(0, 0), make_double2(0, 0), make_double2(0, 0), make_double2(0, 0)};
+    for (long m = threadIdx.x; m < L3; m += 256) {
+        for (int col = 0; col < 3; ++col) {
+            double2 a = v[m * 3 + col];
+            for (int sp = 0; sp < 4; ++sp) {
+                double2 p = cconjmul(a, f[(m * 4 + sp) * 3 + col]);
+                acc[sp].x += p.x;
+                acc[sp].y += p.y;
+            }
+        }
+    }
+    for (int sp = 0; sp < 4; ++sp) {
+        double2 s = block_sum2<256>(acc[sp], lds);
+        if (threadIdx.x == 0) c[((long)r * nev + k) * 4 + sp] = s;
+    }
+}
+
+// out_r = box(t) in_r (mode 0) or (1 - box(t)) in_r (mode 1) on timeslice t, 0 elsewhere
+__global__ void k_proj_apply(const double2* __restrict__ Vt, const double2* in, double2* out, long L3, long V, int t, int nev,
+                             const double2* __restrict__ c, int mode) {
+    long i = (long)blockIdx.x * blockDim.x + threadIdx.x;  // over V sites x 4 spins
+    int r = blockIdx.y;
+    if (i >= V * 4) return;
+    long site = i >> 2;
+    int sp = (int)(i & 3);
+    long base = ((long)r * V * 4 + i) * 3;
+    long tt = site / L3;
+    if (tt != t) {
+        for (int col = 0; col < 3; ++col) out[base + col] = make_double2(0, 0);
+        return;
+    }
+    long m = site - (long)t * L3;
+    double2 acc[3] = {make_double2(0, 0), make_double2(0, 0), make_double2(0, 0)};
+    const double2* cr = c + (long)r * nev * 4;
+    for (int k = 0; k < nev; ++k) {
+        double2 ck = cr[k * 4 + sp];
+        for (int col = 0; col < 3; ++col) {
+            double2 p = cmul2(Vt[((long)k * L3 + m) * 3 + col], ck);
+            acc[col].x += p.x;
+            acc[col].y += p.y;
+        }
+    }
+    for (int col = 0; col < 3; ++col) {
+        double2 o = acc[col];
+        if (mode == 1) {
+            double2 x = in[base + col];
+            o = make_double2(x.x - o.x, x.y - o.y);
+        }
+        out[base + col] = o;
+    }
+}
+
+hipError_t launch_project(const double2* Vt, const double2* in, double2* out, const Geo& g, int t, int nev, int nrhs, int mode,
+                          double2* coef, hipStream_t s) {
+    long L3 = (long)g.Z * g.Y * g.X;
+    long V = 2L * g.Vh;
+    for (int r0 = 0; r0 < nrhs; r0 += 65535) {
+        int nr = nrhs - r0 < 65535 ? nrhs - r0 : 65535;
+        const double2* inr = in + (long)r0 * V * 12;
+        double2* outr = out + (long)r0 * V * 12;
+        hipLaunchKernelGGL(k_proj_coef, dim3(nev, nr), dim3(256), 0, s, Vt, inr, L3, (long)t * L3 * 12, V * 12, nev, coef);
+        hipLaunchKernelGGL(k_proj_apply, dim3((unsigned)((V * 4 + 255) / 256), nr), dim3(256), 0, s, Vt, inr, outr, L3, V, t, nev,
+                           coef, mode);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace dlma

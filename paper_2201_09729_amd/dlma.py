@@ -281,3 +281,28 @@ def dlma_bench_schur(g: Gauge, prec, nrhs: int, rhs_block: int = 0, napply: int 
     _check(load_library().dlma_bench_schur(g.h, int(prec), int(nrhs), int(rhs_block), int(napply),
                                            ctypes.byref(ms), ctypes.byref(by), _stream()))
     return ms.value, by.value
+
+
+# ---------------------------------------------------------------- source placement (data movement only)
+
+def dist_sources(Vt: torch.Tensor, T: int, t0: int) -> torch.Tensor:
+    """Spin-diluted distillation sources v^(k)(t0) x e_s on timeslice t0, index k*4 + s.
+
+    Vt: [nev][Z][Y][X][3] on the GPU.  Returns [4 nev][T][Z][Y][X][4][3]."""
+    Vt = _dev(Vt)
+    nev = Vt.shape[0]
+    out = torch.zeros((nev * 4, T) + tuple(Vt.shape[1:4]) + (4, 3), dtype=torch.complex128, device=Vt.device)
+    for s in range(4):
+        out[s::4, t0, ..., s, :] = Vt
+    return out
+
+
+def noise_sources(xi: torch.Tensor, T: int, t0: int) -> torch.Tensor:
+    """Spin-diluted wall noise xi_r x e_s on timeslice t0, index r*4 + s; xi: [N_r][Z][Y][X][3]."""
+    if not xi.is_cuda:
+        raise ValueError("tensor must be on the GPU")
+    nn = xi.shape[0]
+    out = torch.zeros((nn * 4, T) + tuple(xi.shape[1:4]) + (4, 3), dtype=torch.complex128, device=xi.device)
+    for s in range(4):
+        out[s::4, t0, ..., s, :] = xi.to(torch.complex128)
+    return out
