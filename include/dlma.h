@@ -35,7 +35,7 @@
  *       gauge   [T][Z][Y][X][mu][a][b]
  *       spinor  [nrhs][T][Z][Y][X][spin][colour]
  *       colour  [nvec][Z][Y][X][colour]  (one timeslice)
- *     All four extents must be even and >= 2; the volume must be below 2^24 sites.
+ *     All four extents must be even, >= 2 and <= 4096; the volume must be below 2^24 sites.
  *   - Internal layouts (even-odd, site-fastest structure of arrays per precision)
  *     are private to the library.
  */
@@ -114,6 +114,7 @@ typedef struct {
     int use_x0;        /* 1: x holds the start vector on entry; 0: start from x = 0 */
     int graph_iters;   /* CG iterations captured per hipGraph launch; 0 = direct launches */
     int check_every;   /* CG iterations between host convergence checks (>= 1); 0 = default */
+    int dagger;        /* 1: solve D^dag x = b (x = g5 D^-1 g5 b), the adjoint solve of a backward pass */
 } dlma_solve_opts;
 
 /* Fill opts with the defaults (tol 1e-10, FP64, autotuned blocks, ...). */
@@ -152,16 +153,21 @@ int dlma_solve(const dlma_gauge_t* gs, int ngauge, const dlma_rhs_set* sets,
                const dlma_solve_opts* opts, dlma_solve_stat* stats, void* stream);
 
 typedef struct {
-    double tol;        /* Ritz residual bound |beta_m s_mi| <= tol * 12 (spectrum of -lap in [0,12]) */
+    double tol;        /* residual bound |lap v - lambda v| <= tol * 12 (spectrum of -lap in [0,12]) */
     int max_basis;     /* cap on the Krylov dimension (0 = default) */
     int check_every;   /* Lanczos steps between convergence checks (0 = default) */
+    int cheb_degree;   /* degree of the Chebyshev filter; 0 = automatic (none for 3 L^3 < 4096), < 0 = off */
 } dlma_eig_opts;
 
 /*
  * Lowest nev eigenpairs of -lap(t) for the nt timeslices t0 .. t0+nt-1 (paper
  * eq. 1, Sec. 2: the low-lying modes of the spatial covariant Laplacian on every
- * timeslice, no preconditioning).  Plain Lanczos with full re-orthogonalisation,
- * all timeslices advanced together.
+ * timeslice).  Lanczos with full re-orthogonalisation (two passes of classical
+ * Gram-Schmidt), all timeslices advanced together.  On large timeslices the
+ * Lanczos operator is a Chebyshev polynomial p(-lap) that damps the spectrum
+ * above a cut estimated from a short unfiltered run (p has the same eigenvectors;
+ * the eigenvalues returned are Rayleigh quotients of lap itself, and the
+ * stopping test is the explicit residual |lap v - lambda v|).
  *   v0       device, [nt][Z][Y][X][3] complex128 start vectors (any nonzero vectors)
  *   V_out    device, [nt][nev][Z][Y][X][3] complex128 orthonormal eigenvectors; the
  *            component of largest modulus of each vector is real and positive
@@ -203,6 +209,13 @@ int dlma_project(dlma_gauge_t g, int t, int nev, const void* V_t, const void* in
  */
 int dlma_correlators(dlma_gauge_t g, int t_src, int nev, const void* V_all, const void* phi_dist,
                      int nnoise, const void* phi, const void* phibar, double* C_out, void* stream);
+
+/*
+ * out = <a, b> = sum_i conj(a_i) b_i over n complex128 numbers (FP64, fixed
+ * reduction order).  a, b device; out host double[2] (re, im).  Used by the
+ * backward pass: d/dm0 of a real loss is -Re <D^-dag grad_x, x>.
+ */
+int dlma_dot(const void* a, const void* b, long n, double* out, void* stream);
 
 /* ---------------------------------------------------------------- measurement */
 

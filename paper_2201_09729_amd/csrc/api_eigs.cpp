@@ -109,89 +109,202 @@ extern "C" int dlma_lap_eigs(dlma_gauge_t h, int nev, int t0, int nt, const void
     const long n = 3 * L3;
     if (nt < 1 || t0 < 0 || t0 + nt > T) return fail(DLMA_EINVAL, "timeslices t0..t0+nt-1 must lie in [0, T)");
     if (nev < 1 || nev > n) return fail(DLMA_EINVAL, "nev must be in [1, 3 L^3]");
-    double tol = (opts && opts->tol > 0) ? opts->tol : 1e-10;
+    const double tol = (opts && opts->tol > 0) ? opts->tol : 1e-10;
     int maxm = (opts && opts->max_basis > 0) ? opts->max_basis : (int)std::min<long>(n, 20L * nev + 200);
     maxm = (int)std::min<long>(maxm, n);
     if (maxm < nev) return fail(DLMA_EINVAL, "max_basis must be >= nev");
-    int check = (opts && opts->check_every > 0) ? opts->check_every : 10;
+    const int check = (opts && opts->check_every > 0) ? opts->check_every : 10;
+    int deg = opts ? opts->cheb_degree : 0;
+    if (deg == 0) deg = n >= 4096 ? 24 : 0;
+    if (deg < 0) deg = 0;
     hipStream_t s = S(stream);
     const long isq = n, tsq = (long)(maxm + 1) * n;
-    Buf Q, W, Hc, AB;
+    Buf Q, R[3], Hc, AB, AY, LR;
     DLMA_TRY(Q.allocate(sizeof(double2) * tsq * nt));
-    DLMA_TRY(W.allocate(sizeof(double2) * n * nt));
+    for (auto& b : R) DLMA_TRY(b.allocate(sizeof(double2) * n * nt));
     DLMA_TRY(Hc.allocate(sizeof(double2) * (size_t)(maxm + 1) * nt));
     DLMA_TRY(AB.allocate(sizeof(double) * 2 * (size_t)maxm * nt + 64));
+    DLMA_TRY(AY.allocate(sizeof(double2) * (size_t)nt * nev * n));
+    DLMA_TRY(LR.allocate(sizeof(double) * 2 * (size_t)nt * nev));
     double2* q = Q.as<double2>();
-    double2* w = W.as<double2>();
     double* alpha = AB.as<double>();
     double* beta = alpha + (size_t)maxm * nt;
-    // q_0 = v0 / |v0|  (norm stored in the beta slot of step 0, overwritten later)
-    DLMA_HIP(launch_normalize_into((const double2*)v0, n, q, tsq, n, beta, maxm, 0, nt, s));
-    std::vector<double> ha((size_t)maxm * nt), hb((size_t)maxm * nt);
-    {
-        std::vector<double> b0((size_t)maxm * nt);
-        DLMA_HIP(hipMemcpyAsync(b0.data(), beta, sizeof(double) * maxm * nt, hipMemcpyDeviceToHost, s));
+    double* dlam = LR.as<double>();
+    double* dres = dlam + (size_t)nt * nev;
+    double2* Vo = (double2*)V_out;
+    const double2* U64 = g->U64.as<double2>();
+    std::vector<double> ha((size_t)maxm * nt), hb((size_t)maxm * nt), hlam((size_t)nt * nev), hres((size_t)nt * nev);
+    int cur_deg = 0;
+    double cc = 0, ee = 1;
+
+    // w = B q_j with B = -lap (cur_deg = 0) or T_deg((c - (-lap))/e)
+    auto apply_op = [&](const double2* qj, double2*& w) -> int {
+        if (cur_deg == 0) {
+            DLMA_HIP(launch_neg_lap(U64, g->geo, t0, qj, R[0].as<double2>(), tsq, n, nt, s));
+            w = R[0].as<double2>();
+            return DLMA_OK;
+        }
+        double2 *a = R[0].as<double2>(), *b = R[1].as<double2>(), *c = R[2].as<double2>();
+        DLMA_HIP(hipMemcpy2DAsync(a, n * sizeof(double2), qj, tsq * sizeof(double2), n * sizeof(double2), nt,
+                                  hipMemcpyDeviceToDevice, s));
+        DLMA_HIP(launch_cheb_step(U64, g->geo, t0, a, nullptr, b, n, nt, cc, 1.0 / ee, s));
+        for (int k = 2; k <= cur_deg; ++k) {
+            DLMA_HIP(launch_cheb_step(U64, g->geo, t0, b, a, c, n, nt, cc, 2.0 / ee, s));
+            double2* t = a;
+            a = b;
+            b = c;
+            c = t;
+        }
+        w = b;
+        return DLMA_OK;
+    };
+    // Ritz vectors of the m-step tridiagonal matrices (the nev smallest or largest Ritz
+    // values) into V_out, then their Rayleigh quotients and residuals for -lap
+    auto ritz_check = [&](int m, bool largest, bool& ok) -> int {
+        DLMA_HIP(hipMemcpyAsync(ha.data(), alpha, sizeof(double) * maxm * nt, hipMemcpyDeviceToHost, s));
+        DLMA_HIP(hipMemcpyAsync(hb.data(), beta, sizeof(double) * maxm * nt, hipMemcpyDeviceToHost, s));
+        DLMA_HIP(hipStreamSynchronize(s));
+        std::vector<double> Sall((size_t)nt * m * nev);
+        for (int t = 0; t < nt; ++t) {
+            std::vector<double> d(ha.begin() + (size_t)t * maxm, ha.begin() + (size_t)t * maxm + m);
+            std::vector<double> e(hb.begin() + (size_t)t * maxm, hb.begin() + (size_t)t * maxm + m - 1);
+            std::vector<double> Z;
+            if (!tridiag_ql(d, e, &Z, nullptr)) return fail(DLMA_EHIP, "tridiagonal eigensolver did not converge");
+            std::vector<int> idx = argsort(d);
+            if (largest) std::reverse(idx.begin(), idx.end());
+            for (int k = 0; k < nev; ++k)
+                for (int i = 0; i < m; ++i) Sall[((size_t)t * m + i) * nev + k] = Z[(size_t)i * m + idx[k]];
+        }
+        Buf Sd;
+        DLMA_TRY(Sd.allocate(sizeof(double) * Sall.size()));
+        DLMA_HIP(hipMemcpyAsync(Sd.p, Sall.data(), sizeof(double) * Sall.size(), hipMemcpyHostToDevice, s));
+        DLMA_HIP(launch_ritz(q, tsq, isq, Sd.as<double>(), m, nev, Vo, (long)nev * n, n, nt, s));
+        DLMA_HIP(launch_neg_lap(U64, g->geo, t0, Vo, AY.as<double2>(), (long)nev * n, (long)nev * n, nt, s, nev, n, n));
+        DLMA_HIP(launch_rayleigh(Vo, AY.as<double2>(), n, nt * nev, dlam, dres, s));
+        DLMA_HIP(hipMemcpyAsync(hlam.data(), dlam, sizeof(double) * nt * nev, hipMemcpyDeviceToHost, s));
+        DLMA_HIP(hipMemcpyAsync(hres.data(), dres, sizeof(double) * nt * nev, hipMemcpyDeviceToHost, s));
+        DLMA_HIP(hipStreamSynchronize(s));
+        ok = true;
+        for (double r : hres)
+            if (!(r <= tol * 12.0)) ok = false;
+        return DLMA_OK;
+    };
+    // msteps Lanczos steps with the current operator from q_0 = v0/|v0|
+    auto lanczos = [&](int msteps, bool largest, bool checks, int& m, bool& conv) -> int {
+        conv = false;
+        m = 0;
+        DLMA_HIP(launch_normalize_into((const double2*)v0, n, q, tsq, n, beta, maxm, 0, nt, s));
+        DLMA_HIP(hipMemcpyAsync(hb.data(), beta, sizeof(double) * maxm * nt, hipMemcpyDeviceToHost, s));
         DLMA_HIP(hipStreamSynchronize(s));
         for (int t = 0; t < nt; ++t)
-            if (!(b0[(size_t)t * maxm] > 0) || !std::isfinite(b0[(size_t)t * maxm]))
+            if (!(hb[(size_t)t * maxm] > 0) || !std::isfinite(hb[(size_t)t * maxm]))
                 return fail(DLMA_EINVAL, "start vector is zero or not finite");
-    }
-    int m = 0;
-    bool converged = false;
-    for (int j = 0; j < maxm; ++j) {
-        double2* qj = q + (long)j * isq;
-        DLMA_HIP(launch_neg_lap(g->U64.as<double2>(), g->geo, t0, qj, w, tsq, n, nt, s));
-        DLMA_HIP(launch_lanczos_three(q, tsq, isq, w, n, n, alpha, beta, maxm, j, nt, s));
-        for (int pass = 0; pass < 2; ++pass) {  // classical Gram-Schmidt, twice
-            DLMA_HIP(launch_dots(q, tsq, isq, w, n, n, Hc.as<double2>(), maxm + 1, j + 1, nt, s));
-            DLMA_HIP(launch_sub_combo(q, tsq, isq, Hc.as<double2>(), maxm + 1, j + 1, w, n, n, nt, s));
-        }
-        DLMA_HIP(launch_normalize_into(w, n, q + (long)(j + 1) * isq, tsq, n, beta, maxm, j, nt, s));
-        m = j + 1;
-        bool last_step = (m == maxm);
-        if (m >= nev && (m % check == 0 || last_step)) {
+        for (int j = 0; j < msteps; ++j) {
+            double2* w = nullptr;
+            DLMA_TRY(apply_op(q + (long)j * isq, w));
+            DLMA_HIP(launch_lanczos_three(q, tsq, isq, w, n, n, alpha, beta, maxm, j, nt, s));
+            for (int pass = 0; pass < 2; ++pass) {  // classical Gram-Schmidt against all q_i, twice
+                DLMA_HIP(launch_dots(q, tsq, isq, w, n, n, Hc.as<double2>(), maxm + 1, j + 1, nt, s));
+                DLMA_HIP(launch_sub_combo(q, tsq, isq, Hc.as<double2>(), maxm + 1, j + 1, w, n, n, nt, s));
+            }
+            DLMA_HIP(launch_normalize_into(w, n, q + (long)(j + 1) * isq, tsq, n, beta, maxm, j, nt, s));
+            m = j + 1;
+            if (!checks || m < nev || (m % check != 0 && m != msteps)) continue;
             DLMA_HIP(hipMemcpyAsync(ha.data(), alpha, sizeof(double) * maxm * nt, hipMemcpyDeviceToHost, s));
             DLMA_HIP(hipMemcpyAsync(hb.data(), beta, sizeof(double) * maxm * nt, hipMemcpyDeviceToHost, s));
             DLMA_HIP(hipStreamSynchronize(s));
-            bool all = true, exhausted = false;
-            for (int t = 0; t < nt && all; ++t) {
+            // cheap test first: Ritz residual estimates |beta_m s_mi| of the Lanczos operator
+            bool trigger = true;
+            for (int t = 0; t < nt && trigger; ++t) {
                 std::vector<double> d(ha.begin() + (size_t)t * maxm, ha.begin() + (size_t)t * maxm + m);
                 std::vector<double> e(hb.begin() + (size_t)t * maxm, hb.begin() + (size_t)t * maxm + m - 1);
                 double bm = hb[(size_t)t * maxm + m - 1];
-                if (bm < 1e-12) exhausted = true;  // invariant subspace: Ritz values exact
+                if (bm < 1e-12) continue;  // invariant subspace reached: Ritz pairs exact
                 std::vector<double> last;
                 if (!tridiag_ql(d, e, nullptr, &last)) return fail(DLMA_EHIP, "tridiagonal eigensolver did not converge");
                 std::vector<int> idx = argsort(d);
-                for (int k = 0; k < nev; ++k)
-                    if (std::fabs(bm * last[idx[k]]) > tol * 12.0 && !(bm < 1e-12)) { all = false; break; }
+                if (largest) std::reverse(idx.begin(), idx.end());
+                for (int k = 0; k < nev; ++k) {
+                    double scale = largest ? std::fabs(d[idx[k]]) : 12.0;
+                    if (std::fabs(bm * last[idx[k]]) > tol * scale) { trigger = false; break; }
+                }
             }
-            if (all || exhausted) { converged = true; break; }
+            if (!trigger && m != msteps) continue;
+            bool ok = false;
+            DLMA_TRY(ritz_check(m, largest, ok));
+            if (ok) { conv = true; return DLMA_OK; }
+        }
+        return DLMA_OK;
+    };
+
+    int m = 0;
+    bool conv = false;
+    if (deg > 0) {
+        // short unfiltered run: Ritz values are upper bounds of the lowest eigenvalues,
+        // so the (nev + nev/4 + 4)-th one lies above every wanted eigenvalue
+        int m0 = (int)std::min<long>(std::min(maxm, std::max(2 * nev + 20, 40)), n);
+        DLMA_TRY(lanczos(m0, false, false, m, conv));
+        DLMA_HIP(hipMemcpyAsync(ha.data(), alpha, sizeof(double) * maxm * nt, hipMemcpyDeviceToHost, s));
+        DLMA_HIP(hipMemcpyAsync(hb.data(), beta, sizeof(double) * maxm * nt, hipMemcpyDeviceToHost, s));
+        DLMA_HIP(hipStreamSynchronize(s));
+        double cut = 0;
+        int jc = std::min(m - 1, nev + nev / 4 + 4);
+        for (int t = 0; t < nt; ++t) {
+            std::vector<double> d(ha.begin() + (size_t)t * maxm, ha.begin() + (size_t)t * maxm + m);
+            std::vector<double> e(hb.begin() + (size_t)t * maxm, hb.begin() + (size_t)t * maxm + m - 1);
+            if (!tridiag_ql(d, e, nullptr, nullptr)) return fail(DLMA_EHIP, "tridiagonal eigensolver did not converge");
+            std::sort(d.begin(), d.end());
+            cut = std::max(cut, d[jc]);
+        }
+        if (cut < 11.0) {  // damp [cut, 12]; otherwise the filter would not help
+            cur_deg = deg;
+            cc = 0.5 * (cut + 12.0);
+            ee = 0.5 * (12.0 - cut);
         }
     }
-    // final Ritz pairs from the m-step tridiagonal matrices
-    if (m < nev) return fail(DLMA_ENOTCONV, "Krylov space smaller than nev");
-    DLMA_HIP(hipMemcpyAsync(ha.data(), alpha, sizeof(double) * maxm * nt, hipMemcpyDeviceToHost, s));
-    DLMA_HIP(hipMemcpyAsync(hb.data(), beta, sizeof(double) * maxm * nt, hipMemcpyDeviceToHost, s));
-    DLMA_HIP(hipStreamSynchronize(s));
-    std::vector<double> Sall((size_t)nt * m * nev);
+    DLMA_TRY(lanczos(maxm, cur_deg > 0, true, m, conv));
+    if (!conv) {  // basis cap reached: report the last Ritz pairs
+        bool ok = false;
+        DLMA_TRY(ritz_check(m, cur_deg > 0, ok));
+        conv = ok;
+    }
+    // order by eigenvalue of -lap (ascending) within each timeslice
+    std::vector<int> perm((size_t)nt * nev);
+    bool permute = false;
     for (int t = 0; t < nt; ++t) {
-        std::vector<double> d(ha.begin() + (size_t)t * maxm, ha.begin() + (size_t)t * maxm + m);
-        std::vector<double> e(hb.begin() + (size_t)t * maxm, hb.begin() + (size_t)t * maxm + m - 1);
-        std::vector<double> Z;
-        if (!tridiag_ql(d, e, &Z, nullptr)) return fail(DLMA_EHIP, "tridiagonal eigensolver did not converge");
-        std::vector<int> idx = argsort(d);
+        std::vector<double> l(hlam.begin() + (size_t)t * nev, hlam.begin() + (size_t)t * nev + nev);
+        std::vector<int> idx = argsort(l);
         for (int k = 0; k < nev; ++k) {
-            evals[(size_t)t * nev + k] = -d[idx[k]];
-            for (int i = 0; i < m; ++i) Sall[((size_t)t * m + i) * nev + k] = Z[(size_t)i * m + idx[k]];
+            perm[(size_t)t * nev + k] = idx[k];
+            if (idx[k] != k) permute = true;
+            evals[(size_t)t * nev + k] = -l[idx[k]];
         }
     }
-    Buf Sd;
-    DLMA_TRY(Sd.allocate(sizeof(double) * Sall.size()));
-    DLMA_HIP(hipMemcpyAsync(Sd.p, Sall.data(), sizeof(double) * Sall.size(), hipMemcpyHostToDevice, s));
-    DLMA_HIP(launch_ritz(q, tsq, isq, Sd.as<double>(), m, nev, (double2*)V_out, (long)nev * n, n, nt, s));
-    DLMA_HIP(launch_phase_fix((double2*)V_out, n, nev * nt, s));
+    if (permute) {
+        DLMA_HIP(hipMemcpyAsync(AY.p, Vo, sizeof(double2) * (size_t)nt * nev * n, hipMemcpyDeviceToDevice, s));
+        for (int t = 0; t < nt; ++t)
+            for (int k = 0; k < nev; ++k)
+                DLMA_HIP(hipMemcpyAsync(Vo + ((size_t)t * nev + k) * n, AY.as<double2>() + ((size_t)t * nev + perm[(size_t)t * nev + k]) * n,
+                                        sizeof(double2) * n, hipMemcpyDeviceToDevice, s));
+    }
+    DLMA_HIP(launch_phase_fix(Vo, n, nev * nt, s));
     DLMA_HIP(hipStreamSynchronize(s));
-    if (!converged) return fail(DLMA_ENOTCONV, "Lanczos did not reach the tolerance within max_basis steps");
+    if (!conv) return fail(DLMA_ENOTCONV, "Lanczos did not reach the tolerance within max_basis steps");
+    return DLMA_OK;
+}
+
+extern "C" int dlma_dot(const void* a, const void* b, long n, double* out, void* stream) {
+    if (!a || !b || !out) return fail(DLMA_EINVAL, "NULL pointer");
+    if (n < 0) return fail(DLMA_EINVAL, "n < 0");
+    hipStream_t s = S(stream);
+    Buf r;
+    DLMA_TRY(r.allocate(sizeof(double2)));
+    DLMA_HIP(launch_dots((const double2*)a, 0, 0, (const double2*)b, 0, n, r.as<double2>(), 1, 1, 1, s));
+    double2 h;
+    DLMA_HIP(hipMemcpyAsync(&h, r.p, sizeof(double2), hipMemcpyDeviceToHost, s));
+    DLMA_HIP(hipStreamSynchronize(s));
+    out[0] = h.x;
+    out[1] = h.y;
     return DLMA_OK;
 }
 

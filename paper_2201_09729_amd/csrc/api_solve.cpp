@@ -32,6 +32,7 @@ extern "C" void dlma_solve_opts_default(dlma_solve_opts* o) {
     o->use_x0 = 0;
     o->graph_iters = 0;
     o->check_every = 0;
+    o->dagger = 0;
 }
 
 namespace {
@@ -304,8 +305,9 @@ int solve_impl(std::vector<Cfg>& cs, const dlma_solve_opts& o, hipStream_t s) {
     int ncfg = (int)cs.size();
     // load sources and start vectors
     for (auto& c : cs) {
-        DLMA_HIP(launch_canon_to_eo(c.bcan, c.B.as<double2>(), c.g->geo, c.nrhs, s));
-        if (o.use_x0) DLMA_HIP(launch_canon_to_eo(c.xcan, c.X.as<double2>(), c.g->geo, c.nrhs, s));
+        // D^dag x = b  <=>  D (g5 x) = g5 b: solve for X = g5 x with source g5 b
+        DLMA_HIP(launch_canon_to_eo(c.bcan, c.B.as<double2>(), c.g->geo, c.nrhs, s, o.dagger));
+        if (o.use_x0) DLMA_HIP(launch_canon_to_eo(c.xcan, c.X.as<double2>(), c.g->geo, c.nrhs, s, o.dagger));
         else DLMA_HIP(hipMemsetAsync(c.X.p, 0, c.X.n, s));
     }
     DLMA_HIP(launch_norm<P64>(t.dvnB.template as<VecJob<P64>>(), t.nvnB, t.bvnB, s));
@@ -388,7 +390,7 @@ int solve_impl(std::vector<Cfg>& cs, const dlma_solve_opts& o, hipStream_t s) {
         for (auto& c : cs)
             for (int r = 0; r < c.nrhs; ++r) c.used[r] += c.hiters[r];
     }
-    for (auto& c : cs) DLMA_HIP(launch_eo_to_canon(c.X.as<double2>(), c.xcan, c.g->geo, c.nrhs, s));
+    for (auto& c : cs) DLMA_HIP(launch_eo_to_canon(c.X.as<double2>(), c.xcan, c.g->geo, c.nrhs, s, o.dagger));
     DLMA_HIP(hipStreamSynchronize(s));
     return DLMA_OK;
 }
@@ -461,6 +463,7 @@ extern "C" int dlma_solve(const dlma_gauge_t* gs, int ngauge, const dlma_rhs_set
     if (o.prec < 0 || o.prec > 3) return fail(DLMA_EINVAL, "prec must be one of DLMA_PREC_*");
     if (o.inner_tol < 0 || o.inner_tol >= 1) return fail(DLMA_EINVAL, "inner_tol must be in [0, 1)");
     if (o.check_every < 0 || o.graph_iters < 0) return fail(DLMA_EINVAL, "check_every and graph_iters must be >= 0");
+    if (o.dagger != 0 && o.dagger != 1) return fail(DLMA_EINVAL, "dagger must be 0 or 1");
     std::vector<Cfg> cs;
     cs.reserve(ngauge);
     int total = 0;

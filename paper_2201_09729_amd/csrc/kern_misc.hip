@@ -325,7 +325,7 @@ template hipError_t launch_convert_pairs<PB16>(const double2*, void*, long, hipS
 
 // ---------------------------------------------------------------- canonical <-> even-odd
 
-__global__ void k_canon_to_eo(const double2* __restrict__ can, double2* __restrict__ eo, Geo g, int nrhs) {
+__global__ void k_canon_to_eo(const double2* __restrict__ can, double2* __restrict__ eo, Geo g, int nrhs, int g5) {
     long V = 2L * g.Vh;
     long s = (long)blockIdx.x * blockDim.x + threadIdx.x;
     int r = blockIdx.y;
@@ -336,10 +336,14 @@ __global__ void k_canon_to_eo(const double2* __restrict__ can, double2* __restri
     const double2* src = can + ((size_t)r * V + s) * 12;
     double2* dst = eo + ((size_t)r * 2 + par) * 12 * g.Vh + cb;
 #pragma unroll
-    for (int k = 0; k < 12; ++k) dst[(size_t)k * g.Vh] = src[k];
+    for (int k = 0; k < 12; ++k) {
+        double2 v = src[k];
+        if (g5 && k >= 6) v = make_double2(-v.x, -v.y);  // g5 = diag(1,1,-1,-1) in spin
+        dst[(size_t)k * g.Vh] = v;
+    }
 }
 
-__global__ void k_eo_to_canon(const double2* __restrict__ eo, double2* __restrict__ can, Geo g, int nrhs) {
+__global__ void k_eo_to_canon(const double2* __restrict__ eo, double2* __restrict__ can, Geo g, int nrhs, int g5) {
     long V = 2L * g.Vh;
     long s = (long)blockIdx.x * blockDim.x + threadIdx.x;
     int r = blockIdx.y;
@@ -350,27 +354,31 @@ __global__ void k_eo_to_canon(const double2* __restrict__ eo, double2* __restric
     const double2* src = eo + ((size_t)r * 2 + par) * 12 * g.Vh + cb;
     double2* dst = can + ((size_t)r * V + s) * 12;
 #pragma unroll
-    for (int k = 0; k < 12; ++k) dst[k] = src[(size_t)k * g.Vh];
+    for (int k = 0; k < 12; ++k) {
+        double2 v = src[(size_t)k * g.Vh];
+        if (g5 && k >= 6) v = make_double2(-v.x, -v.y);
+        dst[k] = v;
+    }
 }
 
-hipError_t launch_canon_to_eo(const double2* can, double2* eo, const Geo& g, int nrhs, hipStream_t s) {
+hipError_t launch_canon_to_eo(const double2* can, double2* eo, const Geo& g, int nrhs, hipStream_t s, int g5) {
     if (nrhs <= 0) return hipSuccess;
     long V = 2L * g.Vh;
     for (int r0 = 0; r0 < nrhs; r0 += 65535) {
         int n = nrhs - r0 < 65535 ? nrhs - r0 : 65535;
         hipLaunchKernelGGL(k_canon_to_eo, dim3((unsigned)((V + 255) / 256), n), dim3(256), 0, s,
-                           can + (size_t)r0 * V * 12, eo + (size_t)r0 * V * 12, g, n);
+                           can + (size_t)r0 * V * 12, eo + (size_t)r0 * V * 12, g, n, g5);
     }
     return hipGetLastError();
 }
 
-hipError_t launch_eo_to_canon(const double2* eo, double2* can, const Geo& g, int nrhs, hipStream_t s) {
+hipError_t launch_eo_to_canon(const double2* eo, double2* can, const Geo& g, int nrhs, hipStream_t s, int g5) {
     if (nrhs <= 0) return hipSuccess;
     long V = 2L * g.Vh;
     for (int r0 = 0; r0 < nrhs; r0 += 65535) {
         int n = nrhs - r0 < 65535 ? nrhs - r0 : 65535;
         hipLaunchKernelGGL(k_eo_to_canon, dim3((unsigned)((V + 255) / 256), n), dim3(256), 0, s,
-                           eo + (size_t)r0 * V * 12, can + (size_t)r0 * V * 12, g, n);
+                           eo + (size_t)r0 * V * 12, can + (size_t)r0 * V * 12, g, n, g5);
     }
     return hipGetLastError();
 }

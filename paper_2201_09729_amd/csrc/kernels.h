@@ -49,8 +49,8 @@ hipError_t launch_add_diag(double2* C, int Vh, double delta, hipStream_t s);
 template <int P> hipError_t launch_convert_pairs(const double2* src, void* dst, long n, hipStream_t s);
 
 // full FP64 fields <-> canonical
-hipError_t launch_canon_to_eo(const double2* can, double2* eo, const Geo& g, int nrhs, hipStream_t s);
-hipError_t launch_eo_to_canon(const double2* eo, double2* can, const Geo& g, int nrhs, hipStream_t s);
+hipError_t launch_canon_to_eo(const double2* can, double2* eo, const Geo& g, int nrhs, hipStream_t s, int g5 = 0);
+hipError_t launch_eo_to_canon(const double2* eo, double2* can, const Geo& g, int nrhs, hipStream_t s, int g5 = 0);
 
 // vector kernels (jobs in device memory, total blocks given)
 hipError_t launch_clover_apply64(const VecJob<P64>* j, int njob, int nblocks, hipStream_t s);  // c = C a

@@ -5,7 +5,10 @@
 namespace dlma {
 
 hipError_t launch_neg_lap(const double2* U64, const Geo& g, int t0, const double2* in, double2* out, long tsi, long tso,
-                          int nt, hipStream_t s);
+                          int nt, hipStream_t s, int nv = 1, long vsi = 0, long vso = 0);
+hipError_t launch_cheb_step(const double2* U64, const Geo& g, int t0, const double2* in, const double2* prev, double2* out,
+                            long ts, int nt, double c1, double c2, hipStream_t s);
+hipError_t launch_rayleigh(const double2* y, const double2* ay, long n, int nvec, double* lam, double* res, hipStream_t s);
 hipError_t launch_dots(const double2* a, long tsa, long isa, const double2* b, long tsb, long n, double2* out, int ostride,
                        int ni, int nt, hipStream_t s);
 hipError_t launch_sub_combo(const double2* q, long tsq, long isq, const double2* h, int hstride, int ni, double2* w, long tsw,

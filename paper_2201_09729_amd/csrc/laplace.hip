@@ -13,17 +13,27 @@ __device__ __forceinline__ double2 cconjmul(double2 a, double2 b) {  // conj(a) 
     return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
 }
 
-// out = -lap(t) in = 6 in - sum_j [U_j(m,t) in(m+j) + U_j(m-j,t)^dag in(m-j)],  j = x, y, z
+// Chebyshev-filter mode of the stencil: out = c2 * (c1 * in - (-lap) in) - prev
+struct LapMode {
+    int cheb;            // 0: out = -lap in;  1: out = c2 (c1 in + lap in) - prev
+    double c1, c2;
+    const double2* prev; // same addressing as in; nullptr = 0
+};
+
+// out = -lap(t) in = 6 in - sum_j [U_j(m,t) in(m+j) + U_j(m-j,t)^dag in(m-j)],  j = x, y, z,
+// for nv vectors on each of nt timeslices: vector (tl, kv) at base + tl*tstride + kv*vstride.
 __global__ void k_neg_lap(const double2* __restrict__ U64, Geo g, int t0, const double2* __restrict__ in,
-                          double2* __restrict__ out, long tstride_in, long tstride_out, int nt) {
+                          double2* __restrict__ out, long tstride_in, long tstride_out, int nt, int nv, long vstride_in,
+                          long vstride_out, LapMode md) {
     const int L3 = g.Z * g.Y * g.X;
     long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (long)nt * L3) return;
+    int kv = blockIdx.y;
+    if (i >= (long)nt * L3 || kv >= nv) return;
     int tl = (int)(i / L3);
     int m = (int)(i - (long)tl * L3);
     int t = t0 + tl;
     int x = m % g.X, y = (m / g.X) % g.Y, z = m / (g.X * g.Y);
-    const double2* v = in + tl * tstride_in;
+    const double2* v = in + tl * tstride_in + kv * vstride_in;
     double2 acc[3];
     for (int a = 0; a < 3; ++a) {
         double2 q = v[(long)m * 3 + a];
@@ -57,14 +67,66 @@ __global__ void k_neg_lap(const double2* __restrict__ U64, Geo g, int t0, const 
             acc[a].y -= s.y;
         }
     }
-    double2* o = out + tl * tstride_out;
+    double2* o = out + tl * tstride_out + kv * vstride_out;
+    if (md.cheb) {
+        const double2* pv = md.prev ? md.prev + tl * tstride_in + kv * vstride_in : nullptr;
+        for (int a = 0; a < 3; ++a) {
+            double2 q = v[(long)m * 3 + a], pr = pv ? pv[(long)m * 3 + a] : make_double2(0.0, 0.0);
+            acc[a] = make_double2(md.c2 * (md.c1 * q.x - acc[a].x) - pr.x, md.c2 * (md.c1 * q.y - acc[a].y) - pr.y);
+        }
+    }
     for (int a = 0; a < 3; ++a) o[(long)m * 3 + a] = acc[a];
 }
 
 hipError_t launch_neg_lap(const double2* U64, const Geo& g, int t0, const double2* in, double2* out, long tsi, long tso,
-                          int nt, hipStream_t s) {
+                          int nt, hipStream_t s, int nv, long vsi, long vso) {
     long n = (long)nt * g.Z * g.Y * g.X;
-    hipLaunchKernelGGL(k_neg_lap, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, U64, g, t0, in, out, tsi, tso, nt);
+    LapMode md = {0, 0.0, 0.0, nullptr};
+    hipLaunchKernelGGL(k_neg_lap, dim3((unsigned)((n + 255) / 256), nv), dim3(256), 0, s, U64, g, t0, in, out, tsi, tso, nt, nv,
+                       vsi, vso, md);
+    return hipGetLastError();
+}
+
+// out = c2 * (c1 * in - (-lap) in) - prev  (one step of the Chebyshev three-term recurrence)
+hipError_t launch_cheb_step(const double2* U64, const Geo& g, int t0, const double2* in, const double2* prev, double2* out,
+                            long ts, int nt, double c1, double c2, hipStream_t s) {
+    long n = (long)nt * g.Z * g.Y * g.X;
+    LapMode md = {1, c1, c2, prev};
+    hipLaunchKernelGGL(k_neg_lap, dim3((unsigned)((n + 255) / 256), 1), dim3(256), 0, s, U64, g, t0, in, out, ts, ts, nt, 1, 0L,
+                       0L, md);
+    return hipGetLastError();
+}
+
+// Per vector: lambda = Re <y, Ay> (y normalised), then |Ay - lambda y|; one block per vector
+__global__ void __launch_bounds__(256) k_rayleigh(const double2* __restrict__ y, const double2* __restrict__ ay, long n,
+                                                  double* __restrict__ lam, double* __restrict__ res) {
+    __shared__ double lds[4];
+    const double2* py = y + (long)blockIdx.x * n;
+    const double2* pa = ay + (long)blockIdx.x * n;
+    double d = 0, nn = 0;
+    for (long e = threadIdx.x; e < n; e += 256) {
+        d += py[e].x * pa[e].x + py[e].y * pa[e].y;
+        nn += py[e].x * py[e].x + py[e].y * py[e].y;
+    }
+    d = block_sum<256>(d, lds);
+    nn = block_sum<256>(nn, lds);
+    __shared__ double l;
+    if (threadIdx.x == 0) l = d / nn;
+    __syncthreads();
+    double r = 0;
+    for (long e = threadIdx.x; e < n; e += 256) {
+        double rx = pa[e].x - l * py[e].x, ry = pa[e].y - l * py[e].y;
+        r += rx * rx + ry * ry;
+    }
+    r = block_sum<256>(r, lds);
+    if (threadIdx.x == 0) {
+        lam[blockIdx.x] = l;
+        res[blockIdx.x] = sqrt(r / nn);
+    }
+}
+
+hipError_t launch_rayleigh(const double2* y, const double2* ay, long n, int nvec, double* lam, double* res, hipStream_t s) {
+    hipLaunchKernelGGL(k_rayleigh, dim3(nvec), dim3(256), 0, s, y, ay, n, lam, res);
     return hipGetLastError();
 }
 

@@ -39,7 +39,8 @@ class DlmaError(RuntimeError):
 class SolveOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("maxiter", ctypes.c_int), ("max_outer", ctypes.c_int),
                 ("prec", ctypes.c_int), ("inner_tol", ctypes.c_double), ("rhs_block", ctypes.c_int),
-                ("use_x0", ctypes.c_int), ("graph_iters", ctypes.c_int), ("check_every", ctypes.c_int)]
+                ("use_x0", ctypes.c_int), ("graph_iters", ctypes.c_int), ("check_every", ctypes.c_int),
+                ("dagger", ctypes.c_int)]
 
 
 class SolveStat(ctypes.Structure):
@@ -52,7 +53,8 @@ class RhsSet(ctypes.Structure):
 
 
 class EigOpts(ctypes.Structure):
-    _fields_ = [("tol", ctypes.c_double), ("max_basis", ctypes.c_int), ("check_every", ctypes.c_int)]
+    _fields_ = [("tol", ctypes.c_double), ("max_basis", ctypes.c_int), ("check_every", ctypes.c_int),
+                ("cheb_degree", ctypes.c_int)]
 
 
 _lib = None
@@ -80,6 +82,7 @@ def load_library(path: str = LIB_PATH):
         "dlma_lap_eigs": ([P, I, I, I, P, P, P, P, P], I),
         "dlma_project": ([P, I, I, P, P, P, I, I, P], I),
         "dlma_correlators": ([P, I, I, P, P, I, P, P, P, P], I),
+        "dlma_dot": ([P, P, ctypes.c_long, P, P], I),
         "dlma_profile_enable": ([I], I),
         "dlma_profile_reset": ([], I),
         "dlma_profile_read": ([I, P, P, P], I),
@@ -206,7 +209,7 @@ def dlma_solve(gauges, bs, xs=None, opts: SolveOpts | None = None, allow_notconv
 
 
 def dlma_lap_eigs(g: Gauge, nev: int, t0: int, nt: int, v0: torch.Tensor, tol: float = 1e-10,
-                  max_basis: int = 0, check_every: int = 0):
+                  max_basis: int = 0, check_every: int = 0, cheb_degree: int = 0):
     """Lowest nev modes of -lap(t), t = t0..t0+nt-1; v0: [nt][Z][Y][X][3] start vectors.
 
     Returns (V [nt][nev][Z][Y][X][3] complex128 on the GPU, evals numpy [nt][nev])."""
@@ -215,7 +218,7 @@ def dlma_lap_eigs(g: Gauge, nev: int, t0: int, nt: int, v0: torch.Tensor, tol: f
     T, Z, Y, X = g.dims
     V = torch.empty((nt, nev, Z, Y, X, 3), dtype=torch.complex128, device=v0.device)
     ev = np.zeros((nt, nev), dtype=np.float64)
-    o = EigOpts(tol, max_basis, check_every)
+    o = EigOpts(tol, max_basis, check_every, cheb_degree)
     _check(load_library().dlma_lap_eigs(g.h, int(nev), int(t0), int(nt), ctypes.c_void_p(v0.data_ptr()),
                                         ctypes.c_void_p(V.data_ptr()), ev.ctypes.data_as(ctypes.c_void_p),
                                         ctypes.byref(o), _stream()))
@@ -306,3 +309,63 @@ def noise_sources(xi: torch.Tensor, T: int, t0: int) -> torch.Tensor:
     for s in range(4):
         out[s::4, t0, ..., s, :] = xi.to(torch.complex128)
     return out
+
+
+def dlma_dot(a: torch.Tensor, b: torch.Tensor) -> complex:
+    """<a, b> = sum conj(a) b over all elements (complex128 GPU tensors of equal size)."""
+    import numpy as np
+    a = _dev(a)
+    b = _dev(b)
+    if a.numel() != b.numel():
+        raise ValueError("size mismatch")
+    out = np.zeros(2, dtype=np.float64)
+    _check(load_library().dlma_dot(ctypes.c_void_p(a.data_ptr()), ctypes.c_void_p(b.data_ptr()), int(a.numel()),
+                                   out.ctypes.data_as(ctypes.c_void_p), _stream()))
+    return complex(out[0], out[1])
+
+
+# ---------------------------------------------------------------- differentiation
+
+def kappa_of_m0(m0: float) -> float:
+    return 1.0 / (2.0 * m0 + 8.0)
+
+
+class DiracSolve(torch.autograd.Function):
+    """x = D(m0)^-1 b with the hand-written adjoint as backward.
+
+    forward:  dlma_solve (the configured precision; FP64 defect correction to tol)
+    backward: grad_b  = D^-dag grad_x = g5 D^-1 g5 grad_x  (dlma_solve with dagger = 1)
+              grad_m0 = -Re <grad_b, x>                      (dlma_dot), since dD/dm0 = 1
+    in PyTorch's convention for complex tensors (the gradient of a real loss L with
+    respect to z is dL/dRe z + i dL/dIm z)."""
+
+    @staticmethod
+    def forward(ctx, b, m0, gauge, opts):
+        kappa = kappa_of_m0(float(m0))
+        if gauge.kappa != kappa:
+            dlma_set_mass(gauge, kappa)
+        (x,), _ = dlma_solve([gauge], [b.detach()], opts=opts)
+        ctx.save_for_backward(x)
+        ctx.gauge = gauge
+        ctx.opts = opts
+        ctx.kappa = kappa
+        return x
+
+    @staticmethod
+    def backward(ctx, grad_x):
+        (x,) = ctx.saved_tensors
+        g = ctx.gauge
+        if g.kappa != ctx.kappa:
+            dlma_set_mass(g, ctx.kappa)
+        o = SolveOpts()
+        ctypes.memmove(ctypes.byref(o), ctypes.byref(ctx.opts), ctypes.sizeof(SolveOpts))
+        o.dagger = 1
+        o.use_x0 = 0
+        (gb,), _ = dlma_solve([g], [grad_x.contiguous()], opts=o)
+        gm = -dlma_dot(gb, x).real
+        return gb, torch.tensor(gm, dtype=torch.float64, device=x.device), None, None
+
+
+def dirac_solve(b: torch.Tensor, m0: torch.Tensor, gauge: Gauge, opts: SolveOpts | None = None) -> torch.Tensor:
+    """Differentiable solve; m0 is a 0-dim float64 tensor (bare mass, m0 = 1/(2 kappa) - 4)."""
+    return DiracSolve.apply(b, m0, gauge, opts or default_opts())

@@ -23,14 +23,17 @@ def cu(a):
     return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
 
 
-@pytest.mark.parametrize("dims,nev,seed,ts", [((4, 4, 4, 4), 4, 1, (0, 4)), ((16, 8, 8, 8), 16, 2, (3, 3))])
-def test_lap_eigs_matches_oracle(D, orc, dims, nev, seed, ts):
+@pytest.mark.parametrize("dims,nev,seed,ts,cheb", [((4, 4, 4, 4), 4, 1, (0, 4), 0), ((16, 8, 8, 8), 16, 2, (3, 3), -1),
+                                                   ((16, 8, 8, 8), 16, 2, (3, 3), 12)])
+def test_lap_eigs_matches_oracle(D, orc, dims, nev, seed, ts, cheb):
+    """Plain Lanczos (cheb = -1, and automatic on small timeslices) and the
+    Chebyshev-filtered variant (cheb = 12) against the oracle's plain Lanczos."""
     t0, nt = ts
-    print("lap_eigs", dims, nev, flush=True)
+    print("lap_eigs", dims, nev, cheb, flush=True)
     U = synth.gauge_field(dims, 0.3, seed)
     v0 = synth.gaussian_start(dims, nt, 100 + seed)
     g = D.dlma_load_gauge(cu(U), 0.120, 1.0)
-    Vg, ev = D.dlma_lap_eigs(g, nev, t0, nt, cu(v0), tol=1e-12)
+    Vg, ev = D.dlma_lap_eigs(g, nev, t0, nt, cu(v0), tol=1e-12, cheb_degree=cheb)
     Vg = Vg.cpu().numpy()
     for i in range(nt):
         t = t0 + i
