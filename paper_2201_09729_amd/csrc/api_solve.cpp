@@ -12,6 +12,8 @@
 //   reconstruction:     x_e += e,  x_o += A_oo^-1 (r_o - D_oe e)
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 
 #include "../../include/dlma.h"
@@ -50,7 +52,7 @@ struct Cfg {
     Buf part;                        // partial norms
     Buf dstate;                      // rr rr0 alpha beta tol2 abs2 nrm (double) | active iters (int)
     int hnsb, vnsb;                  // site blocks of stencil and vector kernels
-    double *rr, *rr0, *alpha, *beta, *tol2, *abs2, *nrm;
+    double *rr, *rr0, *alpha, *beta, *tol2, *abs2, *nrm, *enrm;
     int *active, *iters;
     std::vector<double> bnorm2, rnorm2, relres;
     std::vector<int> used, conv, hact, hiters;
@@ -62,10 +64,11 @@ template <int P> struct Tables {
     Buf dresid, dprep, drecon;                 // HopJob<P64>
     Buf dvnB, dclov, dconv64, dacc64;          // VecJob<P64>
     Buf dconv, dacc, dxpay;                    // VecJob<P>
+    Buf dvnE, dfinE;                           // |E|^2 (Schur source) jobs
     Buf dk1d, dk2d, dk1, dk2cg;                // HopJob<P>
     Buf dfinB, dfinR, dfinI, dfinAB;           // FinJob
     int nresid = 0, nprep = 0, nrecon = 0, nvnB = 0, nclov = 0, nconv = 0, nk = 0, nfin = 0;
-    int bresid = 0, bprep = 0, brecon = 0, bvnB = 0, bclov = 0, bconv = 0, bxpay = 0;
+    int bresid = 0, bprep = 0, brecon = 0, bvnB = 0, bclov = 0, bconv = 0, bxpay = 0, bvnE = 0;
     int bk1 = 0, bk2 = 0, bfin = 0;
     std::vector<FinJob> hfinI, hfinAB;  // kept for per-pass updates
 };
@@ -104,13 +107,14 @@ template <int P> int alloc_cfg(Cfg& c, hipStream_t s) {
     c.vnsb = ceil_div(Vh, VEC_BS);
     int pmax = std::max(2 * c.hnsb, 2 * c.vnsb);
     DLMA_TRY(c.part.allocate(sizeof(double) * n * pmax));
-    DLMA_TRY(c.dstate.allocate(sizeof(double) * 7 * n + sizeof(int) * 2 * n + 256));
+    DLMA_TRY(c.dstate.allocate(sizeof(double) * 8 * n + sizeof(int) * 2 * n + 256));
     double* d = c.dstate.as<double>();
     c.rr = d; c.rr0 = d + n; c.alpha = d + 2 * n; c.beta = d + 3 * n; c.tol2 = d + 4 * n; c.abs2 = d + 5 * n;
     c.nrm = d + 6 * n;
-    c.active = (int*)(d + 7 * n);
+    c.enrm = d + 7 * n;
+    c.active = (int*)(d + 8 * n);
     c.iters = c.active + n;
-    DLMA_HIP(hipMemsetAsync(c.dstate.p, 0, sizeof(double) * 7 * n + sizeof(int) * 2 * n, s));
+    DLMA_HIP(hipMemsetAsync(c.dstate.p, 0, sizeof(double) * 8 * n + sizeof(int) * 2 * n, s));
     c.bnorm2.assign(n, 0); c.rnorm2.assign(n, 0); c.relres.assign(n, 0);
     c.used.assign(n, 0); c.conv.assign(n, 0); c.hact.assign(n, 0); c.hiters.assign(n, 0);
     return DLMA_OK;
@@ -120,11 +124,11 @@ template <int P> float* nrm_of(const Buf& b) { return P == P16 ? b.as<float>() :
 
 template <int P> int build_tables(std::vector<Cfg>& cs, Tables<P>& t, int nb, hipStream_t s) {
     std::vector<HopJob<P64>> resid, prep, recon;
-    std::vector<VecJob<P64>> vnB, clov, conv64, acc64;
+    std::vector<VecJob<P64>> vnB, clov, conv64, acc64, vnE;
     std::vector<VecJob<P>> conv, acc, xpay;
     std::vector<HopJob<P>> k1d, k2d, k1, k2cg;
-    std::vector<FinJob> finB, finR, finI, finAB;
-    int rhs0B = 0, rhs0R = 0, rhs0I = 0, rhs0AB = 0;
+    std::vector<FinJob> finB, finR, finI, finAB, finE;
+    int rhs0B = 0, rhs0R = 0, rhs0I = 0, rhs0AB = 0, rhs0E = 0;
     for (auto& c : cs) {
         Gauge* g = c.g;
         int Vh = g->Vh, n = c.nrhs;
@@ -173,11 +177,16 @@ template <int P> int build_tables(std::vector<Cfg>& cs, Tables<P>& t, int nb, hi
             v.c = half_view<P>(c.xs.p, nrm_of<P>(c.nxs), Vh);
             v.part = c.part.as<double>();
             v.pstride = c.vnsb;
+            v.s = c.enrm;
             conv.push_back(v);
             VecJob<P64> v64 = {};
             v64.Vh = Vh; v64.nrhs = n; v64.nsb = c.vnsb;
             v64.a = half_view<P64>(c.E.p, nullptr, Vh);
             conv64.push_back(v64);
+            VecJob<P64> e64 = v64;
+            e64.part = c.part.as<double>();
+            e64.pstride = c.vnsb;
+            vnE.push_back(e64);
             VecJob<P> a = v;
             a.a = half_view<P>(c.xs.p, nrm_of<P>(c.nxs), Vh);
             acc.push_back(a);
@@ -224,12 +233,14 @@ template <int P> int build_tables(std::vector<Cfg>& cs, Tables<P>& t, int nb, hi
         f.active = c.active; f.iters = c.iters; f.out = c.nrm; f.maxit = 1 << 30;
         FinJob fb = f; fb.npart = 2 * c.vnsb; fb.rhs0 = rhs0B; rhs0B += n; finB.push_back(fb);
         FinJob fr = f; fr.npart = 2 * c.hnsb; fr.rhs0 = rhs0R; rhs0R += n; finR.push_back(fr);
-        FinJob fi = f; fi.npart = c.vnsb; fi.rhs0 = rhs0I; rhs0I += n; finI.push_back(fi);
+        FinJob fi = f; fi.npart = c.vnsb; fi.rhs0 = rhs0I; rhs0I += n; fi.out = c.enrm; finI.push_back(fi);
+        FinJob fe = f; fe.npart = c.vnsb; fe.rhs0 = rhs0E; rhs0E += n; fe.out = c.enrm; finE.push_back(fe);
         FinJob fa = f; fa.npart = c.hnsb; fa.rhs0 = rhs0AB; rhs0AB += n; finAB.push_back(fa);
     }
     t.bresid = assign_blocks(resid); t.bprep = assign_blocks(prep); t.brecon = assign_blocks(recon);
     t.bvnB = assign_vec_blocks(vnB); t.bclov = assign_vec_blocks(clov);
     t.bconv = assign_vec_blocks(conv); assign_vec_blocks(conv64); assign_vec_blocks(acc); assign_vec_blocks(acc64);
+    t.bvnE = assign_vec_blocks(vnE);
     t.bxpay = assign_vec_blocks(xpay);
     t.bk1 = assign_blocks(k1d); assign_blocks(k1);
     t.bk2 = assign_blocks(k2d); assign_blocks(k2cg);
@@ -241,6 +252,8 @@ template <int P> int build_tables(std::vector<Cfg>& cs, Tables<P>& t, int nb, hi
     DLMA_TRY(upload(t.dvnB, vnB, s)); DLMA_TRY(upload(t.dclov, clov, s)); DLMA_TRY(upload(t.dconv64, conv64, s));
     DLMA_TRY(upload(t.dacc64, acc64, s)); DLMA_TRY(upload(t.dconv, conv, s)); DLMA_TRY(upload(t.dacc, acc, s));
     DLMA_TRY(upload(t.dxpay, xpay, s));
+    DLMA_TRY(upload(t.dvnE, vnE, s));
+    DLMA_TRY(upload(t.dfinE, finE, s));
     DLMA_TRY(upload(t.dk1d, k1d, s)); DLMA_TRY(upload(t.dk2d, k2d, s)); DLMA_TRY(upload(t.dk1, k1, s));
     DLMA_TRY(upload(t.dk2cg, k2cg, s));
     DLMA_TRY(upload(t.dfinB, finB, s)); DLMA_TRY(upload(t.dfinR, finR, s));
@@ -261,7 +274,24 @@ template <int P> int hop_launch(const HopCfg& hc, const void* djobs, int njob, i
     return DLMA_OK;
 }
 
+// DLMA_LOG=2: after each launch of the inner iteration, count non-finite entries of the
+// vector it wrote (first configuration), to locate where a breakdown starts.
+template <int P> int debug_field(Cfg& c, const Buf& v, const Buf& nv, const char* what, hipStream_t s) {
+    Buf o;
+    DLMA_TRY(o.allocate(sizeof(double) * 4));
+    double init[4] = {0, 0, 1e300, 1e300};
+    DLMA_HIP(hipMemcpyAsync(o.p, init, sizeof(init), hipMemcpyHostToDevice, s));
+    DLMA_HIP(launch_check_field<P>(half_view<P>(v.p, nrm_of<P>(nv), c.g->Vh), c.g->Vh, c.nrhs, o.as<double>(), s));
+    double h[4];
+    DLMA_HIP(hipMemcpyAsync(h, o.p, sizeof(h), hipMemcpyDeviceToHost, s));
+    DLMA_HIP(hipStreamSynchronize(s));
+    std::fprintf(stderr, "[dlma]     %-3s non-finite %.0f, denormal-max sites %.0f, min site max %.3e, min scale %.3e\n", what,
+                 h[0], h[1], h[2], h[3]);
+    return DLMA_OK;
+}
+
 template <int P> int cg_iteration(std::vector<Cfg>& cs, Tables<P>& t, int nb, const std::vector<int>& nact, hipStream_t s) {
+    static const bool dbg = std::getenv("DLMA_LOG") && std::getenv("DLMA_LOG")[0] == '2';
     double b1 = 0, b2 = 0, b3 = 0;
     if (Profiler::get().on)
         for (size_t i = 0; i < cs.size(); ++i) {
@@ -269,11 +299,18 @@ template <int P> int cg_iteration(std::vector<Cfg>& cs, Tables<P>& t, int nb, co
             b2 += hop_bytes(P, K2, F_G5OUT | F_NORM, cs[i].g->Vh, nact[i]);
             b3 += hop_bytes(P, K2, F_CG, cs[i].g->Vh, nact[i]);
         }
+    Cfg& c0 = cs[0];
+    if (dbg) DLMA_TRY(debug_field<P>(c0, c0.p, c0.np, "p", s));
     DLMA_TRY(hop_launch<P>(HopCfg{K1, F_G5IN, nb}, t.dk1d.p, t.nk, t.bk1, KC_K1, b1, s));
+    if (dbg) DLMA_TRY(debug_field<P>(c0, c0.y, c0.ny, "y1", s));
     DLMA_TRY(hop_launch<P>(HopCfg{K2, F_G5OUT | F_NORM, nb}, t.dk2d.p, t.nk, t.bk2, KC_K2, b2, s));
+    if (dbg) DLMA_TRY(debug_field<P>(c0, c0.w, c0.nw, "w", s));
     DLMA_HIP(launch_finish(t.dfinAB.template as<FinJob>(), t.nfin, t.bfin, FIN_ALPHA, s));
     DLMA_TRY(hop_launch<P>(HopCfg{K1, 0, nb}, t.dk1.p, t.nk, t.bk1, KC_K1, b1, s));
+    if (dbg) DLMA_TRY(debug_field<P>(c0, c0.y, c0.ny, "y2", s));
     DLMA_TRY(hop_launch<P>(HopCfg{K2, F_CG, nb}, t.dk2cg.p, t.nk, t.bk2, KC_K2CG, b3, s));
+    if (dbg) DLMA_TRY(debug_field<P>(c0, c0.r, c0.nr, "r", s));
+    if (dbg) DLMA_TRY(debug_field<P>(c0, c0.xs, c0.nxs, "xs", s));
     DLMA_HIP(launch_finish(t.dfinAB.template as<FinJob>(), t.nfin, t.bfin, FIN_BETA, s));
     DLMA_HIP(launch_xpay<P>(t.dxpay.template as<VecJob<P>>(), t.nconv, t.bxpay, s));
     return DLMA_OK;
@@ -325,6 +362,7 @@ int solve_impl(std::vector<Cfg>& cs, const dlma_solve_opts& o, hipStream_t s) {
         DLMA_HIP(hipStreamSynchronize(s));
     }
     if (nan) return fail(DLMA_ENAN, "non-finite value in a source");
+    static const bool dlog = std::getenv("DLMA_LOG") != nullptr;
     double rel = o.inner_tol > 0 ? o.inner_tol : (P == P64 ? 0.0 : (P == P32 ? 1e-5 : (P == P16 ? 2e-3 : 1e-2)));
     int check = o.check_every > 0 ? o.check_every : 8;
 
@@ -355,10 +393,18 @@ int solve_impl(std::vector<Cfg>& cs, const dlma_solve_opts& o, hipStream_t s) {
             }
         }
         if (nan) return fail(DLMA_ENAN, "non-finite residual during the solve");
+        if (dlog) {
+            double mx = 0, mn = 1e300;
+            for (auto& c : cs)
+                for (double r : c.relres) { mx = std::max(mx, r); mn = std::min(mn, r); }
+            std::fprintf(stderr, "[dlma] pass %d: %d rhs left, relres %.3e .. %.3e\n", pass, nleft, mn, mx);
+        }
         if (nleft == 0 || pass >= o.max_outer || maxused >= o.maxiter) break;
         // Schur source and inner start
         DLMA_HIP(launch_clover_apply64(t.dclov.template as<VecJob<P64>>(), t.nclov, t.bclov, s));
         DLMA_HIP(launch_hop<P64>(HopCfg{K2, F_NOA, 1}, t.dprep.template as<HopJob<P64>>(), t.nprep, t.bprep, s));
+        DLMA_HIP(launch_norm<P64>(t.dvnE.template as<VecJob<P64>>(), t.nconv, t.bvnE, s));
+        DLMA_HIP(launch_finish(t.dfinE.template as<FinJob>(), t.nfin, t.bfin, FIN_NORM, s));
         DLMA_HIP(launch_conv_from64<P>(t.dconv.template as<VecJob<P>>(), t.nconv, t.bconv, t.dconv64.template as<VecJob<P64>>(), s));
         for (auto& c : cs) DLMA_HIP(hipMemcpyAsync(c.active, c.hact.data(), sizeof(int) * c.nrhs, hipMemcpyHostToDevice, s));
         for (auto& f : t.hfinI) { f.rel2 = rel * rel; f.maxit = std::max(1, o.maxiter - maxused); }
@@ -379,6 +425,13 @@ int solve_impl(std::vector<Cfg>& cs, const dlma_solve_opts& o, hipStream_t s) {
             for (int i = 0; i < ncfg; ++i) {
                 nact[i] = (int)std::count(cs[i].hact.begin(), cs[i].hact.end(), 1);
                 tot += nact[i];
+            }
+            if (dlog) {
+                std::vector<double> rr(cs[0].nrhs), rr0(cs[0].nrhs), al(cs[0].nrhs);
+                (void)hipMemcpy(rr.data(), cs[0].rr, sizeof(double) * cs[0].nrhs, hipMemcpyDeviceToHost);
+                (void)hipMemcpy(rr0.data(), cs[0].rr0, sizeof(double) * cs[0].nrhs, hipMemcpyDeviceToHost);
+                (void)hipMemcpy(al.data(), cs[0].alpha, sizeof(double) * cs[0].nrhs, hipMemcpyDeviceToHost);
+                std::fprintf(stderr, "[dlma]   inner: %d active; rhs0 |r|^2 %.3e / %.3e alpha %.3e\n", tot, rr[0], rr0[0], al[0]);
             }
             if (tot == 0) break;
         }

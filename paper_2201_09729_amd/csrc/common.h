@@ -136,6 +136,10 @@ template <int P, class R> HD void store_spinor(const SF<P>& f, int Vh, int r, in
         float m = 0.f;
 #pragma unroll
         for (int i = 0; i < 24; ++i) m = fmaxf(m, fabsf((float)s[i]));
+        // Sites whose largest component is below 1e-30 are stored as zero: the inner
+        // solver works on unit-norm vectors, so such sites are rounding residue at the
+        // edge of a propagating support, and 1/m would overflow near FP32's denormal range.
+        if (!(m >= 1e-30f)) m = 0.f;
         float inv = m > 0.f ? 1.0f / m : 0.f;
         f.nrm[(size_t)r * f.ns + cb] = m;
 #pragma unroll

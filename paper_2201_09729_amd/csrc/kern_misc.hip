@@ -423,7 +423,8 @@ hipError_t launch_clover_apply64(const VecJob<P64>* j, int njob, int nblocks, hi
     return hipGetLastError();
 }
 
-// a = b = P(src), c = 0 (inner CG start: r = p = bhat, x = 0); part = |src|^2
+// a = b = P(src / |src|), c = 0 (inner CG start on the unit-norm Schur source:
+// r = p = bhat/|bhat|, x = 0); s[r] = |src|^2; part = |a|^2 as stored
 template <int P> __global__ void __launch_bounds__(VEC_BS) k_conv_from64(const VecJob<P>* jobs, int njob, const VecJob<P64>* j64) {
     const VecJob<P>* J; int r, cb, sb;
     vec_locate(jobs, njob, J, r, cb, sb);
@@ -432,8 +433,10 @@ template <int P> __global__ void __launch_bounds__(VEC_BS) k_conv_from64(const V
     if (cb < J->Vh) {
         double x[24];
         load_spinor<P64, double>(S->a, J->Vh, r, cb, x);
+        double n2 = J->s[r];
+        double sc = n2 > 0 ? 1.0 / sqrt(n2) : 0.0;
         typename PT<P>::R y[24], z[24];
-        for (int i = 0; i < 24; ++i) { y[i] = (typename PT<P>::R)x[i]; z[i] = 0; nrm += x[i] * x[i]; }
+        for (int i = 0; i < 24; ++i) { y[i] = (typename PT<P>::R)(x[i] * sc); z[i] = 0; nrm += (double)y[i] * (double)y[i]; }
         store_spinor<P, typename PT<P>::R>(J->a, J->Vh, r, cb, y);
         store_spinor<P, typename PT<P>::R>(J->b, J->Vh, r, cb, y);
         store_spinor<P, typename PT<P>::R>(J->c, J->Vh, r, cb, z);
@@ -446,7 +449,7 @@ template <int P> hipError_t launch_conv_from64(const VecJob<P>* j, int njob, int
     return hipGetLastError();
 }
 
-// e64 = e (to FP64), x64 += e64
+// e64 = |bhat| e (back to the scale of the Schur source, FP64), x64 += e64
 template <int P> __global__ void __launch_bounds__(VEC_BS) k_accum_to64(const VecJob<P>* jobs, const VecJob<P64>* j64, int njob) {
     const VecJob<P>* J; int r, cb, sb;
     vec_locate(jobs, njob, J, r, cb, sb);
@@ -454,9 +457,10 @@ template <int P> __global__ void __launch_bounds__(VEC_BS) k_accum_to64(const Ve
     const VecJob<P64>* S = &j64[J - jobs];
     typename PT<P>::R e[24];
     load_spinor<P, typename PT<P>::R>(J->a, J->Vh, r, cb, e);
+    double sc = sqrt(J->s[r]);
     double ed[24], x[24];
     load_spinor<P64, double>(S->b, J->Vh, r, cb, x);
-    for (int i = 0; i < 24; ++i) { ed[i] = (double)e[i]; x[i] += ed[i]; }
+    for (int i = 0; i < 24; ++i) { ed[i] = (double)e[i] * sc; x[i] += ed[i]; }
     store_spinor<P64, double>(S->a, J->Vh, r, cb, ed);
     store_spinor<P64, double>(S->b, J->Vh, r, cb, x);
 }
@@ -526,12 +530,44 @@ template <int P> hipError_t launch_fill_random(SF<P> f, int Vh, int nrhs, unsign
     return hipGetLastError();
 }
 
+// diagnostics: out[0] += non-finite values, out[1] += sites whose largest |component| is
+// nonzero but below FLT_MIN, out[2] = min over sites of the nonzero largest |component|
+template <int P> __global__ void k_check_field(SF<P> f, int Vh, int nrhs, double* out) {
+    long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (long)Vh * nrhs) return;
+    int r = (int)(i / Vh);
+    int cb = (int)(i - (long)r * Vh);
+    typename PT<P>::R v[24];
+    load_spinor<P, typename PT<P>::R>(f, Vh, r, cb, v);
+    double bad = 0, m = 0;
+    for (int k = 0; k < 24; ++k) {
+        double x = (double)v[k];
+        if (!isfinite(x)) bad += 1;
+        else m = fmax(m, fabs(x));
+    }
+    if (bad > 0) atomicAdd(&out[0], bad);
+    if (m > 0 && m < 1.17549435e-38) atomicAdd(&out[1], 1.0);
+    if (m > 0) atomicMin((unsigned long long*)&out[2], (unsigned long long)__double_as_longlong(m));
+    if (P == P16 && f.nrm[(size_t)r * f.ns + cb] > 0) {
+        double nm = f.nrm[(size_t)r * f.ns + cb];
+        atomicMin((unsigned long long*)&out[3], (unsigned long long)__double_as_longlong(nm));
+    }
+    if (P == P16 && f.nrm[(size_t)r * f.ns + cb] != f.nrm[(size_t)r * f.ns + cb]) atomicAdd(&out[0], 1000.0);
+}
+
+template <int P> hipError_t launch_check_field(SF<P> f, int Vh, int nrhs, double* out, hipStream_t s) {
+    long n = (long)Vh * nrhs;
+    hipLaunchKernelGGL(k_check_field<P>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, f, Vh, nrhs, out);
+    return hipGetLastError();
+}
+
 #define DLMA_INST_VEC(P)                                                                                       \
     template hipError_t launch_conv_from64<P>(const VecJob<P>*, int, int, const VecJob<P64>*, hipStream_t); \
     template hipError_t launch_accum_to64<P>(const VecJob<P>*, const VecJob<P64>*, int, int, hipStream_t); \
     template hipError_t launch_xpay<P>(const VecJob<P>*, int, int, hipStream_t);                           \
     template hipError_t launch_norm<P>(const VecJob<P>*, int, int, hipStream_t);                           \
-    template hipError_t launch_fill_random<P>(SF<P>, int, int, unsigned, hipStream_t);
+    template hipError_t launch_fill_random<P>(SF<P>, int, int, unsigned, hipStream_t);          \
+    template hipError_t launch_check_field<P>(SF<P>, int, int, double*, hipStream_t);
 DLMA_INST_VEC(P64)
 DLMA_INST_VEC(P32)
 DLMA_INST_VEC(P16)
@@ -560,7 +596,9 @@ __global__ void __launch_bounds__(256) k_finish(const FinJob* jobs, int njob, in
         // start of an inner solve: |r|^2 = s; active unless already below target
         J.rr[r] = s;
         J.rr0[r] = s;
-        J.tol2[r] = fmax(J.rel2 * s, J.abs2[r]);
+        // targets refer to the unit-norm source: the absolute one is divided by |bhat|^2
+        double sc2 = J.out[r];
+        J.tol2[r] = fmax(J.rel2 * s, sc2 > 0 ? J.abs2[r] / sc2 : 0.0);
         J.iters[r] = 0;
         J.alpha[r] = 0;
         J.beta[r] = 0;

@@ -31,7 +31,7 @@ struct FinJob {
     int* active;
     int* iters;
     int maxit;
-    double* out;               // FIN_NORM: sums
+    double* out;               // FIN_NORM: sums; FIN_INIT: |bhat|^2 (scale of the unit-norm inner source)
 };
 enum FinMode { FIN_NORM = 0, FIN_ALPHA = 1, FIN_BETA = 2, FIN_INIT = 3 };
 
@@ -59,6 +59,7 @@ template <int P> hipError_t launch_accum_to64(const VecJob<P>* j, const VecJob<P
 template <int P> hipError_t launch_xpay(const VecJob<P>* j, int njob, int nblocks, hipStream_t s);       // b = a + s*b
 template <int P> hipError_t launch_norm(const VecJob<P>* j, int njob, int nblocks, hipStream_t s);       // part = |a|^2
 template <int P> hipError_t launch_fill_random(SF<P> f, int Vh, int nrhs, unsigned seed, hipStream_t s);
+template <int P> hipError_t launch_check_field(SF<P> f, int Vh, int nrhs, double* out, hipStream_t s);
 hipError_t launch_finish(const FinJob* j, int njob, int nblocks, int mode, hipStream_t s);
 
 }  // namespace dlma
