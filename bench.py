@@ -32,9 +32,15 @@ HBM_PEAK_GBS = 8000.0
 DIMS = (48, 24, 24, 24)
 EPS, SEED, KAPPA, CSW = 0.25, 6, 0.121, 1.2
 T0, NEV, NNOISE, TOL = 0, 32, 8, 1e-10
-KCLASS = {0: "hop_k1 (odd sites: A_oo^-1 D_oe, Dhat and Dhat^dag halves)",
-          1: "hop_k2 (even sites: A_ee - D_eo y, with |w|^2)",
-          2: "hop_k2_cg (even sites, fused r -= alpha q, x += alpha w, |r|^2)"}
+# stencil kernel classes timed by the library (include/dlma.h, dlma_profile_read) and the
+# template parameters (kind, flags) of the hop_kernel instantiation each one is
+KCLASS = {0: "hop_k1 (odd sites: y = A_oo^-1 D_oe x)",
+          1: "hop_k1_dag (odd sites: y = A_oo^-1 D_oe g5 x)",
+          2: "hop_k2_dag (even sites: w = A_ee x - g5 D_eo y, with |w|^2)",
+          3: "hop_k2_cg (even sites: q = A_ee w - D_eo y fused with r -= alpha q, x += alpha w, |r|^2)",
+          4: "hop_k2 (even sites: z = A_ee x - D_eo y)"}
+KTEMPLATE = {0: (0, 0), 1: (0, 1), 2: (1, 6), 3: (1, 8), 4: (1, 0)}
+PREC_ID = {"fp64": 0, "mix_fp32": 1, "mix_fp16": 2, "mix_bf16": 3}
 HOP_SOURCES = ["paper_2201_09729_amd/csrc/hop.h", "paper_2201_09729_amd/csrc/common.h",
                "paper_2201_09729_amd/csrc/hop_inst.h"]
 
@@ -61,7 +67,17 @@ def main():
     ap.add_argument("--no-variants", action="store_true", help="skip the FP64 / BF16 / single-RHS comparisons")
     ap.add_argument("--copy-probe", action="store_true", help="also run a plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--rhs-block", type=int, default=None,
+                    help="right-hand sides per thread in the stencil kernels (0 = autotune; default 2, 1 for fp64)")
+    ap.add_argument("--summarize", nargs=3, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR"),
+                    help="write profiles/ summaries from rocprofv3 output directories and exit")
+    ap.add_argument("--profile-cmd", default="", help="command line recorded in the summaries")
     args = ap.parse_args()
+    if args.rhs_block is None:
+        args.rhs_block = 1 if args.prec == "fp64" else 2
+    if args.summarize:
+        summarize(args)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build runs the whole hot path on a single MI355X "
               "(multi-GPU sharding is design only).", file=sys.stderr)
@@ -91,7 +107,7 @@ def main():
             b[s:nd:4, T0, ..., s, :] = V[0]
             b[nd + s:nd + nn:4, T0, ..., s, :] = xi
         dlma.dlma_project(g, T0, V[0], b[nd:nd + nn], 1, out=b[nd + nn:])  # (1 - box(t')) eta
-        opts = dlma.default_opts(tol=TOL, prec=prec)
+        opts = dlma.default_opts(tol=TOL, prec=prec, rhs_block=args.rhs_block)
         xs, st = dlma.dlma_solve([g], [b], xs=[x], opts=opts)
         if timed_stats is not None:
             timed_stats.append(st)
@@ -114,7 +130,7 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.time() - t_start
     dlma.dlma_profile_enable(False)
-    prof = {kc: dlma.dlma_profile_read(kc) for kc in (0, 1, 2)}
+    prof = {kc: dlma.dlma_profile_read(kc) for kc in KCLASS}
     ms_per_step = 1e3 * elapsed / args.steps
     value = nrhs * args.steps / elapsed
     st = stats[-1]
@@ -132,11 +148,12 @@ def main():
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                 "launches": n_l, "avg_launch_ms": round(ms_tot / max(n_l, 1), 4),
                 "alg_bytes_per_launch": round(by_tot / max(n_l, 1))}
-    tfile = os.path.join(ROOT, "profiles", "traffic_%s.json" % ("k1", "k2", "k2cg")[kc])
+    tfile = os.path.join(ROOT, "profiles", "traffic_%s.json" % KCLASS[kc].split()[0])
     if os.path.exists(tfile):
         with open(tfile) as fh:
             tr = json.load(fh)
-        if tr.get("source_sha") == sources_sha() and tr.get("precision") == args.prec:
+        if (tr.get("source_sha") == sources_sha() and tr.get("precision") == args.prec
+                and tr.get("rhs_block") == args.rhs_block):
             roofline["traffic"] = tr.get("traffic_bytes_per_launch")
             roofline["traffic_note"] = tr.get("note")
 
@@ -153,8 +170,9 @@ def main():
                       "step": "gauge load + clover + Laplacian modes on t' + sources + projection + batched solve"},
            "roofline": roofline,
            "iterations": {"inner_min": min(iters), "inner_max": max(iters), "outer_max": max(outer)},
-           "kernel_classes": {KCLASS[k]: {"launches": prof[k][0], "total_ms": round(prof[k][1], 3),
-                                          "GBps": round(prof[k][2] / max(prof[k][1], 1e-9) / 1e6, 1)} for k in prof}}
+           "kernel_classes": {KCLASS[k].split()[0]: {"launches": prof[k][0], "total_ms": round(prof[k][1], 3),
+                                                     "GBps": round(prof[k][2] / max(prof[k][1], 1e-9) / 1e6, 1)}
+                              for k in prof if prof[k][0] > 0}}
 
     # ------------------------------------------------------------ comparisons (outside the timed region)
     if not args.no_variants:
@@ -240,6 +258,79 @@ def main():
                                "clover_build_s": round(t_cl, 2)}
         log("cpu baseline: %.4g RHS/s (%d threads)" % (rate, oracle.num_threads()))
     print(json.dumps(out), flush=True)
+
+
+def summarize(args):
+    """rocprofv3 CSVs -> profiles/: per-kernel time summary and HBM traffic of the
+    stencil kernels, with FETCH_SIZE / WRITE_SIZE scaled by what the counters read for
+    the 1 GiB device copy of --copy-probe (kernel __amd_rocclr_copyBuffer)."""
+    import csv
+    import collections
+    trace, fetch, write = args.summarize
+    prec = args.prec
+
+    def find(d, suffix):
+        for f in sorted(os.listdir(d)):
+            if f.endswith(suffix):
+                return os.path.join(d, f)
+        raise FileNotFoundError(suffix)
+
+    stats = list(csv.DictReader(open(find(trace, "kernel_stats.csv"))))
+    counters = {}
+    copy_ref = {}
+    for name, d in (("FETCH_SIZE", fetch), ("WRITE_SIZE", write)):
+        agg = collections.defaultdict(list)
+        for row in csv.DictReader(open(find(d, "counter_collection.csv"))):
+            agg[row["Kernel_Name"]].append(float(row["Counter_Value"]))
+        counters[name] = agg
+        cp = [v for k, vs in agg.items() if "copyBuffer" in k for v in vs]
+        copy_ref[name] = max(cp) if cp else None
+    copy_kib = (1 << 30) / 1024.0  # the probe reads and writes 1 GiB
+    scale = {k: (copy_kib / v if v else None) for k, v in copy_ref.items()}
+    pid = PREC_ID[prec]
+
+    def hop_name(kc, nb):
+        kind, fl = KTEMPLATE[kc]
+        return "void dlma::hop_kernel<%d, %d, %d, %d, 128>(dlma::HopJob<%d> const*, int)" % (pid, nb, kind, fl, pid)
+
+    by_name = {r["Name"]: r for r in stats}
+    nb = args.rhs_block
+    lines = ["# Stencil kernels, 24^3x48 headline step (%s, %d right-hand sides per thread)" % (prec, nb), "",
+             "Command: `%s`" % args.profile_cmd, "",
+             "## rocprofv3 --kernel-trace --stats (top kernels)", "",
+             "| kernel | calls | total ms | avg ms |", "|---|---|---|---|"]
+    for r in stats[:14]:
+        lines.append("| `%s` | %s | %.2f | %.4f |" % (r["Name"][:110], r["Calls"], float(r["TotalDurationNs"]) / 1e6,
+                                                  float(r["AverageNs"]) / 1e6))
+    lines += ["", "## HBM traffic per dispatch (rocprofv3 --pmc, one counter per run)", "",
+              "Copy calibration (1 GiB device copy): FETCH_SIZE reads %.0f KiB (scale %.4f), WRITE_SIZE %.0f KiB (scale %.4f)."
+              % (copy_ref["FETCH_SIZE"] or 0, scale["FETCH_SIZE"] or 0, copy_ref["WRITE_SIZE"] or 0, scale["WRITE_SIZE"] or 0), "",
+              "| class | kernel | dispatches | FETCH KiB | WRITE KiB | scaled traffic GB | avg ms |", "|---|---|---|---|---|---|---|"]
+    out = {}
+    for kc in KCLASS:
+        nm = hop_name(kc, nb)
+        f = counters["FETCH_SIZE"].get(nm)
+        w = counters["WRITE_SIZE"].get(nm)
+        if not f or not w or nm not in by_name:
+            continue
+        fk, wk = sum(f) / len(f), sum(w) / len(w)
+        tb = (fk * scale["FETCH_SIZE"] + wk * scale["WRITE_SIZE"]) * 1024.0
+        avg_ms = float(by_name[nm]["AverageNs"]) / 1e6
+        lines.append("| %s | `hop_kernel<%d,%d,%d,%d>` | %d | %.0f | %.0f | %.3f | %.4f |"
+                     % (KCLASS[kc].split()[0], pid, nb, KTEMPLATE[kc][0], KTEMPLATE[kc][1], len(f), fk, wk, tb / 1e9, avg_ms))
+        out[kc] = {"kernel": nm, "precision": prec, "rhs_block": nb, "source_sha": sources_sha(),
+                   "fetch_kib_per_dispatch": fk, "write_kib_per_dispatch": wk, "copy_scale": scale,
+                   "traffic_bytes_per_launch": tb, "avg_ms_rocprof": avg_ms,
+                   "note": "FETCH_SIZE and WRITE_SIZE per dispatch scaled by the 1 GiB copy calibration",
+                   "command": args.profile_cmd}
+    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    tag = "24x48_%s" % prec
+    with open(os.path.join(ROOT, "profiles", "hop_kernels_%s.md" % tag), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    for kc, d in out.items():
+        with open(os.path.join(ROOT, "profiles", "traffic_%s.json" % KCLASS[kc].split()[0]), "w") as fh:
+            json.dump(d, fh, indent=1)
+    print("\n".join(lines))
 
 
 if __name__ == "__main__":

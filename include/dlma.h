@@ -223,8 +223,12 @@ int dlma_dot(const void* a, const void* b, long n, double* out, void* stream);
  * Kernel timing: while enabled, the stencil launches of dlma_solve and
  * dlma_bench_schur are bracketed with hipEvents on the launch stream and the
  * durations accumulated per kernel class:
- *   0 = hop_k1 (odd sites: A_oo^-1 D_oe), 1 = hop_k2 (even sites: A_ee and D_eo,
- *   plain or with the fused norm), 2 = hop_k2_cg (even sites, fused CG update).
+ *   0 = hop_k1      odd sites, y = A_oo^-1 D_oe x                 (Dhat)
+ *   1 = hop_k1_dag  odd sites, y = A_oo^-1 D_oe g5 x              (Dhat^dag)
+ *   2 = hop_k2_dag  even sites, w = A_ee x - g5 D_eo y, with |w|^2  (Dhat^dag)
+ *   3 = hop_k2_cg   even sites, q = A_ee w - D_eo y fused with r -= alpha q,
+ *                   x += alpha w and |r|^2 (CG update, q not stored)
+ *   4 = hop_k2      even sites, z = A_ee x - D_eo y               (benchmark only)
  * dlma_profile_read returns the launch count, total milliseconds and total
  * algorithmic bytes (compulsory HBM traffic of the launches, summed) per class.
  */

@@ -122,7 +122,7 @@ template <int P> int alloc_cfg(Cfg& c, hipStream_t s) {
 
 template <int P> float* nrm_of(const Buf& b) { return P == P16 ? b.as<float>() : nullptr; }
 
-template <int P> int build_tables(std::vector<Cfg>& cs, Tables<P>& t, int nb, hipStream_t s) {
+template <int P> int build_tables(std::vector<Cfg>& cs, Tables<P>& t, int nb, int sg_in, int sg64, hipStream_t s) {
     std::vector<HopJob<P64>> resid, prep, recon;
     std::vector<VecJob<P64>> vnB, clov, conv64, acc64, vnE;
     std::vector<VecJob<P>> conv, acc, xpay;
@@ -135,6 +135,7 @@ template <int P> int build_tables(std::vector<Cfg>& cs, Tables<P>& t, int nb, hi
         const double2* U64 = g->U64.as<double2>();
         for (int par = 0; par < 2; ++par) {
             HopJob<P64> j = hop_job<P64>(g, par, n, 1);
+            j.sg = sg64;
             j.U = U64;
             j.C = g->Cl64[par].as<double2>();
             j.b = full_view(c.B.p, Vh, par);
@@ -162,6 +163,7 @@ template <int P> int build_tables(std::vector<Cfg>& cs, Tables<P>& t, int nb, hi
         }
         {   // E = R_e + 1/2 H T
             HopJob<P64> j = hop_job<P64>(g, 0, n, 1);
+            j.sg = sg64;
             j.U = U64;
             j.x = full_view(c.R.p, Vh, 0);
             j.in = half_view<P64>(c.T.p, nullptr, Vh);
@@ -202,6 +204,7 @@ template <int P> int build_tables(std::vector<Cfg>& cs, Tables<P>& t, int nb, hi
         }
         {   // X_o += A_oo^-1 (R_o + 1/2 H E)
             HopJob<P64> j = hop_job<P64>(g, 1, n, 1);
+            j.sg = sg64;
             j.U = U64;
             j.C = g->Ci64.as<double2>();
             j.in = half_view<P64>(c.E.p, nullptr, Vh);
@@ -218,9 +221,9 @@ template <int P> int build_tables(std::vector<Cfg>& cs, Tables<P>& t, int nb, hi
             SF<P> vw = half_view<P>(c.w.p, nrm_of<P>(c.nw), Vh), vr = half_view<P>(c.r.p, nrm_of<P>(c.nr), Vh);
             SF<P> vx = half_view<P>(c.xs.p, nrm_of<P>(c.nxs), Vh);
             HopJob<P> j1 = hop_job<P>(g, 1, n, nb);
-            j1.U = U; j1.C = Cio; j1.ch = -0.5; j1.active = c.active;
+            j1.U = U; j1.C = Cio; j1.ch = -0.5; j1.active = c.active; j1.sg = sg_in;
             HopJob<P> j2 = hop_job<P>(g, 0, n, nb);
-            j2.U = U; j2.C = Cee; j2.ca = 1.0; j2.ch = 0.5; j2.active = c.active;
+            j2.U = U; j2.C = Cee; j2.ca = 1.0; j2.ch = 0.5; j2.active = c.active; j2.sg = sg_in;
             j2.part = c.part.as<double>(); j2.pstride = c.hnsb;
             HopJob<P> a = j1; a.in = vp; a.out = vy; k1d.push_back(a);
             HopJob<P> b = j2; b.x = vp; b.in = vy; b.out = vw; k2d.push_back(b);
@@ -301,9 +304,9 @@ template <int P> int cg_iteration(std::vector<Cfg>& cs, Tables<P>& t, int nb, co
         }
     Cfg& c0 = cs[0];
     if (dbg) DLMA_TRY(debug_field<P>(c0, c0.p, c0.np, "p", s));
-    DLMA_TRY(hop_launch<P>(HopCfg{K1, F_G5IN, nb}, t.dk1d.p, t.nk, t.bk1, KC_K1, b1, s));
+    DLMA_TRY(hop_launch<P>(HopCfg{K1, F_G5IN, nb}, t.dk1d.p, t.nk, t.bk1, KC_K1DAG, b1, s));
     if (dbg) DLMA_TRY(debug_field<P>(c0, c0.y, c0.ny, "y1", s));
-    DLMA_TRY(hop_launch<P>(HopCfg{K2, F_G5OUT | F_NORM, nb}, t.dk2d.p, t.nk, t.bk2, KC_K2, b2, s));
+    DLMA_TRY(hop_launch<P>(HopCfg{K2, F_G5OUT | F_NORM, nb}, t.dk2d.p, t.nk, t.bk2, KC_K2DAGN, b2, s));
     if (dbg) DLMA_TRY(debug_field<P>(c0, c0.w, c0.nw, "w", s));
     DLMA_HIP(launch_finish(t.dfinAB.template as<FinJob>(), t.nfin, t.bfin, FIN_ALPHA, s));
     DLMA_TRY(hop_launch<P>(HopCfg{K1, 0, nb}, t.dk1.p, t.nk, t.bk1, KC_K1, b1, s));
@@ -316,7 +319,8 @@ template <int P> int cg_iteration(std::vector<Cfg>& cs, Tables<P>& t, int nb, co
     return DLMA_OK;
 }
 
-template <int P> int tune_nb(Gauge* g, int nrhs, SF<P> vp, SF<P> vy, SF<P> vw, hipStream_t s);
+struct Tune { int nb, sg; };
+template <int P> int tune_hop(Gauge* g, int nrhs, int fixed_nb, SF<P> vp, SF<P> vy, SF<P> vw, Tune& out, hipStream_t s);
 
 template <int P>
 int solve_impl(std::vector<Cfg>& cs, const dlma_solve_opts& o, hipStream_t s) {
@@ -324,21 +328,25 @@ int solve_impl(std::vector<Cfg>& cs, const dlma_solve_opts& o, hipStream_t s) {
         DLMA_TRY(gauge_prepare(c.g, P, s));
         DLMA_TRY(alloc_cfg<P>(c, s));
     }
-    int nb = o.rhs_block;
-    if (nb != 0 && nb != 1 && nb != 2 && nb != 4) return fail(DLMA_EINVAL, "rhs_block must be 0, 1, 2 or 4");
-    if (nb == 0) {
-        // tune on the largest configuration
-        size_t big = 0;
-        for (size_t i = 1; i < cs.size(); ++i)
-            if ((long)cs[i].g->Vh * cs[i].nrhs > (long)cs[big].g->Vh * cs[big].nrhs) big = i;
+    if (o.rhs_block != 0 && o.rhs_block != 1 && o.rhs_block != 2 && o.rhs_block != 4)
+        return fail(DLMA_EINVAL, "rhs_block must be 0, 1, 2 or 4");
+    // launch shapes, tuned on the largest configuration: inner stencils (precision P) and
+    // the FP64 outer stencils (one right-hand side per thread)
+    size_t big = 0;
+    for (size_t i = 1; i < cs.size(); ++i)
+        if ((long)cs[i].g->Vh * cs[i].nrhs > (long)cs[big].g->Vh * cs[big].nrhs) big = i;
+    Tune tin{1, 0}, t64{1, 0};
+    {
         Cfg& c = cs[big];
         int Vh = c.g->Vh;
-        nb = tune_nb<P>(c.g, c.nrhs, half_view<P>(c.p.p, nrm_of<P>(c.np), Vh), half_view<P>(c.y.p, nrm_of<P>(c.ny), Vh),
-                        half_view<P>(c.w.p, nrm_of<P>(c.nw), Vh), s);
-        if (nb < 0) return nb;
+        DLMA_TRY(tune_hop<P>(c.g, c.nrhs, o.rhs_block, half_view<P>(c.p.p, nrm_of<P>(c.np), Vh),
+                             half_view<P>(c.y.p, nrm_of<P>(c.ny), Vh), half_view<P>(c.w.p, nrm_of<P>(c.nw), Vh), tin, s));
+        DLMA_TRY(tune_hop<P64>(c.g, c.nrhs, 1, half_view<P64>(c.E.p, nullptr, Vh), half_view<P64>(c.T.p, nullptr, Vh),
+                               full_view(c.R.p, Vh, 0), t64, s));
     }
+    const int nb = tin.nb;
     Tables<P> t;
-    DLMA_TRY(build_tables<P>(cs, t, nb, s));
+    DLMA_TRY(build_tables<P>(cs, t, nb, tin.sg, t64.sg, s));
     int ncfg = (int)cs.size();
     // load sources and start vectors
     for (auto& c : cs) {
@@ -448,59 +456,85 @@ int solve_impl(std::vector<Cfg>& cs, const dlma_solve_opts& o, hipStream_t s) {
     return DLMA_OK;
 }
 
-// Autotune the right-hand sides per thread: time the Schur pair K1+K2 for each
-// candidate on the caller's buffers (p filled with random numbers).  Cached per
-// gauge handle, precision and number of right-hand sides.
-template <int P> int tune_nb(Gauge* g, int nrhs, SF<P> vp, SF<P> vy, SF<P> vw, hipStream_t s) {
-    auto key = std::make_pair(P, nrhs);
-    auto it = g->tuned.find(key);
-    if (it != g->tuned.end()) return it->second;
+// Autotuner of the stencil launch shape: right-hand sides per thread (nb; fixed
+// when the caller gives one) and right-hand-side groups per super-group (sg, the
+// block order of hop_kernel).  Each candidate times the Schur pair K1 + K2 on the
+// caller's buffers (vp filled with random numbers): one warm-up and five timed
+// repetitions, median.  Results are cached per lattice, precision, right-hand
+// sides and fixed nb for the life of the process.
+template <int P> int tune_hop(Gauge* g, int nrhs, int fixed_nb, SF<P> vp, SF<P> vy, SF<P> vw, Tune& out, hipStream_t s) {
+    const int key = P * 16 + fixed_nb;
+    if (int v = tuned_lookup(g->dims, key, nrhs)) {
+        out.nb = v & 255;
+        out.sg = v >> 8;
+        return DLMA_OK;
+    }
     DLMA_HIP(launch_fill_random<P>(vp, g->Vh, nrhs, 7u, s));
-    int best = 1;
+    Tune best{1, 0};
     float bt = 1e30f;
-    const int cand[3] = {1, 2, 4};
     hipEvent_t e0, e1;
     DLMA_HIP(hipEventCreate(&e0));
     DLMA_HIP(hipEventCreate(&e1));
-    for (int nb : cand) {
-        if (nb > 1 && nrhs < nb) continue;
-        // all right-hand sides active (active = nullptr)
-        std::vector<HopJob<P>> k1v, k2v;
-        HopJob<P> j1 = hop_job<P>(g, 1, nrhs, nb);
-        j1.U = (const typename PT<P>::S*)gauge_links(g, P);
-        j1.C = (const typename PT<P>::S*)gauge_clover_oo_inv(g, P);
-        j1.ch = -0.5;
-        j1.in = vp;
-        j1.out = vy;
-        HopJob<P> j2 = hop_job<P>(g, 0, nrhs, nb);
-        j2.U = j1.U;
-        j2.C = (const typename PT<P>::S*)gauge_clover_ee(g, P);
-        j2.ca = 1.0; j2.ch = 0.5;
-        j2.x = vp; j2.in = vy;
-        j2.out = vw;
-        k1v.push_back(j1); k2v.push_back(j2);
-        int b1 = assign_blocks(k1v), b2 = assign_blocks(k2v);
-        Buf d1, d2;
-        DLMA_TRY(upload(d1, k1v, s));
-        DLMA_TRY(upload(d2, k2v, s));
-        float best_t = 1e30f;
-        for (int rep = 0; rep < 3; ++rep) {
-            DLMA_HIP(hipEventRecord(e0, s));
-            DLMA_HIP(launch_hop<P>(HopCfg{K1, 0, nb}, d1.as<HopJob<P>>(), 1, b1, s));
-            DLMA_HIP(launch_hop<P>(HopCfg{K2, 0, nb}, d2.as<HopJob<P>>(), 1, b2, s));
-            DLMA_HIP(hipEventRecord(e1, s));
-            DLMA_HIP(hipEventSynchronize(e1));
-            float ms = 0;
-            DLMA_HIP(hipEventElapsedTime(&ms, e0, e1));
-            if (rep > 0) best_t = std::min(best_t, ms);
+    const int nbs[3] = {1, 2, 4};
+    const int sgs[7] = {1, 2, 4, 8, 16, 32, 0};
+    for (int nb : nbs) {
+        if (fixed_nb && nb != fixed_nb) continue;
+        if (!fixed_nb && nb > 1 && nrhs < nb) continue;
+        const int G = ceil_div(nrhs, nb);
+        for (int sg : sgs) {
+            if (sg >= G) continue;  // same order as sg = 0 (all groups)
+            std::vector<HopJob<P>> k1v, k2v;
+            HopJob<P> j1 = hop_job<P>(g, 1, nrhs, nb);
+            j1.U = (const typename PT<P>::S*)gauge_links(g, P);
+            j1.C = (const typename PT<P>::S*)gauge_clover_oo_inv(g, P);
+            j1.ch = -0.5;
+            j1.in = vp;
+            j1.out = vy;
+            j1.sg = sg;
+            HopJob<P> j2 = hop_job<P>(g, 0, nrhs, nb);
+            j2.U = j1.U;
+            j2.C = (const typename PT<P>::S*)gauge_clover_ee(g, P);
+            j2.ca = 1.0;
+            j2.ch = 0.5;
+            j2.x = vp;
+            j2.in = vy;
+            j2.out = vw;
+            j2.sg = sg;
+            k1v.push_back(j1);
+            k2v.push_back(j2);
+            int b1 = assign_blocks(k1v), b2 = assign_blocks(k2v);
+            Buf d1, d2;
+            DLMA_TRY(upload(d1, k1v, s));
+            DLMA_TRY(upload(d2, k2v, s));
+            std::vector<float> ts;
+            for (int rep = 0; rep < 6; ++rep) {
+                DLMA_HIP(hipEventRecord(e0, s));
+                DLMA_HIP(launch_hop<P>(HopCfg{K1, 0, nb}, d1.as<HopJob<P>>(), 1, b1, s));
+                DLMA_HIP(launch_hop<P>(HopCfg{K2, 0, nb}, d2.as<HopJob<P>>(), 1, b2, s));
+                DLMA_HIP(hipEventRecord(e1, s));
+                DLMA_HIP(hipEventSynchronize(e1));
+                float ms = 0;
+                DLMA_HIP(hipEventElapsedTime(&ms, e0, e1));
+                if (rep > 0) ts.push_back(ms);
+            }
+            DLMA_HIP(hipStreamSynchronize(s));
+            std::sort(ts.begin(), ts.end());
+            float med = ts[ts.size() / 2];
+            static const bool tlog = std::getenv("DLMA_LOG") != nullptr;
+            if (tlog)
+                std::fprintf(stderr, "[dlma] tune prec %d nrhs %d Vh %d: nb %d sg %d -> %.3f ms (K1+K2)\n", P, nrhs, g->Vh, nb, sg,
+                             med);
+            if (med < bt) {
+                bt = med;
+                best = Tune{nb, sg};
+            }
         }
-        DLMA_HIP(hipStreamSynchronize(s));
-        if (best_t < bt) { bt = best_t; best = nb; }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    g->tuned[key] = best;
-    return best;
+    tuned_store(g->dims, key, nrhs, best.nb | (best.sg << 8));
+    out = best;
+    return DLMA_OK;
 }
 
 }  // namespace
@@ -587,18 +621,19 @@ int bench_impl(Gauge* g, int nrhs, int nb, int napply, double* ms_out, double* b
     SF<P> va = half_view<P>(a.p, nrm_of<P>(na), Vh), vy = half_view<P>(y.p, nrm_of<P>(ny), Vh),
           vw = half_view<P>(w.p, nrm_of<P>(nw), Vh);
     DLMA_HIP(launch_fill_random<P>(va, Vh, nrhs, 11u, s));
-    if (nb == 0) {
-        nb = tune_nb<P>(g, nrhs, va, vy, vw, s);
-        if (nb < 0) return nb;
-        DLMA_HIP(launch_fill_random<P>(va, Vh, nrhs, 11u, s));
-    }
+    Tune tn{nb ? nb : 1, 0};
+    DLMA_TRY(tune_hop<P>(g, nrhs, nb, va, vy, vw, tn, s));
+    nb = tn.nb;
+    DLMA_HIP(launch_fill_random<P>(va, Vh, nrhs, 11u, s));
     // alternate Dhat and Dhat^dag: a -> w -> a
     std::vector<HopJob<P>> j1f, j2f, j1b, j2b;
     HopJob<P> j1 = hop_job<P>(g, 1, nrhs, nb);
     j1.U = (const typename PT<P>::S*)gauge_links(g, P);
     j1.C = (const typename PT<P>::S*)gauge_clover_oo_inv(g, P);
     j1.ch = -0.5;
+    j1.sg = tn.sg;
     HopJob<P> j2 = hop_job<P>(g, 0, nrhs, nb);
+    j2.sg = tn.sg;
     j2.U = j1.U;
     j2.C = (const typename PT<P>::S*)gauge_clover_ee(g, P);
     j2.ca = 1.0;
@@ -615,7 +650,7 @@ int bench_impl(Gauge* g, int nrhs, int nb, int napply, double* ms_out, double* b
     double by1 = hop_bytes(P, K1, 0, Vh, nrhs), by2 = hop_bytes(P, K2, 0, Vh, nrhs);
     auto run = [&](int k) -> int {
         bool fwd = (k & 1) == 0;
-        DLMA_TRY(hop_launch<P>(HopCfg{K1, fwd ? 0 : F_G5IN, nb}, (fwd ? d1f : d1b).p, 1, b1, KC_K1, by1, s));
+        DLMA_TRY(hop_launch<P>(HopCfg{K1, fwd ? 0 : F_G5IN, nb}, (fwd ? d1f : d1b).p, 1, b1, fwd ? KC_K1 : KC_K1DAG, by1, s));
         DLMA_TRY(hop_launch<P>(HopCfg{K2, fwd ? 0 : F_G5OUT, nb}, (fwd ? d2f : d2b).p, 1, b2, KC_K2, by2, s));
         return DLMA_OK;
     };

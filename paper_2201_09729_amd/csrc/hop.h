@@ -42,7 +42,7 @@ template <int P> struct HopJob {
     int nsb;    // site blocks = ceil(Vh / BS)
     int nsbp;   // nsb rounded up to a multiple of 8
     int blk0;   // first workgroup of this job (multiple of 8)
-    int xmap;   // 0: each XCD sweeps a contiguous range of site blocks; 1: site blocks dealt round-robin
+    int sg;     // right-hand-side groups per super-group (see the block decode); 0 = all groups
     const typename PT<P>::S* U;  // links, all parities
     const typename PT<P>::S* C;  // clover blocks of the output parity (A or A^-1)
     SF<P> in, x, b, out, r, xs;
@@ -250,12 +250,22 @@ __global__ void __launch_bounds__(BS) hop_kernel(const HopJob<P>* __restrict__ j
     int jb = 0;
     while (jb + 1 < njob && bid >= jobs[jb + 1].blk0) ++jb;
     const HopJob<P>& J = jobs[jb];
+    // Block decode.  Workgroups are dealt round-robin to the 8 XCDs, so XCD (lb & 7)
+    // runs the sequence k = lb >> 3.  Each XCD owns the contiguous site blocks
+    // [xcd * CS, (xcd+1) * CS), CS = nsbp/8.  Its sequence runs over super-groups of
+    // SG right-hand-side groups; within one super-group it sweeps its site blocks in
+    // order with the SG groups innermost.  Small SG keeps the neighbour spinors of the
+    // sweep (the +-z and +-t halos) in the XCD's L2 until they are reused; large SG
+    // reuses each site block's links and clover across more groups.
     const int lb = bid - J.blk0;
     const int k = lb >> 3;
-    const int gi = k % J.G;
-    // XCD (lb & 7) owns site blocks [xcd * nsbp/8, (xcd+1) * nsbp/8) in the contiguous
-    // mapping, so neighbouring site blocks (the +-x,y,z halos) are reused from its L2.
-    const int sb = J.xmap ? (k / J.G) * 8 + (lb & 7) : (lb & 7) * (J.nsbp >> 3) + k / J.G;
+    const int CS = J.nsbp >> 3;
+    const int SG = (J.sg > 0 && J.sg < J.G) ? J.sg : J.G;
+    const int si = k / (CS * SG);
+    const int kk = k - si * CS * SG;
+    const int sge = min(SG, J.G - si * SG);
+    const int gi = si * SG + kk % sge;
+    const int sb = (lb & 7) * CS + kk / sge;
     if (sb >= J.nsb) return;  // whole block: padding of the XCD decomposition
     const int cb = sb * BS + (int)threadIdx.x;
     const int g0 = gi * NB;

@@ -99,6 +99,22 @@ const void* gauge_links(const Gauge* g, int prec) { return prec == P64 ? g->U64.
 const void* gauge_clover_ee(const Gauge* g, int prec) { return prec == P64 ? g->Cl64[0].p : g->Cee[prec].p; }
 const void* gauge_clover_oo_inv(const Gauge* g, int prec) { return prec == P64 ? g->Ci64.p : g->Cio[prec].p; }
 
+// ---------------------------------------------------------------- tuning cache
+
+static std::mutex g_tune_m;
+static std::map<std::vector<int>, int> g_tuned;
+
+int tuned_lookup(const int dims[4], int prec, int nrhs) {
+    std::lock_guard<std::mutex> l(g_tune_m);
+    auto it = g_tuned.find({dims[0], dims[1], dims[2], dims[3], prec, nrhs});
+    return it == g_tuned.end() ? 0 : it->second;
+}
+
+void tuned_store(const int dims[4], int prec, int nrhs, int nb) {
+    std::lock_guard<std::mutex> l(g_tune_m);
+    g_tuned[{dims[0], dims[1], dims[2], dims[3], prec, nrhs}] = nb;
+}
+
 // ---------------------------------------------------------------- byte model
 
 double hop_bytes(int prec, int kind, int flags, int Vh, int n) {

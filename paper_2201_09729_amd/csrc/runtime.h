@@ -85,8 +85,11 @@ struct Gauge {
     Buf Cee[4];     // A_ee in that precision
     Buf Cio[4];     // A_oo^-1 in that precision
     bool lo_ready[4] = {false, false, false, false};
-    std::map<std::pair<int, int>, int> tuned;  // (precision, nrhs) -> right-hand sides per thread
 };
+
+// Autotuner results, shared by all handles: (T, Z, Y, X, precision, nrhs) -> right-hand sides per thread
+int tuned_lookup(const int dims[4], int prec, int nrhs);
+void tuned_store(const int dims[4], int prec, int nrhs, int nb);
 
 int gauge_prepare(Gauge* g, int prec, hipStream_t s);  // low-precision copies on demand
 const void* gauge_links(const Gauge* g, int prec);
@@ -152,7 +155,7 @@ double hop_bytes(int prec, int kind, int flags, int Vh, int nrhs_active);
 
 // ---------------------------------------------------------------- timing registry
 
-enum KClass { KC_K1 = 0, KC_K2 = 1, KC_K2CG = 2, KC_N = 3 };
+enum KClass { KC_K1 = 0, KC_K1DAG = 1, KC_K2DAGN = 2, KC_K2CG = 3, KC_K2 = 4, KC_N = 5 };
 
 struct Profiler {
     static Profiler& get();
