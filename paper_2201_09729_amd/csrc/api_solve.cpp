@@ -103,7 +103,7 @@ template <int P> int alloc_cfg(Cfg& c, hipStream_t s) {
         DLMA_TRY(c.nxs.allocate(nb));
         DLMA_TRY(c.ny.allocate(nb));
     }
-    c.hnsb = ceil_div(Vh, HOP_BS);
+    c.hnsb = hop_nsb(g->geo);
     c.vnsb = ceil_div(Vh, VEC_BS);
     int pmax = std::max(2 * c.hnsb, 2 * c.vnsb);
     DLMA_TRY(c.part.allocate(sizeof(double) * n * pmax));

@@ -39,8 +39,10 @@ template <int P> struct HopJob {
     int par;    // output parity
     int nrhs;   // right-hand sides
     int G;      // right-hand-side groups = ceil(nrhs / NB)
-    int nsb;    // site blocks = ceil(Vh / BS)
-    int nsbp;   // nsb rounded up to a multiple of 8
+    int vt;     // sites of one parity on one timeslice (Z*Y*X/2)
+    int nbt;    // site blocks per timeslice = ceil(vt / BS); a block never spans two timeslices
+    int nsb;    // site blocks = T * nbt
+    int nxb;    // site blocks per XCD = ceil(T/8) * nbt
     int blk0;   // first workgroup of this job (multiple of 8)
     int sg;     // right-hand-side groups per super-group (see the block decode); 0 = all groups
     const typename PT<P>::S* U;  // links, all parities
@@ -51,6 +53,7 @@ template <int P> struct HopJob {
     double* part;         // partial squared norms (F_NORM / F_CG): part[r * pstride + site block]
     int pstride;
     double ca, cb, ch;
+    float one;  // 1.0f, opaque to the compiler (keeps FP16 widening inside FMAs)
 };
 
 template <int P, class R> HD void load_half_spinor(const SF<P>& f, int Vh, int r, int cb, int blk, R s[12]) {
@@ -226,6 +229,12 @@ HD void hop_site(const HopJob<P>& J, int cb, int g0, double (&nrm2)[NB]) {
     }
 }
 
+}  // namespace dlma
+
+#include "hop16.h"
+
+namespace dlma {
+
 // ---------------------------------------------------------------- block reduction
 
 // Sum of v over the block (BS threads, wave64), result valid in thread 0.
@@ -244,6 +253,13 @@ template <int BS> __device__ __forceinline__ double block_sum(double v, double* 
     return s;
 }
 
+// The per-site body for precision P: FP16 fields take the raw-word path of hop16.h.
+template <int P, int NB, int KIND, int FL>
+HD void site_body(const HopJob<P>& J, int cb, int g0, double (&nrm2)[NB]) {
+    if constexpr (P == P16) hop_site16<NB, KIND, FL>(J, cb, g0, nrm2);
+    else hop_site<P, NB, KIND, FL>(J, cb, g0, nrm2);
+}
+
 template <int P, int NB, int KIND, int FL, int BS>
 __global__ void __launch_bounds__(BS) hop_kernel(const HopJob<P>* __restrict__ jobs, int njob) {
     const int bid = blockIdx.x;
@@ -251,27 +267,50 @@ __global__ void __launch_bounds__(BS) hop_kernel(const HopJob<P>* __restrict__ j
     while (jb + 1 < njob && bid >= jobs[jb + 1].blk0) ++jb;
     const HopJob<P>& J = jobs[jb];
     // Block decode.  Workgroups are dealt round-robin to the 8 XCDs, so XCD (lb & 7)
-    // runs the sequence k = lb >> 3.  Each XCD owns the contiguous site blocks
-    // [xcd * CS, (xcd+1) * CS), CS = nsbp/8.  Its sequence runs over super-groups of
-    // SG right-hand-side groups; within one super-group it sweeps its site blocks in
-    // order with the SG groups innermost.  Small SG keeps the neighbour spinors of the
-    // sweep (the +-z and +-t halos) in the XCD's L2 until they are reused; large SG
-    // reuses each site block's links and clover across more groups.
+    // runs the sequence k = lb >> 3.  Each XCD owns a contiguous range of timeslices.
+    // Its sequence runs over super-groups of SG right-hand-side groups; within one
+    // super-group it walks the site blocks of a timeslice (index s) in the outer loop,
+    // its timeslices in the middle loop and the SG groups innermost.  A block's links
+    // and clover are then reused by the SG groups straight away, its +-t neighbours
+    // were loaded SG blocks earlier, and its +-z neighbours about 2*(Z*Y*X/2)/BS * nt * SG
+    // blocks earlier (nt = timeslices per XCD): small SG keeps those halos in the XCD's
+    // L2, large SG reads the links and clover fewer times.
     const int lb = bid - J.blk0;
+    const int xcd = lb & 7;
     const int k = lb >> 3;
-    const int CS = J.nsbp >> 3;
+    const int T = J.g.T;
+    const int tl = xcd * T / 8, nt = (xcd + 1) * T / 8 - tl;
+    if (nt == 0) return;  // more XCDs than timeslices
     const int SG = (J.sg > 0 && J.sg < J.G) ? J.sg : J.G;
-    const int si = k / (CS * SG);
-    const int kk = k - si * CS * SG;
+    const int per = J.nbt * nt * SG;
+    const int si = k / per;
+    if (si * SG >= J.G) return;  // padding of the XCD decomposition
+    const int kk = k - si * per;
     const int sge = min(SG, J.G - si * SG);
-    const int gi = si * SG + kk % sge;
-    const int sb = (lb & 7) * CS + kk / sge;
-    if (sb >= J.nsb) return;  // whole block: padding of the XCD decomposition
-    const int cb = sb * BS + (int)threadIdx.x;
+    if (kk >= J.nbt * nt * sge) return;
+    const int q = kk / sge;
+    const int gi = si * SG + (kk - q * sge);
+    const int s = q / nt;
+    const int t = tl + (q - s * nt);
+    const int sb = t * J.nbt + s;
+    const int sx = s * BS + (int)threadIdx.x;  // site within the timeslice
+    const int cb = t * J.vt + sx;
     const int g0 = gi * NB;
+    // right-hand-side groups with nothing active skip the block (partials written as 0)
+    bool live = false;
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        const int r = g0 + j;
+        live = live || (r < J.nrhs && (J.active == nullptr || J.active[r] != 0));
+    }
+    if (!live) {
+        if ((FL & (F_NORM | F_CG)) && threadIdx.x < NB && g0 + (int)threadIdx.x < J.nrhs)
+            J.part[(size_t)(g0 + threadIdx.x) * J.pstride + sb] = 0.0;
+        return;
+    }
     double nrm2[NB];
-    if (cb < J.g.Vh) {
-        hop_site<P, NB, KIND, FL>(J, cb, g0, nrm2);
+    if (sx < J.vt) {
+        site_body<P, NB, KIND, FL>(J, cb, g0, nrm2);
     } else {
 #pragma unroll
         for (int j = 0; j < NB; ++j) nrm2[j] = 0.0;

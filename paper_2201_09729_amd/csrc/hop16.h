@@ -1,0 +1,427 @@
+// Per-site body of the stencil kernels for FP16-stored fields.
+//
+// Same operator and flags as the generic body in hop.h; what differs is how the
+// binary16 data reaches the FP32 arithmetic, which decides the speed once many
+// right-hand sides share each link (the multi-RHS stencil is bound by vector
+// instruction issue, not by HBM):
+//   * every field is read as raw 32-bit words (one complex binary16 pair each)
+//     through buffer loads whose per-lane operand is just the site's byte offset;
+//     component and right-hand-side offsets travel in scalar registers;
+//   * the binary16 halves enter mixed-precision FMAs directly (gfx950 reads an
+//     f16 operand, low or high half, inside an FP32 FMA), so links, clover
+//     entries and neighbour spinors are never converted one by one;
+//   * the per-(site, RHS) scale of an FP16 spinor and the kernel's coefficients
+//     (ch, ca, -alpha) are folded into the FMAs that accumulate the result
+//     instead of being multiplied into every component.
+// All arithmetic is FP32 with FP32 accumulation; the binary16 values enter exactly.
+#pragma once
+#include "common.h"
+
+namespace dlma {
+
+// ---------------------------------------------------------------- word access
+
+// A read-only or writable region of 32-bit words.  On the device it is a buffer
+// resource; word (lane byte offset v, uniform byte offset s) sits at base + v + s.
+struct WSrc {
+#if defined(__HIP_DEVICE_COMPILE__)
+    __amdgpu_buffer_rsrc_t r;
+#else
+    char* p;
+#endif
+};
+
+HD WSrc wsrc(const void* base, uint32_t bytes) {
+    WSrc s;
+#if defined(__HIP_DEVICE_COMPILE__)
+    // third descriptor word of a raw (unswizzled, stride 0) 32-bit buffer on gfx9-class parts
+    s.r = __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+#else
+    (void)bytes;
+    s.p = (char*)const_cast<void*>(base);
+#endif
+    return s;
+}
+
+HD uint32_t wld(const WSrc& s, uint32_t v, uint32_t u) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_raw_buffer_load_b32(s.r, (int)v, (int)u, 0);
+#else
+    return *(const uint32_t*)(s.p + (size_t)v + u);
+#endif
+}
+
+HD void wst(const WSrc& s, uint32_t v, uint32_t u, uint32_t w) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    __builtin_amdgcn_raw_buffer_store_b32(w, s.r, (int)v, (int)u, 0);
+#else
+    *(uint32_t*)(s.p + (size_t)v + u) = w;
+#endif
+}
+
+HD float wldf(const WSrc& s, uint32_t v, uint32_t u) { return __builtin_bit_cast(float, wld(s, v, u)); }
+
+// A value the caller knows to be the same on every lane, marked as such so that
+// branches on it and values merged after them stay in scalar registers.
+HD int wave_uniform(int v) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_readfirstlane(v);
+#else
+    return v;
+#endif
+}
+
+// binary16 halves of a word, widened where they are consumed
+HD float lo16(uint32_t w) { return (float)__builtin_bit_cast(_Float16, (uint16_t)(w & 0xffffu)); }
+HD float hi16(uint32_t w) { return (float)__builtin_bit_cast(_Float16, (uint16_t)(w >> 16)); }
+
+// One FP16 spinor field of the job for right-hand side r: components and the scale.
+struct F16Field {
+    WSrc v, n;
+};
+HD F16Field f16_field(const SF<P16>& f, int Vh, int r) {
+    F16Field o;
+    o.v = wsrc(f.v + (size_t)r * f.rs, 12u * 4u * (uint32_t)Vh);
+    o.n = wsrc(f.nrm + (size_t)r * f.ns, 4u * (uint32_t)Vh);
+    return o;
+}
+
+// ---------------------------------------------------------------- spin structure
+
+// Chiral-basis spin projection of the hop in direction MU (see hop_term in
+// common.h, which this restates in table form):
+//   h_s = p_s + c_s p_{Q_s}       (s = 0, 1)
+//   lower spins: d_2 = e_2 g_{R_2}, d_3 = e_3 g_{R_3},  g = U' h
+// with coefficient codes 0: +1, 1: -1, 2: +i, 3: -i.  The backward hop negates
+// every c and e; g5 on the input negates c, g5 on the output negates e.
+template <int MU> struct Spin {
+    static constexpr int Q0 = (MU == 0 || MU == 3) ? 2 : 3;
+    static constexpr int Q1 = 5 - Q0;
+    static constexpr int C0 = MU == 0 ? 0 : (MU == 1 ? 2 : (MU == 2 ? 0 : 2));
+    static constexpr int C1 = MU == 0 ? 0 : (MU == 1 ? 2 : (MU == 2 ? 1 : 3));
+    static constexpr int R2 = (MU == 0 || MU == 3) ? 0 : 1;
+    static constexpr int R3 = 1 - R2;
+    static constexpr int E2 = MU == 0 ? 0 : (MU == 1 ? 3 : (MU == 2 ? 1 : 3));
+    static constexpr int E3 = MU == 0 ? 0 : (MU == 1 ? 3 : (MU == 2 ? 0 : 2));
+};
+
+// h = p + c q on binary16 words, FP32 result.  The multiplications by `one` (an
+// opaque 1.0f) keep the widening inside the FMA: p*1 + (+-q) is exact.
+template <int C> HD void proj16(uint32_t p, uint32_t q, float one, float& hr, float& hi) {
+    if (C == 0) { hr = __builtin_fmaf(lo16(p), one, lo16(q)); hi = __builtin_fmaf(hi16(p), one, hi16(q)); }
+    if (C == 1) { hr = __builtin_fmaf(lo16(p), one, -lo16(q)); hi = __builtin_fmaf(hi16(p), one, -hi16(q)); }
+    if (C == 2) { hr = __builtin_fmaf(lo16(p), one, -hi16(q)); hi = __builtin_fmaf(hi16(p), one, lo16(q)); }
+    if (C == 3) { hr = __builtin_fmaf(lo16(p), one, hi16(q)); hi = __builtin_fmaf(hi16(p), one, -lo16(q)); }
+}
+
+// acc += n * (e g)
+template <int E> HD void recon16(float n, float gr, float gi, float& ar, float& ai) {
+    if (E == 0) { ar = __builtin_fmaf(n, gr, ar); ai = __builtin_fmaf(n, gi, ai); }
+    if (E == 1) { ar = __builtin_fmaf(-n, gr, ar); ai = __builtin_fmaf(-n, gi, ai); }
+    if (E == 2) { ar = __builtin_fmaf(-n, gi, ar); ai = __builtin_fmaf(n, gr, ai); }
+    if (E == 3) { ar = __builtin_fmaf(n, gi, ar); ai = __builtin_fmaf(-n, gr, ai); }
+}
+
+// One hopping term on raw words: acc += n (1 -/+ g_mu) U' psi, U' = U (forward) or
+// U^dag (backward); w[spin*3 + colour] are the neighbour's words, u[a*3 + b] the link's.
+template <int MU, bool FWD, bool G5IN, bool G5OUT>
+HD void hop_term16(const uint32_t u[9], const uint32_t w[12], float n, float one, float acc[24]) {
+    using S = Spin<MU>;
+    constexpr int fc = (FWD ? 0 : 1) ^ (G5IN ? 1 : 0);
+    constexpr int fe = (FWD ? 0 : 1) ^ (G5OUT ? 1 : 0);
+    float h[2][6];
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        proj16<S::C0 ^ fc>(w[0 * 3 + b], w[S::Q0 * 3 + b], one, h[0][2 * b], h[0][2 * b + 1]);
+        proj16<S::C1 ^ fc>(w[1 * 3 + b], w[S::Q1 * 3 + b], one, h[1][2 * b], h[1][2 * b + 1]);
+    }
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            float gr = 0.f, gi = 0.f;
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                const float hr = h[s][2 * b], hi = h[s][2 * b + 1];
+                if (FWD) {
+                    const uint32_t l = u[a * 3 + b];
+                    gr = __builtin_fmaf(lo16(l), hr, gr);
+                    gr = __builtin_fmaf(-hi16(l), hi, gr);
+                    gi = __builtin_fmaf(lo16(l), hi, gi);
+                    gi = __builtin_fmaf(hi16(l), hr, gi);
+                } else {
+                    const uint32_t l = u[b * 3 + a];
+                    gr = __builtin_fmaf(lo16(l), hr, gr);
+                    gr = __builtin_fmaf(hi16(l), hi, gr);
+                    gi = __builtin_fmaf(lo16(l), hi, gi);
+                    gi = __builtin_fmaf(-hi16(l), hr, gi);
+                }
+            }
+            // upper spin s gets g_s; lower spins take theirs from the table
+            acc[2 * (s * 3 + a)] = __builtin_fmaf(n, gr, acc[2 * (s * 3 + a)]);
+            acc[2 * (s * 3 + a) + 1] = __builtin_fmaf(n, gi, acc[2 * (s * 3 + a) + 1]);
+            if (S::R2 == s) recon16<S::E2 ^ fe>(n, gr, gi, acc[2 * (2 * 3 + a)], acc[2 * (2 * 3 + a) + 1]);
+            if (S::R3 == s) recon16<S::E3 ^ fe>(n, gr, gi, acc[2 * (3 * 3 + a)], acc[2 * (3 * 3 + a) + 1]);
+        }
+}
+
+// ---------------------------------------------------------------- clover block
+
+// y = C x for one packed Hermitian 6x6 block held as 18 words (3 diagonal pairs,
+// then the 15 lower entries), x given by an accessor returning FP32 values.
+template <class X> HD void herm6_16(const uint32_t c[18], const X& x, float y[12]) {
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        const uint32_t dw = c[i >> 1];
+        const float d = (i & 1) ? hi16(dw) : lo16(dw);
+        y[2 * i] = x.mul(d, 2 * i);
+        y[2 * i + 1] = x.mul(d, 2 * i + 1);
+    }
+    int k = 0;
+#pragma unroll
+    for (int i = 1; i < 6; ++i)
+#pragma unroll
+        for (int j = 0; j < i; ++j, ++k) {
+            const uint32_t l = c[3 + k];
+            y[2 * i] = x.fma(lo16(l), 2 * j, y[2 * i]);
+            y[2 * i] = x.fma(-hi16(l), 2 * j + 1, y[2 * i]);
+            y[2 * i + 1] = x.fma(lo16(l), 2 * j + 1, y[2 * i + 1]);
+            y[2 * i + 1] = x.fma(hi16(l), 2 * j, y[2 * i + 1]);
+            y[2 * j] = x.fma(lo16(l), 2 * i, y[2 * j]);
+            y[2 * j] = x.fma(hi16(l), 2 * i + 1, y[2 * j]);
+            y[2 * j + 1] = x.fma(lo16(l), 2 * i + 1, y[2 * j + 1]);
+            y[2 * j + 1] = x.fma(-hi16(l), 2 * i, y[2 * j + 1]);
+        }
+}
+
+// x as FP32 registers
+struct XF {
+    const float* v;
+    HD float mul(float c, int i) const { return __builtin_fmaf(c, v[i], 0.f); }
+    HD float fma(float c, int i, float y) const { return __builtin_fmaf(c, v[i], y); }
+};
+// x as six binary16 words (unscaled)
+struct XW {
+    const uint32_t* w;
+    HD float val(int i) const { return (i & 1) ? hi16(w[i >> 1]) : lo16(w[i >> 1]); }
+    HD float mul(float c, int i) const { return __builtin_fmaf(c, val(i), 0.f); }
+    HD float fma(float c, int i, float y) const { return __builtin_fmaf(c, val(i), y); }
+};
+
+HD void load_clover16(const WSrc& C, uint32_t VB, int blk, uint32_t lo, uint32_t c[18]) {
+#pragma unroll
+    for (int q = 0; q < 18; ++q) c[q] = wld(C, lo, (uint32_t)(blk * 18 + q) * VB);
+}
+
+// ---------------------------------------------------------------- spinor store
+
+// Stores 24 FP32 values as binary16 words scaled by their largest magnitude
+// (the rule of store_spinor in common.h) and returns the sum of their squares.
+HD float store16(const F16Field& f, uint32_t VB, uint32_t lo, const float s[24]) {
+    float m = 0.f;
+#pragma unroll
+    for (int i = 0; i < 24; ++i) m = fmaxf(m, fabsf(s[i]));
+    if (!(m >= 1e-30f)) m = 0.f;
+    const float inv = m > 0.f ? 1.0f / m : 0.f;
+    wst(f.n, lo, 0, __builtin_bit_cast(uint32_t, m));
+    float q = 0.f;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+        const uint32_t w = f_to_h(s[2 * c] * inv) | (f_to_h(s[2 * c + 1] * inv) << 16);
+        wst(f.v, lo, (uint32_t)c * VB, w);
+        q = __builtin_fmaf(s[2 * c], s[2 * c], q);
+        q = __builtin_fmaf(s[2 * c + 1], s[2 * c + 1], q);
+    }
+    return q;
+}
+
+// ---------------------------------------------------------------- site body
+
+template <int NB, int MU, bool G5IN, bool G5OUT>
+HD void hop_dir16(const HopJob<P16>& J, const WSrc& U, const F16Field (&in)[NB], const Nbr& nb, uint32_t lo,
+                  const bool (&use)[NB], const float (&sc)[NB], float (&acc)[NB][24]) {
+    const uint32_t VB = 4u * (uint32_t)J.g.Vh;
+    const float one = J.one;
+    uint32_t u[9], w[12];
+    const uint32_t f = 4u * (uint32_t)nb.n[2 * MU], bk = 4u * (uint32_t)nb.n[2 * MU + 1];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) u[k] = wld(U, lo, (uint32_t)((J.par * 4 + MU) * 9 + k) * VB);
+#pragma unroll
+    for (int j = 0; j < NB; ++j)
+        if (use[j]) {
+#pragma unroll
+            for (int c = 0; c < 12; ++c) w[c] = wld(in[j].v, f, (uint32_t)c * VB);
+            const float n = wldf(in[j].n, f, 0) * sc[j];
+            hop_term16<MU, true, G5IN, G5OUT>(u, w, n, one, acc[j]);
+        }
+#pragma unroll
+    for (int k = 0; k < 9; ++k) u[k] = wld(U, bk, (uint32_t)(((1 - J.par) * 4 + MU) * 9 + k) * VB);
+#pragma unroll
+    for (int j = 0; j < NB; ++j)
+        if (use[j]) {
+#pragma unroll
+            for (int c = 0; c < 12; ++c) w[c] = wld(in[j].v, bk, (uint32_t)c * VB);
+            const float n = wldf(in[j].n, bk, 0) * sc[j];
+            hop_term16<MU, false, G5IN, G5OUT>(u, w, n, one, acc[j]);
+        }
+}
+
+// out = ... as in hop_site (hop.h) for P16 fields; nrm2 as there.
+template <int NB, int KIND, int FL>
+HD void hop_site16(const HopJob<P16>& J, int cb, int g0, double (&nrm2)[NB]) {
+    const uint32_t VB = 4u * (uint32_t)J.g.Vh;
+    const uint32_t lo = 4u * (uint32_t)cb;
+    const float one = J.one;
+    constexpr bool G5IN = (FL & F_G5IN) != 0;
+    constexpr bool G5OUT = (FL & F_G5OUT) != 0;
+    constexpr bool CG = (KIND == K2) && (FL & F_CG);
+    bool use[NB];
+    float sc[NB], al[NB];
+    F16Field in[NB];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        const int r = g0 + j;
+        use[j] = wave_uniform(r < J.nrhs && (J.active == nullptr || J.active[r] != 0)) != 0;
+        nrm2[j] = 0.0;
+        in[j] = f16_field(J.in, J.g.Vh, r);
+        al[j] = CG ? (float)J.alpha[r < J.nrhs ? r : 0] : 0.f;
+        // K2 with the CG update accumulates -alpha * out directly
+        sc[j] = CG ? (float)(-J.ch) * al[j] : (float)J.ch;
+    }
+    float acc[NB][24];
+#pragma unroll
+    for (int j = 0; j < NB; ++j)
+#pragma unroll
+        for (int i = 0; i < 24; ++i) acc[j][i] = 0.f;
+
+    const WSrc U = wsrc(J.U, 72u * VB);
+    const Nbr nb = neighbours(J.g, J.par, cb);
+    hop_dir16<NB, 0, G5IN, G5OUT>(J, U, in, nb, lo, use, sc, acc);
+    hop_dir16<NB, 1, G5IN, G5OUT>(J, U, in, nb, lo, use, sc, acc);
+    hop_dir16<NB, 2, G5IN, G5OUT>(J, U, in, nb, lo, use, sc, acc);
+    hop_dir16<NB, 3, G5IN, G5OUT>(J, U, in, nb, lo, use, sc, acc);
+
+    const WSrc C = wsrc(J.C, 36u * VB);
+    if (KIND == K1) {
+        if (FL & F_HASD) {
+#pragma unroll
+            for (int j = 0; j < NB; ++j)
+                if (use[j]) {
+                    const F16Field d = f16_field(J.x, J.g.Vh, g0 + j);
+                    const float n = wldf(d.n, lo, 0);
+#pragma unroll
+                    for (int c = 0; c < 12; ++c) {
+                        const uint32_t w = wld(d.v, lo, (uint32_t)c * VB);
+                        acc[j][2 * c] = __builtin_fmaf(lo16(w), n, acc[j][2 * c]);
+                        acc[j][2 * c + 1] = __builtin_fmaf(hi16(w), n, acc[j][2 * c + 1]);
+                    }
+                }
+        }
+#pragma unroll
+        for (int blk = 0; blk < 2; ++blk) {
+            uint32_t c[18];
+            load_clover16(C, VB, blk, lo, c);
+#pragma unroll
+            for (int j = 0; j < NB; ++j)
+                if (use[j]) {
+                    float t[12];
+                    herm6_16(c, XF{&acc[j][blk * 12]}, t);
+#pragma unroll
+                    for (int i = 0; i < 12; ++i) acc[j][blk * 12 + i] = t[i];
+                }
+        }
+#pragma unroll
+        for (int j = 0; j < NB; ++j)
+            if (use[j]) {
+                const F16Field o = f16_field(J.out, J.g.Vh, g0 + j);
+                if (FL & F_ACCUM) {
+                    const float n = wldf(o.n, lo, 0);
+#pragma unroll
+                    for (int c = 0; c < 12; ++c) {
+                        const uint32_t w = wld(o.v, lo, (uint32_t)c * VB);
+                        acc[j][2 * c] = __builtin_fmaf(lo16(w), n, acc[j][2 * c]);
+                        acc[j][2 * c + 1] = __builtin_fmaf(hi16(w), n, acc[j][2 * c + 1]);
+                    }
+                }
+                const float q = store16(o, VB, lo, acc[j]);
+                if (FL & F_NORM) nrm2[j] = (double)q;
+            }
+    } else {
+        // clover (or identity) term on x: acc += ca' * n_x * (A x^)
+        uint32_t xw[NB][12];
+        float nx[NB];
+#pragma unroll
+        for (int j = 0; j < NB; ++j)
+            if (use[j]) {
+                const F16Field xf = f16_field(J.x, J.g.Vh, g0 + j);
+                nx[j] = wldf(xf.n, lo, 0);
+#pragma unroll
+                for (int c = 0; c < 12; ++c) xw[j][c] = wld(xf.v, lo, (uint32_t)c * VB);
+            }
+#pragma unroll
+        for (int blk = 0; blk < 2; ++blk) {
+            uint32_t c[18];
+            if (!(FL & F_NOA)) load_clover16(C, VB, blk, lo, c);
+#pragma unroll
+            for (int j = 0; j < NB; ++j)
+                if (use[j]) {
+                    const float f = (CG ? -(float)J.ca * al[j] : (float)J.ca) * nx[j];
+                    if (FL & F_NOA) {
+#pragma unroll
+                        for (int i = 0; i < 6; ++i) {
+                            const uint32_t w = xw[j][blk * 6 + i];
+                            acc[j][blk * 12 + 2 * i] = __builtin_fmaf(lo16(w), f, acc[j][blk * 12 + 2 * i]);
+                            acc[j][blk * 12 + 2 * i + 1] = __builtin_fmaf(hi16(w), f, acc[j][blk * 12 + 2 * i + 1]);
+                        }
+                    } else {
+                        float t[12];
+                        herm6_16(c, XW{&xw[j][blk * 6]}, t);
+#pragma unroll
+                        for (int i = 0; i < 12; ++i) acc[j][blk * 12 + i] = __builtin_fmaf(f, t[i], acc[j][blk * 12 + i]);
+                    }
+                }
+        }
+#pragma unroll
+        for (int j = 0; j < NB; ++j)
+            if (use[j]) {
+                if (FL & F_HASB) {
+                    const F16Field bf = f16_field(J.b, J.g.Vh, g0 + j);
+                    const float n = wldf(bf.n, lo, 0) * (float)J.cb;
+#pragma unroll
+                    for (int c = 0; c < 12; ++c) {
+                        const uint32_t w = wld(bf.v, lo, (uint32_t)c * VB);
+                        acc[j][2 * c] = __builtin_fmaf(lo16(w), n, acc[j][2 * c]);
+                        acc[j][2 * c + 1] = __builtin_fmaf(hi16(w), n, acc[j][2 * c + 1]);
+                    }
+                }
+                if (CG) {
+                    // r -= alpha out  (acc already holds -alpha out)
+                    const F16Field rf = f16_field(J.r, J.g.Vh, g0 + j);
+                    const float nr = wldf(rf.n, lo, 0);
+#pragma unroll
+                    for (int c = 0; c < 12; ++c) {
+                        const uint32_t w = wld(rf.v, lo, (uint32_t)c * VB);
+                        acc[j][2 * c] = __builtin_fmaf(lo16(w), nr, acc[j][2 * c]);
+                        acc[j][2 * c + 1] = __builtin_fmaf(hi16(w), nr, acc[j][2 * c + 1]);
+                    }
+                    nrm2[j] = (double)store16(rf, VB, lo, acc[j]);
+                    // xs += alpha x
+                    const F16Field sf = f16_field(J.xs, J.g.Vh, g0 + j);
+                    const float ns = wldf(sf.n, lo, 0), ax = al[j] * nx[j];
+#pragma unroll
+                    for (int c = 0; c < 12; ++c) {
+                        const uint32_t w = wld(sf.v, lo, (uint32_t)c * VB);
+                        acc[j][2 * c] = __builtin_fmaf(lo16(xw[j][c]), ax, __builtin_fmaf(lo16(w), ns, 0.f));
+                        acc[j][2 * c + 1] = __builtin_fmaf(hi16(xw[j][c]), ax, __builtin_fmaf(hi16(w), ns, 0.f));
+                    }
+                    (void)store16(sf, VB, lo, acc[j]);
+                } else {
+                    const F16Field o = f16_field(J.out, J.g.Vh, g0 + j);
+                    const float q = store16(o, VB, lo, acc[j]);
+                    if (FL & F_NORM) nrm2[j] = (double)q;
+                }
+            }
+    }
+}
+
+}  // namespace dlma

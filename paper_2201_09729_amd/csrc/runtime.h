@@ -100,15 +100,21 @@ const void* gauge_clover_oo_inv(const Gauge* g, int prec);
 
 inline int ceil_div(long a, long b) { return (int)((a + b - 1) / b); }
 
+// site blocks of a stencil launch: whole blocks per timeslice (see the block decode)
+inline int hop_nsb(const Geo& g) { return g.T * ceil_div(g.Z * g.Y * g.Xh, HOP_BS); }
+
 template <int P> HopJob<P> hop_job(const Gauge* g, int par, int nrhs, int nb) {
     HopJob<P> j = {};
     j.g = g->geo;
     j.par = par;
     j.nrhs = nrhs;
     j.G = ceil_div(nrhs, nb);
-    j.nsb = ceil_div(g->Vh, HOP_BS);
-    j.nsbp = ceil_div(j.nsb, 8) * 8;
+    j.vt = g->geo.Z * g->geo.Y * g->geo.Xh;
+    j.nbt = ceil_div(j.vt, HOP_BS);
+    j.nsb = hop_nsb(g->geo);
+    j.nxb = ceil_div(g->geo.T, 8) * j.nbt;
     j.pstride = j.nsb;
+    j.one = 1.0f;
     return j;
 }
 
@@ -117,7 +123,7 @@ template <int P> int assign_blocks(std::vector<HopJob<P>>& jobs) {
     int b = 0;
     for (auto& j : jobs) {
         j.blk0 = b;
-        b += j.nsbp * j.G;
+        b += 8 * j.nxb * j.G;
     }
     return b;
 }
