@@ -43,9 +43,14 @@ HD WSrc wsrc(const void* base, uint32_t bytes) {
     return s;
 }
 
-HD uint32_t wld(const WSrc& s, uint32_t v, uint32_t u) {
+// Cache policy of a buffer access: 0 = default, NT = non-temporal (streamed, not
+// kept in L2).  Stores and single-use loads of the own site stream, so the L2
+// keeps the data that is reused: links, clover and the neighbour spinors.
+enum { CP_DEFAULT = 0, CP_NT = 2 };
+
+template <int CP = CP_DEFAULT> HD uint32_t wld(const WSrc& s, uint32_t v, uint32_t u) {
 #if defined(__HIP_DEVICE_COMPILE__)
-    return __builtin_amdgcn_raw_buffer_load_b32(s.r, (int)v, (int)u, 0);
+    return __builtin_amdgcn_raw_buffer_load_b32(s.r, (int)v, (int)u, CP);
 #else
     return *(const uint32_t*)(s.p + (size_t)v + u);
 #endif
@@ -53,13 +58,15 @@ HD uint32_t wld(const WSrc& s, uint32_t v, uint32_t u) {
 
 HD void wst(const WSrc& s, uint32_t v, uint32_t u, uint32_t w) {
 #if defined(__HIP_DEVICE_COMPILE__)
-    __builtin_amdgcn_raw_buffer_store_b32(w, s.r, (int)v, (int)u, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(w, s.r, (int)v, (int)u, CP_NT);
 #else
     *(uint32_t*)(s.p + (size_t)v + u) = w;
 #endif
 }
 
-HD float wldf(const WSrc& s, uint32_t v, uint32_t u) { return __builtin_bit_cast(float, wld(s, v, u)); }
+template <int CP = CP_DEFAULT> HD float wldf(const WSrc& s, uint32_t v, uint32_t u) {
+    return __builtin_bit_cast(float, wld<CP>(s, v, u));
+}
 
 // A value the caller knows to be the same on every lane, marked as such so that
 // branches on it and values merged after them stay in scalar registers.
@@ -308,10 +315,10 @@ HD void hop_site16(const HopJob<P16>& J, int cb, int g0, double (&nrm2)[NB]) {
             for (int j = 0; j < NB; ++j)
                 if (use[j]) {
                     const F16Field d = f16_field(J.x, J.g.Vh, g0 + j);
-                    const float n = wldf(d.n, lo, 0);
+                    const float n = wldf<CP_NT>(d.n, lo, 0);
 #pragma unroll
                     for (int c = 0; c < 12; ++c) {
-                        const uint32_t w = wld(d.v, lo, (uint32_t)c * VB);
+                        const uint32_t w = wld<CP_NT>(d.v, lo, (uint32_t)c * VB);
                         acc[j][2 * c] = __builtin_fmaf(lo16(w), n, acc[j][2 * c]);
                         acc[j][2 * c + 1] = __builtin_fmaf(hi16(w), n, acc[j][2 * c + 1]);
                     }
@@ -335,10 +342,10 @@ HD void hop_site16(const HopJob<P16>& J, int cb, int g0, double (&nrm2)[NB]) {
             if (use[j]) {
                 const F16Field o = f16_field(J.out, J.g.Vh, g0 + j);
                 if (FL & F_ACCUM) {
-                    const float n = wldf(o.n, lo, 0);
+                    const float n = wldf<CP_NT>(o.n, lo, 0);
 #pragma unroll
                     for (int c = 0; c < 12; ++c) {
-                        const uint32_t w = wld(o.v, lo, (uint32_t)c * VB);
+                        const uint32_t w = wld<CP_NT>(o.v, lo, (uint32_t)c * VB);
                         acc[j][2 * c] = __builtin_fmaf(lo16(w), n, acc[j][2 * c]);
                         acc[j][2 * c + 1] = __builtin_fmaf(hi16(w), n, acc[j][2 * c + 1]);
                     }
@@ -354,9 +361,9 @@ HD void hop_site16(const HopJob<P16>& J, int cb, int g0, double (&nrm2)[NB]) {
         for (int j = 0; j < NB; ++j)
             if (use[j]) {
                 const F16Field xf = f16_field(J.x, J.g.Vh, g0 + j);
-                nx[j] = wldf(xf.n, lo, 0);
+                nx[j] = wldf<CP_NT>(xf.n, lo, 0);
 #pragma unroll
-                for (int c = 0; c < 12; ++c) xw[j][c] = wld(xf.v, lo, (uint32_t)c * VB);
+                for (int c = 0; c < 12; ++c) xw[j][c] = wld<CP_NT>(xf.v, lo, (uint32_t)c * VB);
             }
 #pragma unroll
         for (int blk = 0; blk < 2; ++blk) {
@@ -386,10 +393,10 @@ HD void hop_site16(const HopJob<P16>& J, int cb, int g0, double (&nrm2)[NB]) {
             if (use[j]) {
                 if (FL & F_HASB) {
                     const F16Field bf = f16_field(J.b, J.g.Vh, g0 + j);
-                    const float n = wldf(bf.n, lo, 0) * (float)J.cb;
+                    const float n = wldf<CP_NT>(bf.n, lo, 0) * (float)J.cb;
 #pragma unroll
                     for (int c = 0; c < 12; ++c) {
-                        const uint32_t w = wld(bf.v, lo, (uint32_t)c * VB);
+                        const uint32_t w = wld<CP_NT>(bf.v, lo, (uint32_t)c * VB);
                         acc[j][2 * c] = __builtin_fmaf(lo16(w), n, acc[j][2 * c]);
                         acc[j][2 * c + 1] = __builtin_fmaf(hi16(w), n, acc[j][2 * c + 1]);
                     }
@@ -397,20 +404,20 @@ HD void hop_site16(const HopJob<P16>& J, int cb, int g0, double (&nrm2)[NB]) {
                 if (CG) {
                     // r -= alpha out  (acc already holds -alpha out)
                     const F16Field rf = f16_field(J.r, J.g.Vh, g0 + j);
-                    const float nr = wldf(rf.n, lo, 0);
+                    const float nr = wldf<CP_NT>(rf.n, lo, 0);
 #pragma unroll
                     for (int c = 0; c < 12; ++c) {
-                        const uint32_t w = wld(rf.v, lo, (uint32_t)c * VB);
+                        const uint32_t w = wld<CP_NT>(rf.v, lo, (uint32_t)c * VB);
                         acc[j][2 * c] = __builtin_fmaf(lo16(w), nr, acc[j][2 * c]);
                         acc[j][2 * c + 1] = __builtin_fmaf(hi16(w), nr, acc[j][2 * c + 1]);
                     }
                     nrm2[j] = (double)store16(rf, VB, lo, acc[j]);
                     // xs += alpha x
                     const F16Field sf = f16_field(J.xs, J.g.Vh, g0 + j);
-                    const float ns = wldf(sf.n, lo, 0), ax = al[j] * nx[j];
+                    const float ns = wldf<CP_NT>(sf.n, lo, 0), ax = al[j] * nx[j];
 #pragma unroll
                     for (int c = 0; c < 12; ++c) {
-                        const uint32_t w = wld(sf.v, lo, (uint32_t)c * VB);
+                        const uint32_t w = wld<CP_NT>(sf.v, lo, (uint32_t)c * VB);
                         acc[j][2 * c] = __builtin_fmaf(lo16(xw[j][c]), ax, __builtin_fmaf(lo16(w), ns, 0.f));
                         acc[j][2 * c + 1] = __builtin_fmaf(hi16(xw[j][c]), ax, __builtin_fmaf(hi16(w), ns, 0.f));
                     }
