@@ -112,12 +112,14 @@ typedef struct {
     double inner_tol;  /* relative reduction of the inner residual per pass; 0 = default */
     int rhs_block;     /* right-hand sides per thread in the stencil kernels: 0 = autotune, 1, 2 or 4 */
     int use_x0;        /* 1: x holds the start vector on entry; 0: start from x = 0 */
-    int graph_iters;   /* CG iterations captured per hipGraph launch; 0 = direct launches */
+    int graph_iters;   /* inner CG iterations captured in one hipGraph and replayed between host
+                          convergence checks (replaces check_every); 0 = direct launches.
+                          Direct launches are also used while dlma_profile_enable is on. */
     int check_every;   /* CG iterations between host convergence checks (>= 1); 0 = default */
     int dagger;        /* 1: solve D^dag x = b (x = g5 D^-1 g5 b), the adjoint solve of a backward pass */
 } dlma_solve_opts;
 
-/* Fill opts with the defaults (tol 1e-10, FP64, autotuned blocks, ...). */
+/* Fill opts with the defaults (tol 1e-10, FP64, autotuned blocks, graph_iters 8, ...). */
 void dlma_solve_opts_default(dlma_solve_opts* opts);
 
 typedef struct {

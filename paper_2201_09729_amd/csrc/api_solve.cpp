@@ -32,7 +32,7 @@ extern "C" void dlma_solve_opts_default(dlma_solve_opts* o) {
     o->inner_tol = 0.0;
     o->rhs_block = 0;
     o->use_x0 = 0;
-    o->graph_iters = 0;
+    o->graph_iters = 8;
     o->check_every = 0;
     o->dagger = 0;
 }
@@ -319,6 +319,38 @@ template <int P> int cg_iteration(std::vector<Cfg>& cs, Tables<P>& t, int nb, co
     return DLMA_OK;
 }
 
+// The inner iterations as one HIP graph: `iters` consecutive CG iterations are
+// captured once per solve on a library stream and replayed with one launch.  Every
+// parameter the kernels read lives in device memory (job tables, per-RHS scalars,
+// active flags), so the captured launches stay valid for the whole solve.  The
+// iteration contains kernel launches only (no memset or copy nodes).
+struct IterGraph {
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    IterGraph() = default;
+    IterGraph(const IterGraph&) = delete;
+    IterGraph& operator=(const IterGraph&) = delete;
+    ~IterGraph() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (cap) (void)hipStreamDestroy(cap);
+    }
+};
+
+template <int P>
+int capture_iterations(std::vector<Cfg>& cs, Tables<P>& t, int nb, const std::vector<int>& nact, int iters, IterGraph& ig) {
+    DLMA_HIP(hipStreamCreateWithFlags(&ig.cap, hipStreamNonBlocking));
+    DLMA_HIP(hipStreamBeginCapture(ig.cap, hipStreamCaptureModeRelaxed));
+    int rc = DLMA_OK;
+    for (int k = 0; k < iters && rc == DLMA_OK; ++k) rc = cg_iteration<P>(cs, t, nb, nact, ig.cap);
+    hipError_t e = hipStreamEndCapture(ig.cap, &ig.graph);
+    if (rc != DLMA_OK) return rc;
+    if (e != hipSuccess) return fail(DLMA_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+    DLMA_HIP(hipGraphInstantiate(&ig.exec, ig.graph, nullptr, nullptr, 0));
+    return DLMA_OK;
+}
+
 struct Tune { int nb, sg; };
 template <int P> int tune_hop(Gauge* g, int nrhs, int fixed_nb, SF<P> vp, SF<P> vy, SF<P> vw, Tune& out, hipStream_t s);
 
@@ -373,6 +405,12 @@ int solve_impl(std::vector<Cfg>& cs, const dlma_solve_opts& o, hipStream_t s) {
     static const bool dlog = std::getenv("DLMA_LOG") != nullptr;
     double rel = o.inner_tol > 0 ? o.inner_tol : (P == P64 ? 0.0 : (P == P32 ? 1e-5 : (P == P16 ? 2e-3 : 1e-2)));
     int check = o.check_every > 0 ? o.check_every : 8;
+    // hipGraph replay of the inner iterations (not while kernels are timed one by one
+    // or traced: both need the individual launches on the caller's stream)
+    static const bool dbg2 = std::getenv("DLMA_LOG") && std::getenv("DLMA_LOG")[0] == '2';
+    const bool use_graph = o.graph_iters > 0 && !Profiler::get().on && !dbg2;
+    IterGraph ig;
+    if (use_graph) check = o.graph_iters;
 
     for (int pass = 0;; ++pass) {
         // true residual
@@ -423,8 +461,11 @@ int solve_impl(std::vector<Cfg>& cs, const dlma_solve_opts& o, hipStream_t s) {
         std::vector<int> nact(ncfg);
         for (int i = 0; i < ncfg; ++i) nact[i] = (int)std::count(cs[i].hact.begin(), cs[i].hact.end(), 1);
         // inner CG
+        if (use_graph && !ig.exec) DLMA_TRY(capture_iterations<P>(cs, t, nb, nact, check, ig));
         for (;;) {
-            for (int k = 0; k < check; ++k) DLMA_TRY(cg_iteration<P>(cs, t, nb, nact, s));
+            if (use_graph) DLMA_HIP(hipGraphLaunch(ig.exec, s));
+            else
+                for (int k = 0; k < check; ++k) DLMA_TRY(cg_iteration<P>(cs, t, nb, nact, s));
             int tot = 0;
             for (int i = 0; i < ncfg; ++i)
                 DLMA_HIP(hipMemcpyAsync(cs[i].hact.data(), cs[i].active, sizeof(int) * cs[i].nrhs, hipMemcpyDeviceToHost, s));
