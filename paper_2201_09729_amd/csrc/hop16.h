@@ -7,13 +7,17 @@
 //   * every field is read as raw 32-bit words (one complex binary16 pair each)
 //     through buffer loads whose per-lane operand is just the site's byte offset;
 //     component and right-hand-side offsets travel in scalar registers;
-//   * the binary16 halves enter mixed-precision FMAs directly (gfx950 reads an
-//     f16 operand, low or high half, inside an FP32 FMA), so links, clover
-//     entries and neighbour spinors are never converted one by one;
+//   * the SU(3) products run on packed binary16 pairs: the spin projection
+//     h = a +- b (or a +- i b) is formed in binary16 (one rounding, at storage
+//     precision) and each complex product is two v_dot2 instructions (exact
+//     binary16 products, FP32 accumulation), half the instructions of FP32 FMAs;
+//   * clover entries and own-site spinors enter mixed-precision FMAs directly
+//     (gfx950 reads an f16 operand, low or high half, inside an FP32 FMA), so
+//     nothing is converted one value at a time;
 //   * the per-(site, RHS) scale of an FP16 spinor and the kernel's coefficients
 //     (ch, ca, -alpha) are folded into the FMAs that accumulate the result
 //     instead of being multiplied into every component.
-// All arithmetic is FP32 with FP32 accumulation; the binary16 values enter exactly.
+// Accumulation is FP32 throughout.
 #pragma once
 #include "common.h"
 
@@ -112,13 +116,56 @@ template <int MU> struct Spin {
     static constexpr int E3 = MU == 0 ? 0 : (MU == 1 ? 3 : (MU == 2 ? 0 : 2));
 };
 
-// h = p + c q on binary16 words, FP32 result.  The multiplications by `one` (an
-// opaque 1.0f) keep the widening inside the FMA: p*1 + (+-q) is exact.
-template <int C> HD void proj16(uint32_t p, uint32_t q, float one, float& hr, float& hi) {
-    if (C == 0) { hr = __builtin_fmaf(lo16(p), one, lo16(q)); hi = __builtin_fmaf(hi16(p), one, hi16(q)); }
-    if (C == 1) { hr = __builtin_fmaf(lo16(p), one, -lo16(q)); hi = __builtin_fmaf(hi16(p), one, -hi16(q)); }
-    if (C == 2) { hr = __builtin_fmaf(lo16(p), one, -hi16(q)); hi = __builtin_fmaf(hi16(p), one, lo16(q)); }
-    if (C == 3) { hr = __builtin_fmaf(lo16(p), one, hi16(q)); hi = __builtin_fmaf(hi16(p), one, -lo16(q)); }
+// Packed binary16 pairs and the spin projection in the two forms the dot products
+// of the SU(3) multiplication need.  For h = p + c q (complex, formed in binary16
+// with one rounding, |h| <= 2 since stored spinors are scaled to magnitude <= 1):
+//   forward hop  (U h):     w1 = (hr, -hi), w2 = (hi, hr)
+//   backward hop (U^dag h): w1 = (hr,  hi), w2 = (hi, -hr)
+// so that with u = (ur, ui) of one link entry, dot(u, w1) and dot(u, w2) are the
+// real and imaginary parts of u h (forward) or conj(u) h (backward).  Each dot
+// product is one v_dot2 instruction: two exact binary16 products summed in FP32.
+typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
+HD half2_t as_h2(uint32_t w) { return __builtin_bit_cast(half2_t, w); }
+
+template <int C, bool FWD> HD void proj_h2(uint32_t pw, uint32_t qw, half2_t& w1, half2_t& w2) {
+    const half2_t p = as_h2(pw), q = as_h2(qw);
+    if (FWD) {
+        const half2_t pa = (half2_t){p.x, -p.y}, pb = (half2_t){p.y, p.x};
+        if (C == 0) { w1 = pa + (half2_t){q.x, -q.y}; w2 = pb + (half2_t){q.y, q.x}; }
+        if (C == 1) { w1 = pa - (half2_t){q.x, -q.y}; w2 = pb - (half2_t){q.y, q.x}; }
+        if (C == 2) { w1 = pa + (half2_t){-q.y, -q.x}; w2 = pb + (half2_t){q.x, -q.y}; }
+        if (C == 3) { w1 = pa + (half2_t){q.y, q.x}; w2 = pb + (half2_t){-q.x, q.y}; }
+    } else {
+        const half2_t pb = (half2_t){p.y, -p.x};
+        if (C == 0) { w1 = p + q; w2 = pb + (half2_t){q.y, -q.x}; }
+        if (C == 1) { w1 = p - q; w2 = pb - (half2_t){q.y, -q.x}; }
+        if (C == 2) { w1 = p + (half2_t){-q.y, q.x}; w2 = pb + (half2_t){q.x, q.y}; }
+        if (C == 3) { w1 = p + (half2_t){q.y, -q.x}; w2 = pb + (half2_t){-q.x, -q.y}; }
+    }
+}
+
+// a.x b.x + a.y b.y with exact binary16 products, FP32 result: the head of a dot
+// product chain, written as the three-operand form with an inline zero (the
+// compiler would otherwise start every chain with a register move of 0.0).
+HD float dot2_first(uint32_t a, half2_t b) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    float r;
+    asm("v_dot2_f32_f16 %0, %1, %2, 0" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+#else
+    const half2_t x = as_h2(a);
+    return (float)x.x * (float)b.x + (float)x.y * (float)b.y;
+#endif
+}
+
+// a.x b.x + a.y b.y + c with exact binary16 products and FP32 accumulation
+HD float dot2(uint32_t a, half2_t b, float c) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_fdot2(as_h2(a), b, c, false);
+#else
+    const half2_t x = as_h2(a);
+    return (float)x.x * (float)b.x + (float)x.y * (float)b.y + c;
+#endif
 }
 
 // acc += n * (e g)
@@ -133,36 +180,27 @@ template <int E> HD void recon16(float n, float gr, float gi, float& ar, float& 
 // U^dag (backward); w[spin*3 + colour] are the neighbour's words, u[a*3 + b] the link's.
 template <int MU, bool FWD, bool G5IN, bool G5OUT>
 HD void hop_term16(const uint32_t u[9], const uint32_t w[12], float n, float one, float acc[24]) {
+    (void)one;
     using S = Spin<MU>;
     constexpr int fc = (FWD ? 0 : 1) ^ (G5IN ? 1 : 0);
     constexpr int fe = (FWD ? 0 : 1) ^ (G5OUT ? 1 : 0);
-    float h[2][6];
+    half2_t w1[2][3], w2[2][3];
 #pragma unroll
     for (int b = 0; b < 3; ++b) {
-        proj16<S::C0 ^ fc>(w[0 * 3 + b], w[S::Q0 * 3 + b], one, h[0][2 * b], h[0][2 * b + 1]);
-        proj16<S::C1 ^ fc>(w[1 * 3 + b], w[S::Q1 * 3 + b], one, h[1][2 * b], h[1][2 * b + 1]);
+        proj_h2<S::C0 ^ fc, FWD>(w[0 * 3 + b], w[S::Q0 * 3 + b], w1[0][b], w2[0][b]);
+        proj_h2<S::C1 ^ fc, FWD>(w[1 * 3 + b], w[S::Q1 * 3 + b], w1[1][b], w2[1][b]);
     }
 #pragma unroll
     for (int s = 0; s < 2; ++s)
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            float gr = 0.f, gi = 0.f;
+            const uint32_t l0 = FWD ? u[a * 3] : u[a];
+            float gr = dot2_first(l0, w1[s][0]), gi = dot2_first(l0, w2[s][0]);
 #pragma unroll
-            for (int b = 0; b < 3; ++b) {
-                const float hr = h[s][2 * b], hi = h[s][2 * b + 1];
-                if (FWD) {
-                    const uint32_t l = u[a * 3 + b];
-                    gr = __builtin_fmaf(lo16(l), hr, gr);
-                    gr = __builtin_fmaf(-hi16(l), hi, gr);
-                    gi = __builtin_fmaf(lo16(l), hi, gi);
-                    gi = __builtin_fmaf(hi16(l), hr, gi);
-                } else {
-                    const uint32_t l = u[b * 3 + a];
-                    gr = __builtin_fmaf(lo16(l), hr, gr);
-                    gr = __builtin_fmaf(hi16(l), hi, gr);
-                    gi = __builtin_fmaf(lo16(l), hi, gi);
-                    gi = __builtin_fmaf(-hi16(l), hr, gi);
-                }
+            for (int b = 1; b < 3; ++b) {
+                const uint32_t l = FWD ? u[a * 3 + b] : u[b * 3 + a];
+                gr = dot2(l, w1[s][b], gr);
+                gi = dot2(l, w2[s][b], gi);
             }
             // upper spin s gets g_s; lower spins take theirs from the table
             acc[2 * (s * 3 + a)] = __builtin_fmaf(n, gr, acc[2 * (s * 3 + a)]);
