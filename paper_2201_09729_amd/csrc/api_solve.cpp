@@ -70,6 +70,7 @@ template <int P> struct Tables {
     int nresid = 0, nprep = 0, nrecon = 0, nvnB = 0, nclov = 0, nconv = 0, nk = 0, nfin = 0;
     int bresid = 0, bprep = 0, brecon = 0, bvnB = 0, bclov = 0, bconv = 0, bxpay = 0, bvnE = 0;
     int bk1 = 0, bk2 = 0, bfin = 0;
+    int nb64 = 1;                      // right-hand sides per thread of the FP64 outer stencils
     std::vector<FinJob> hfinI, hfinAB;  // kept for per-pass updates
 };
 
@@ -122,7 +123,7 @@ template <int P> int alloc_cfg(Cfg& c, hipStream_t s) {
 
 template <int P> float* nrm_of(const Buf& b) { return P == P16 ? b.as<float>() : nullptr; }
 
-template <int P> int build_tables(std::vector<Cfg>& cs, Tables<P>& t, int nb, int sg_in, int sg64, hipStream_t s) {
+template <int P> int build_tables(std::vector<Cfg>& cs, Tables<P>& t, int nb, int sg_in, int nb64, int sg64, hipStream_t s) {
     std::vector<HopJob<P64>> resid, prep, recon;
     std::vector<VecJob<P64>> vnB, clov, conv64, acc64, vnE;
     std::vector<VecJob<P>> conv, acc, xpay;
@@ -134,7 +135,7 @@ template <int P> int build_tables(std::vector<Cfg>& cs, Tables<P>& t, int nb, in
         int Vh = g->Vh, n = c.nrhs;
         const double2* U64 = g->U64.as<double2>();
         for (int par = 0; par < 2; ++par) {
-            HopJob<P64> j = hop_job<P64>(g, par, n, 1);
+            HopJob<P64> j = hop_job<P64>(g, par, n, nb64);
             j.sg = sg64;
             j.U = U64;
             j.C = g->Cl64[par].as<double2>();
@@ -162,7 +163,7 @@ template <int P> int build_tables(std::vector<Cfg>& cs, Tables<P>& t, int nb, in
             clov.push_back(v);
         }
         {   // E = R_e + 1/2 H T
-            HopJob<P64> j = hop_job<P64>(g, 0, n, 1);
+            HopJob<P64> j = hop_job<P64>(g, 0, n, nb64);
             j.sg = sg64;
             j.U = U64;
             j.x = full_view(c.R.p, Vh, 0);
@@ -203,7 +204,7 @@ template <int P> int build_tables(std::vector<Cfg>& cs, Tables<P>& t, int nb, in
             xpay.push_back(x);
         }
         {   // X_o += A_oo^-1 (R_o + 1/2 H E)
-            HopJob<P64> j = hop_job<P64>(g, 1, n, 1);
+            HopJob<P64> j = hop_job<P64>(g, 1, n, nb64);
             j.sg = sg64;
             j.U = U64;
             j.C = g->Ci64.as<double2>();
@@ -248,6 +249,7 @@ template <int P> int build_tables(std::vector<Cfg>& cs, Tables<P>& t, int nb, in
     t.bk1 = assign_blocks(k1d); assign_blocks(k1);
     t.bk2 = assign_blocks(k2d); assign_blocks(k2cg);
     t.bfin = rhs0AB;
+    t.nb64 = nb64;
     t.nresid = (int)resid.size(); t.nprep = (int)prep.size(); t.nrecon = (int)recon.size();
     t.nvnB = (int)vnB.size(); t.nclov = (int)clov.size(); t.nconv = (int)conv.size(); t.nk = (int)k1d.size();
     t.nfin = (int)finAB.size();
@@ -373,12 +375,12 @@ int solve_impl(std::vector<Cfg>& cs, const dlma_solve_opts& o, hipStream_t s) {
         int Vh = c.g->Vh;
         DLMA_TRY(tune_hop<P>(c.g, c.nrhs, o.rhs_block, half_view<P>(c.p.p, nrm_of<P>(c.np), Vh),
                              half_view<P>(c.y.p, nrm_of<P>(c.ny), Vh), half_view<P>(c.w.p, nrm_of<P>(c.nw), Vh), tin, s));
-        DLMA_TRY(tune_hop<P64>(c.g, c.nrhs, 1, half_view<P64>(c.E.p, nullptr, Vh), half_view<P64>(c.T.p, nullptr, Vh),
+        DLMA_TRY(tune_hop<P64>(c.g, c.nrhs, 0, half_view<P64>(c.E.p, nullptr, Vh), half_view<P64>(c.T.p, nullptr, Vh),
                                full_view(c.R.p, Vh, 0), t64, s));
     }
     const int nb = tin.nb;
     Tables<P> t;
-    DLMA_TRY(build_tables<P>(cs, t, nb, tin.sg, t64.sg, s));
+    DLMA_TRY(build_tables<P>(cs, t, nb, tin.sg, t64.nb, t64.sg, s));
     int ncfg = (int)cs.size();
     // load sources and start vectors
     for (auto& c : cs) {
@@ -420,7 +422,7 @@ int solve_impl(std::vector<Cfg>& cs, const dlma_solve_opts& o, hipStream_t s) {
                 c.rnorm2 = c.bnorm2;
             }
         } else {
-            DLMA_HIP(launch_hop<P64>(HopCfg{K2, F_HASB | F_NORM, 1}, t.dresid.template as<HopJob<P64>>(), t.nresid, t.bresid, s));
+            DLMA_HIP(launch_hop<P64>(HopCfg{K2, F_HASB | F_NORM, t.nb64}, t.dresid.template as<HopJob<P64>>(), t.nresid, t.bresid, s));
             DLMA_HIP(launch_finish(t.dfinR.template as<FinJob>(), t.nfin, t.bfin, FIN_NORM, s));
             for (auto& c : cs) DLMA_HIP(hipMemcpyAsync(c.rnorm2.data(), c.nrm, sizeof(double) * c.nrhs, hipMemcpyDeviceToHost, s));
             DLMA_HIP(hipStreamSynchronize(s));
@@ -448,7 +450,7 @@ int solve_impl(std::vector<Cfg>& cs, const dlma_solve_opts& o, hipStream_t s) {
         if (nleft == 0 || pass >= o.max_outer || maxused >= o.maxiter) break;
         // Schur source and inner start
         DLMA_HIP(launch_clover_apply64(t.dclov.template as<VecJob<P64>>(), t.nclov, t.bclov, s));
-        DLMA_HIP(launch_hop<P64>(HopCfg{K2, F_NOA, 1}, t.dprep.template as<HopJob<P64>>(), t.nprep, t.bprep, s));
+        DLMA_HIP(launch_hop<P64>(HopCfg{K2, F_NOA, t.nb64}, t.dprep.template as<HopJob<P64>>(), t.nprep, t.bprep, s));
         DLMA_HIP(launch_norm<P64>(t.dvnE.template as<VecJob<P64>>(), t.nconv, t.bvnE, s));
         DLMA_HIP(launch_finish(t.dfinE.template as<FinJob>(), t.nfin, t.bfin, FIN_NORM, s));
         DLMA_HIP(launch_conv_from64<P>(t.dconv.template as<VecJob<P>>(), t.nconv, t.bconv, t.dconv64.template as<VecJob<P64>>(), s));
@@ -486,7 +488,7 @@ int solve_impl(std::vector<Cfg>& cs, const dlma_solve_opts& o, hipStream_t s) {
         }
         // reconstruction
         DLMA_HIP(launch_accum_to64<P>(t.dacc.template as<VecJob<P>>(), t.dacc64.template as<VecJob<P64>>(), t.nconv, t.bconv, s));
-        DLMA_HIP(launch_hop<P64>(HopCfg{K1, F_HASD | F_ACCUM, 1}, t.drecon.template as<HopJob<P64>>(), t.nrecon, t.brecon, s));
+        DLMA_HIP(launch_hop<P64>(HopCfg{K1, F_HASD | F_ACCUM, t.nb64}, t.drecon.template as<HopJob<P64>>(), t.nrecon, t.brecon, s));
         for (auto& c : cs) DLMA_HIP(hipMemcpyAsync(c.hiters.data(), c.iters, sizeof(int) * c.nrhs, hipMemcpyDeviceToHost, s));
         DLMA_HIP(hipStreamSynchronize(s));
         for (auto& c : cs)
