@@ -95,11 +95,19 @@ def main():
     ap.add_argument("--summarize", nargs=3, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR"),
                     help="write profiles/ summaries from rocprofv3 output directories and exit")
     ap.add_argument("--profile-cmd", default="", help="command line recorded in the summaries")
+    ap.add_argument("--lap-scaling", action="store_true",
+                    help="Laplacian eigensolver cost vs number of modes on a 64x32^3 lattice (matvec / "
+                         "orthogonalisation / Ritz split), instead of the headline benchmark")
+    ap.add_argument("--lap-nev", default="20,40,80,160,320", help="modes per timeslice for --lap-scaling")
+    ap.add_argument("--lap-nt", type=int, default=16, help="timeslices per eigensolver call for --lap-scaling")
     args = ap.parse_args()
     if args.rhs_block is None:
         args.rhs_block = 1 if args.prec == "fp64" else 2
     if args.summarize:
         summarize(args)
+        return
+    if args.lap_scaling:
+        lap_scaling(args)
         return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build runs the whole hot path on a single MI355X "
@@ -295,6 +303,53 @@ def main():
                                "clover_build_s": round(t_cl, 2)}
         log("cpu baseline: %.4g RHS/s (%d threads)" % (rate, oracle.num_threads()))
     print(json.dumps(out), flush=True)
+
+
+def lap_scaling(args):
+    """Cost of the Laplacian modes of every timeslice against the number of modes N,
+    split into applications of the operator, orthogonalisation and Ritz extraction
+    (the quantities of the paper's Table 2, on a synthetic field of the paper's
+    lattice size 64 x 32^3).  One JSON line per N on stdout."""
+    import torch
+    from paper_2201_09729_amd import dlma, synth
+    dims = (64, 32, 32, 32)
+    T = dims[0]
+    dlma.load_library()
+    t = time.time()
+    U = torch.from_numpy(synth.gauge_field(dims, 0.2, 5)).to("cuda")
+    g = dlma.dlma_load_gauge(U, 0.1215, 1.3)
+    v0 = torch.from_numpy(synth.gaussian_start(dims, T, 605)).to("cuda")
+    log("setup %.1f s" % (time.time() - t))
+    paper = {20: (46.3, 3.5, 31.1), 40: (104.0, 10.8, 68.7), 80: (243.0, 41.8, 152.0), 160: (777.0, 251.0, 346.0),
+             320: (2140.0, 1140.0, 740.0)}
+    for variant, nevs in (("chebyshev", [int(x) for x in args.lap_nev.split(",")]),):
+        for nev in nevs:
+            nt = max(1, min(args.lap_nt, T))
+            cheb = 0 if variant == "chebyshev" else -1
+            maxb = 3 * nev + 300 if variant == "chebyshev" else 0
+            dlma.dlma_profile_reset()
+            dlma.dlma_profile_enable(True)
+            torch.cuda.synchronize()
+            t = time.time()
+            for t0 in range(0, T, nt):
+                V, ev = dlma.dlma_lap_eigs(g, nev, t0, min(nt, T - t0), v0[t0:t0 + nt], tol=1e-10,
+                                           max_basis=maxb, cheb_degree=cheb)
+                del V
+            torch.cuda.synchronize()
+            wall = time.time() - t
+            dlma.dlma_profile_enable(False)
+            ph = {name: dlma.dlma_profile_read(kc) for name, kc in (("matvec", 5), ("ortho", 6), ("ritz", 7))}
+            row = {"lattice": "64x32^3", "timeslices": T, "nev": nev, "variant": variant, "wall_s": round(wall, 3),
+                   "matvec_s": round(ph["matvec"][1] / 1e3, 3), "ortho_s": round(ph["ortho"][1] / 1e3, 3),
+                   "ritz_s": round(ph["ritz"][1] / 1e3, 3), "lanczos_steps_per_call": ph["ortho"][0] // max(1, -(-T // nt)),
+                   "matvec_GBps": round(ph["matvec"][2] / max(ph["matvec"][1], 1e-9) / 1e6, 1),
+                   "ortho_GBps": round(ph["ortho"][2] / max(ph["ortho"][1], 1e-9) / 1e6, 1)}
+            if nev in paper and variant == "chebyshev":
+                row["paper_table2_s"] = {"total": paper[nev][0], "ortho": paper[nev][1], "matvec": paper[nev][2],
+                                         "note": "E5 configuration, PRIMME on the authors' (unstated) cluster; context only"}
+            print(json.dumps(row), flush=True)
+            log("%s nev %d: %.2f s (matvec %.2f, ortho %.2f, ritz %.2f)" % (variant, nev, wall, row["matvec_s"],
+                                                                             row["ortho_s"], row["ritz_s"]))
 
 
 def summarize(args):

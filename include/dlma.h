@@ -231,6 +231,10 @@ int dlma_dot(const void* a, const void* b, long n, double* out, void* stream);
  *   3 = hop_k2_cg   even sites, q = A_ee w - D_eo y fused with r -= alpha q,
  *                   x += alpha w and |r|^2 (CG update, q not stored)
  *   4 = hop_k2      even sites, z = A_ee x - D_eo y               (benchmark only)
+ * and the phases of dlma_lap_eigs, per Lanczos step (all timeslices of the call):
+ *   5 = lap_matvec  application of -lap (or of its Chebyshev polynomial)
+ *   6 = lap_ortho   three-term recurrence, two classical Gram-Schmidt passes, normalisation
+ *   7 = lap_ritz    Ritz vectors and Rayleigh-quotient residual checks
  * dlma_profile_read returns the launch count, total milliseconds and total
  * algorithmic bytes (compulsory HBM traffic of the launches, summed) per class.
  */

@@ -1,6 +1,8 @@
 // C ABI: Laplacian eigenmodes per timeslice (dlma_lap_eigs), the distillation
 // projector (dlma_project) and the correlator pieces (dlma_correlators).
 #include <algorithm>
+#include <atomic>
+#include <thread>
 #include <cmath>
 #include <complex>
 #include <numeric>
@@ -97,6 +99,23 @@ std::vector<int> argsort(const std::vector<double>& v) {
     return idx;
 }
 
+// f(t) for t = 0 .. n-1 on the host's cores (the per-timeslice tridiagonal problems
+// are independent); false if any call returned false
+template <class F> bool parallel_for(int n, F f) {
+    const int nth = std::max(1, std::min<int>(n, (int)std::thread::hardware_concurrency()));
+    std::atomic<int> next(0);
+    std::atomic<bool> all(true);
+    auto work = [&]() {
+        for (int t; (t = next.fetch_add(1)) < n;)
+            if (!f(t)) all = false;
+    };
+    std::vector<std::thread> th;
+    for (int i = 1; i < nth; ++i) th.emplace_back(work);
+    work();
+    for (auto& x : th) x.join();
+    return all;
+}
+
 }  // namespace
 
 extern "C" int dlma_lap_eigs(dlma_gauge_t h, int nev, int t0, int nt, const void* v0, void* V_out, double* evals,
@@ -136,6 +155,18 @@ extern "C" int dlma_lap_eigs(dlma_gauge_t h, int nev, int t0, int nt, const void
     std::vector<double> ha((size_t)maxm * nt), hb((size_t)maxm * nt), hlam((size_t)nt * nev), hres((size_t)nt * nev);
     int cur_deg = 0;
     double cc = 0, ee = 1;
+    // phase timing for the profiler (events bracket each phase on the stream);
+    // bytes: the algorithmic traffic of the phase (matvec: links of the timeslice
+    // plus the input and output vectors; Gram-Schmidt: every basis vector read twice
+    // per pass plus w read and written)
+    Profiler& prof = Profiler::get();
+    auto t_begin = [&](hipEvent_t& e) {
+        if (prof.on) prof.begin(0, 0.0, s, e);
+    };
+    auto t_end = [&](hipEvent_t e, int kc, double bytes) {
+        if (prof.on) prof.end(e, kc, bytes, s);
+    };
+    const double vec_b = 16.0 * n * nt, link_b = 3.0 * 2.0 * 9.0 * 16.0 * L3 * nt;
 
     // w = B q_j with B = -lap (cur_deg = 0) or T_deg((c - (-lap))/e)
     auto apply_op = [&](const double2* qj, double2*& w) -> int {
@@ -165,25 +196,31 @@ extern "C" int dlma_lap_eigs(dlma_gauge_t h, int nev, int t0, int nt, const void
         DLMA_HIP(hipMemcpyAsync(hb.data(), beta, sizeof(double) * maxm * nt, hipMemcpyDeviceToHost, s));
         DLMA_HIP(hipStreamSynchronize(s));
         std::vector<double> Sall((size_t)nt * m * nev);
-        for (int t = 0; t < nt; ++t) {
+        const bool solved = parallel_for(nt, [&](int t) {
             std::vector<double> d(ha.begin() + (size_t)t * maxm, ha.begin() + (size_t)t * maxm + m);
             std::vector<double> e(hb.begin() + (size_t)t * maxm, hb.begin() + (size_t)t * maxm + m - 1);
             std::vector<double> Z;
-            if (!tridiag_ql(d, e, &Z, nullptr)) return fail(DLMA_EHIP, "tridiagonal eigensolver did not converge");
+            if (!tridiag_ql(d, e, &Z, nullptr)) return false;
             std::vector<int> idx = argsort(d);
             if (largest) std::reverse(idx.begin(), idx.end());
             for (int k = 0; k < nev; ++k)
                 for (int i = 0; i < m; ++i) Sall[((size_t)t * m + i) * nev + k] = Z[(size_t)i * m + idx[k]];
-        }
+            return true;
+        });
+        if (!solved) return fail(DLMA_EHIP, "tridiagonal eigensolver did not converge");
         Buf Sd;
         DLMA_TRY(Sd.allocate(sizeof(double) * Sall.size()));
         DLMA_HIP(hipMemcpyAsync(Sd.p, Sall.data(), sizeof(double) * Sall.size(), hipMemcpyHostToDevice, s));
+        hipEvent_t ev = nullptr;
+        t_begin(ev);
         DLMA_HIP(launch_ritz(q, tsq, isq, Sd.as<double>(), m, nev, Vo, (long)nev * n, n, nt, s));
         DLMA_HIP(launch_neg_lap(U64, g->geo, t0, Vo, AY.as<double2>(), (long)nev * n, (long)nev * n, nt, s, nev, n, n));
         DLMA_HIP(launch_rayleigh(Vo, AY.as<double2>(), n, nt * nev, dlam, dres, s));
+        t_end(ev, KC_LAP_RITZ, (double)m * vec_b + nev * (link_b + 4.0 * vec_b));
         DLMA_HIP(hipMemcpyAsync(hlam.data(), dlam, sizeof(double) * nt * nev, hipMemcpyDeviceToHost, s));
         DLMA_HIP(hipMemcpyAsync(hres.data(), dres, sizeof(double) * nt * nev, hipMemcpyDeviceToHost, s));
         DLMA_HIP(hipStreamSynchronize(s));
+        if (prof.on) prof.collect();
         ok = true;
         for (double r : hres)
             if (!(r <= tol * 12.0)) ok = false;
@@ -193,6 +230,7 @@ extern "C" int dlma_lap_eigs(dlma_gauge_t h, int nev, int t0, int nt, const void
     auto lanczos = [&](int msteps, bool largest, bool checks, int& m, bool& conv) -> int {
         conv = false;
         m = 0;
+        int next_check = check;
         DLMA_HIP(launch_normalize_into((const double2*)v0, n, q, tsq, n, beta, maxm, 0, nt, s));
         DLMA_HIP(hipMemcpyAsync(hb.data(), beta, sizeof(double) * maxm * nt, hipMemcpyDeviceToHost, s));
         DLMA_HIP(hipStreamSynchronize(s));
@@ -201,34 +239,45 @@ extern "C" int dlma_lap_eigs(dlma_gauge_t h, int nev, int t0, int nt, const void
                 return fail(DLMA_EINVAL, "start vector is zero or not finite");
         for (int j = 0; j < msteps; ++j) {
             double2* w = nullptr;
+            hipEvent_t ev = nullptr;
+            t_begin(ev);
             DLMA_TRY(apply_op(q + (long)j * isq, w));
+            t_end(ev, KC_LAP_MATVEC, (cur_deg > 0 ? cur_deg : 1) * (link_b + 2.0 * vec_b));
+            t_begin(ev);
             DLMA_HIP(launch_lanczos_three(q, tsq, isq, w, n, n, alpha, beta, maxm, j, nt, s));
             for (int pass = 0; pass < 2; ++pass) {  // classical Gram-Schmidt against all q_i, twice
                 DLMA_HIP(launch_dots(q, tsq, isq, w, n, n, Hc.as<double2>(), maxm + 1, j + 1, nt, s));
                 DLMA_HIP(launch_sub_combo(q, tsq, isq, Hc.as<double2>(), maxm + 1, j + 1, w, n, n, nt, s));
             }
             DLMA_HIP(launch_normalize_into(w, n, q + (long)(j + 1) * isq, tsq, n, beta, maxm, j, nt, s));
+            t_end(ev, KC_LAP_ORTHO, (4.0 * (j + 1) + 8.0) * vec_b);
             m = j + 1;
-            if (!checks || m < nev || (m % check != 0 && m != msteps)) continue;
+            // convergence checks every `check` steps, spaced out to m/16 on long runs
+            // (each one solves the m x m tridiagonal problems on the host)
+            if (!checks || m < nev || (m < next_check && m != msteps)) continue;
+            next_check = m + std::max(check, m / 16);
             DLMA_HIP(hipMemcpyAsync(ha.data(), alpha, sizeof(double) * maxm * nt, hipMemcpyDeviceToHost, s));
             DLMA_HIP(hipMemcpyAsync(hb.data(), beta, sizeof(double) * maxm * nt, hipMemcpyDeviceToHost, s));
             DLMA_HIP(hipStreamSynchronize(s));
             // cheap test first: Ritz residual estimates |beta_m s_mi| of the Lanczos operator
-            bool trigger = true;
-            for (int t = 0; t < nt && trigger; ++t) {
+            std::atomic<bool> trigger(true), solved(true);
+            parallel_for(nt, [&](int t) {
+                if (!trigger) return true;
                 std::vector<double> d(ha.begin() + (size_t)t * maxm, ha.begin() + (size_t)t * maxm + m);
                 std::vector<double> e(hb.begin() + (size_t)t * maxm, hb.begin() + (size_t)t * maxm + m - 1);
                 double bm = hb[(size_t)t * maxm + m - 1];
-                if (bm < 1e-12) continue;  // invariant subspace reached: Ritz pairs exact
+                if (bm < 1e-12) return true;  // invariant subspace reached: Ritz pairs exact
                 std::vector<double> last;
-                if (!tridiag_ql(d, e, nullptr, &last)) return fail(DLMA_EHIP, "tridiagonal eigensolver did not converge");
+                if (!tridiag_ql(d, e, nullptr, &last)) { solved = false; return false; }
                 std::vector<int> idx = argsort(d);
                 if (largest) std::reverse(idx.begin(), idx.end());
                 for (int k = 0; k < nev; ++k) {
                     double scale = largest ? std::fabs(d[idx[k]]) : 12.0;
                     if (std::fabs(bm * last[idx[k]]) > tol * scale) { trigger = false; break; }
                 }
-            }
+                return true;
+            });
+            if (!solved) return fail(DLMA_EHIP, "tridiagonal eigensolver did not converge");
             if (!trigger && m != msteps) continue;
             bool ok = false;
             DLMA_TRY(ritz_check(m, largest, ok));
@@ -289,6 +338,7 @@ extern "C" int dlma_lap_eigs(dlma_gauge_t h, int nev, int t0, int nt, const void
     }
     DLMA_HIP(launch_phase_fix(Vo, n, nev * nt, s));
     DLMA_HIP(hipStreamSynchronize(s));
+    if (prof.on) prof.collect();
     if (!conv) return fail(DLMA_ENOTCONV, "Lanczos did not reach the tolerance within max_basis steps");
     return DLMA_OK;
 }

@@ -161,7 +161,13 @@ double hop_bytes(int prec, int kind, int flags, int Vh, int nrhs_active);
 
 // ---------------------------------------------------------------- timing registry
 
-enum KClass { KC_K1 = 0, KC_K1DAG = 1, KC_K2DAGN = 2, KC_K2CG = 3, KC_K2 = 4, KC_N = 5 };
+enum KClass {
+    KC_K1 = 0, KC_K1DAG = 1, KC_K2DAGN = 2, KC_K2CG = 3, KC_K2 = 4,  // stencils
+    KC_LAP_MATVEC = 5,  // Lanczos: applications of -lap (or of its Chebyshev polynomial)
+    KC_LAP_ORTHO = 6,   // Lanczos: three-term step, two Gram-Schmidt passes, normalisation
+    KC_LAP_RITZ = 7,    // Lanczos: Ritz vectors and Rayleigh-quotient residual checks
+    KC_N = 8
+};
 
 struct Profiler {
     static Profiler& get();
