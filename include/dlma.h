@@ -195,14 +195,19 @@ int dlma_project(dlma_gauge_t g, int t, int nev, const void* V_t, const void* in
 /*
  * Correlator pieces for source timeslice t_src (paper eq. 2-4).  For
  * G in {g5 (pseudoscalar), g1/g2/g3 averaged (vector)} and X, Y in {1, P = box, Q = 1 - box}:
- *   one-end estimators  C_XY(t) = 1/N_r sum_r sum_{s,s'} (G g5)_{s s'} <phiY_{r,s'}, g5 G X_t phi_{r,s}>_t
- *   with phi^1 = phi, phi^Q = phibar, phi^P = phi - phibar (eq. 3-4), and the exact pieces
+ *   one-end estimators  C_XY(t) = 1/N_r sum_{r,d} sum_{s,s'} (G g5)_{s s'} <phiY_{r,d,s'}, g5 G X_t phi_{r,d,s}>_t
+ *   with phi^1 = phi, phi^Q = phibar, phi^P = phi - phibar (eq. 3-4), d the dilution
+ *   components of one noise vector (colour and/or even-odd, each also spin-diluted),
+ *   and the exact pieces
  *   C_dist = sum_{k,l} tr[g5G tau_kl Gg5 tau_kl^dag], tau = <v_k(t) x e_s, phi_{l,s'}>_t,
  *   C_QP   = sum_l sum_{s,s'} (G g5)_{s s'} <phi_{l,s'}, g5 G Q_t phi_{l,s}>_t.
  *   V_all     device, [T][nev][Z][Y][X][3]: Laplacian modes of every timeslice
  *   phi_dist  device, [4 nev] spinors: solutions for v_k(t_src) x e_s, index k*4 + s
- *   phi       device, [4 nnoise] spinors: D^-1 eta_{r,s}, index r*4 + s
- *   phibar    device, [4 nnoise] spinors: D^-1 (1 - box(t_src)) eta_{r,s}
+ *   nnoise    spin-diluted noise source groups (4 spinors each) = N_r * ndil
+ *   ndil      dilution components per noise vector: 1 (spin only), 2 (even-odd),
+ *             3 (colour) or 6 (colour and even-odd); must divide nnoise
+ *   phi       device, [4 nnoise] spinors: D^-1 eta_{r,d,s}, index (r*ndil + d)*4 + s
+ *   phibar    device, [4 nnoise] spinors: D^-1 (1 - box(t_src)) eta_{r,d,s}
  *   C_out     host, double[DLMA_NGAMMA][DLMA_NPARTS][T][2] (re, im), gamma 0 = PS, 1 = V;
  *             parts: 0 QQ_est (C_rest), 1 PQ_est (C_mixed: box at sink, 1-box at source),
  *             2 QP_est, 3 PP_est, 4 11_est (full correlator), 5 PP_exact (C_dist),
@@ -210,7 +215,7 @@ int dlma_project(dlma_gauge_t g, int t, int nev, const void* V_t, const void* in
  *             factor and no sign; nnoise = 0 leaves parts 0-4 zero.
  */
 int dlma_correlators(dlma_gauge_t g, int t_src, int nev, const void* V_all, const void* phi_dist,
-                     int nnoise, const void* phi, const void* phibar, double* C_out, void* stream);
+                     int nnoise, int ndil, const void* phi, const void* phibar, double* C_out, void* stream);
 
 /*
  * out = <a, b> = sum_i conj(a_i) b_i over n complex128 numbers (FP64, fixed

@@ -279,14 +279,43 @@ def dist_sources(Vt, T: int, t0: int) -> np.ndarray:
     return out
 
 
-def noise_sources(xi, T: int, t0: int) -> np.ndarray:
-    """Spin-diluted wall noise xi_r x e_s on timeslice t0, index r*4 + s."""
+DILUTIONS = {"spin": (1, 1), "spin-colour": (3, 1), "spin-eo": (1, 2), "spin-colour-eo": (3, 2)}
+
+
+def dilution_size(dilution: str) -> int:
+    """Dilution components per noise vector besides spin: colours x parities."""
+    nc, npar = DILUTIONS[dilution]
+    return nc * npar
+
+
+def noise_sources(xi, T: int, t0: int, dilution: str = "spin") -> np.ndarray:
+    """Diluted wall noise on timeslice t0 (the stochastic wall sources of Sec. 2).
+
+    Each noise vector xi_r is split into the components P_d xi_r, d = c * npar + p:
+    colour c only (colour dilution, nc = 3) and wall sites of parity
+    p = (t0 + z + y + x) mod 2 only (even-odd dilution, npar = 2); each component
+    is then spin-diluted, giving P_d xi_r x e_s with index (r * ndil + d) * 4 + s.
+    "spin" alone is nc = npar = 1.  Returns [4 ndil N_r][T][Z][Y][X][4][3]."""
+    nc, npar = DILUTIONS[dilution]
     nn = xi.shape[0]
-    shp = xi.shape[1:4]
-    out = np.zeros((nn * 4, T) + tuple(shp) + (4, 3), dtype=np.complex128)
+    Z, Y, X = xi.shape[1:4]
+    z, y, x = np.indices((Z, Y, X))
+    par = (t0 + z + y + x) % 2
+    ndil = nc * npar
+    out = np.zeros((nn * ndil * 4, T, Z, Y, X, 4, 3), dtype=np.complex128)
     for r in range(nn):
-        for s in range(4):
-            out[r * 4 + s, t0, ..., s, :] = xi[r]
+        for c in range(nc):
+            for p in range(npar):
+                comp = np.array(xi[r], dtype=np.complex128)
+                if nc == 3:
+                    keep = np.zeros(3, bool)
+                    keep[c] = True
+                    comp[..., ~keep] = 0
+                if npar == 2:
+                    comp[par != p] = 0
+                d = c * npar + p
+                for s in range(4):
+                    out[(r * ndil + d) * 4 + s, t0, ..., s, :] = comp
     return out
 
 
@@ -324,24 +353,28 @@ def _spin(M, psi):
     return np.einsum("st,...tc->...sc", M, psi)
 
 
-def estimator(Vall, t0, phi_rows, phiY_rows, X: str, name: str) -> np.ndarray:
-    """One-end spin-diluted estimator (eq. 3):
+def estimator(Vall, t0, phi_rows, phiY_rows, X: str, name: str, ndil: int = 1) -> np.ndarray:
+    """One-end diluted estimator (eq. 3):
 
-    C_XY(t) = 1/N_r sum_r sum_{s,s'} (G g5)_{s s'} < phiY_{r,s'}, g5 G X_t phi_{r,s} >_t
+    C_XY(t) = 1/N_r sum_{r,d} sum_{s,s'} (G g5)_{s s'} < phiY_{r,d,s'}, g5 G X_t phi_{r,d,s} >_t
 
-    phi_rows, phiY_rows: [N_r][4][T][Z][Y][X][4][3] (dilution spin index second).
-    For the vector channel the three spatial G are averaged.  Output indexed by
-    Delta = (t - t0) mod T."""
+    phi_rows, phiY_rows: [N_r * ndil][4][T][Z][Y][X][4][3], the solutions for the
+    components P_d xi_r x e_s (spin index second).  The components d of one noise
+    vector are summed, the N_r noise vectors averaged.  For the vector channel the
+    three spatial G are averaged.  Output indexed by Delta = (t - t0) mod T."""
     g = gammas()
     g5 = g[4]
-    Nr = phi_rows.shape[0]
+    if phi_rows.shape[0] % ndil:
+        raise ValueError("source groups must be a multiple of the dilution size")
+    Nr = phi_rows.shape[0] // ndil
+    Ng = phi_rows.shape[0]
     T = phi_rows.shape[2]
     acc = np.zeros(T, dtype=np.complex128)
     glist = _gamma_list(name, g)
     for G in glist:
         GL = g5 @ G
         GR = G @ g5
-        for r in range(Nr):
+        for r in range(Ng):
             for s in range(4):
                 xp = _spin(GL, _apply_X(X, Vall, phi_rows[r, s]))
                 for sp in range(4):
@@ -398,12 +431,13 @@ def c_qp_exact(Vall, t0, phi_dist_rows, name: str) -> np.ndarray:
 PARTS = ("QQ_est", "PQ_est", "QP_est", "PP_est", "11_est", "PP_exact", "QP_exact")
 
 
-def correlators(Vall, t0: int, phi_dist, phi, phibar, names=GAMMA_NAMES):
+def correlators(Vall, t0: int, phi_dist, phi, phibar, names=GAMMA_NAMES, ndil: int = 1):
     """All correlator pieces for source timeslice t0.
 
     Vall: [T][nev][Z][Y][X][3] Laplacian eigenvectors of every timeslice.
     phi_dist: [4 nev] solutions for the distillation sources (index k*4+s).
-    phi, phibar: [4 N_r] solutions D^-1 eta and D^-1 (1-box(t0)) eta (index r*4+s).
+    phi, phibar: [4 ndil N_r] solutions D^-1 eta and D^-1 (1-box(t0)) eta for the
+    diluted noise sources of noise_sources (index (r*ndil + d)*4 + s).
 
     Returns {name: {part: [T] complex}} with parts
       QQ_est = C_rest estimate, PQ_est = C_mixed estimate (box at sink, 1-box at
@@ -413,20 +447,20 @@ def correlators(Vall, t0: int, phi_dist, phi, phibar, names=GAMMA_NAMES):
     """
     T = phi.shape[1]
     nev = phi_dist.shape[0] // 4
-    Nr = phi.shape[0] // 4
+    Ng = phi.shape[0] // 4
     sh = phi.shape[1:]
     pd = phi_dist.reshape((nev, 4) + sh)
-    p1 = phi.reshape((Nr, 4) + sh)
-    pq = phibar.reshape((Nr, 4) + sh)
+    p1 = phi.reshape((Ng, 4) + sh)
+    pq = phibar.reshape((Ng, 4) + sh)
     pp = p1 - pq  # D^-1 box eta
     out = {}
     for name in names:
         res = {
-            "QQ_est": estimator(Vall, t0, p1, pq, "Q", name),
-            "PQ_est": estimator(Vall, t0, p1, pq, "P", name),
-            "QP_est": estimator(Vall, t0, p1, pp, "Q", name),
-            "PP_est": estimator(Vall, t0, p1, pp, "P", name),
-            "11_est": estimator(Vall, t0, p1, p1, "1", name),
+            "QQ_est": estimator(Vall, t0, p1, pq, "Q", name, ndil),
+            "PQ_est": estimator(Vall, t0, p1, pq, "P", name, ndil),
+            "QP_est": estimator(Vall, t0, p1, pp, "Q", name, ndil),
+            "PP_est": estimator(Vall, t0, p1, pp, "P", name, ndil),
+            "11_est": estimator(Vall, t0, p1, p1, "1", name, ndil),
             "PP_exact": c_dist_exact(Vall, t0, pd, name),
             "QP_exact": c_qp_exact(Vall, t0, pd, name),
         }

@@ -420,12 +420,14 @@ std::vector<Gam> gammas() {
 }  // namespace
 
 extern "C" int dlma_correlators(dlma_gauge_t h, int t_src, int nev, const void* V_all, const void* phi_dist, int nnoise,
-                                const void* phi, const void* phibar, double* C_out, void* stream) {
+                                int ndil, const void* phi, const void* phibar, double* C_out, void* stream) {
     Gauge* g = (Gauge*)h;
     if (!g) return fail(DLMA_EINVAL, "NULL handle");
     const int T = g->dims[0];
     if (t_src < 0 || t_src >= T) return fail(DLMA_EINVAL, "t_src out of range");
     if (nev < 1 || nnoise < 0) return fail(DLMA_EINVAL, "nev must be >= 1 and nnoise >= 0");
+    if (ndil < 1 || nnoise % ndil != 0) return fail(DLMA_EINVAL, "ndil must be >= 1 and divide nnoise");
+    const double nvec = nnoise > 0 ? (double)(nnoise / ndil) : 1.0;  // independent noise vectors
     if (!V_all || !phi_dist || !C_out || (nnoise > 0 && (!phi || !phibar))) return fail(DLMA_EINVAL, "NULL pointer");
     hipStream_t s = S(stream);
     const long V = g->V;
@@ -521,11 +523,11 @@ extern "C" int dlma_correlators(dlma_gauge_t h, int t_src, int nev, const void* 
                                 one += nc * y1x1;
                                 (void)y1xp;
                             }
-                    acc[0 * T + d] += qq / (double)nnoise;
-                    acc[1 * T + d] += pq / (double)nnoise;
-                    acc[2 * T + d] += qp / (double)nnoise;
-                    acc[3 * T + d] += pp / (double)nnoise;
-                    acc[4 * T + d] += one / (double)nnoise;
+                    acc[0 * T + d] += qq / nvec;
+                    acc[1 * T + d] += pq / nvec;
+                    acc[2 * T + d] += qp / nvec;
+                    acc[3 * T + d] += pp / nvec;
+                    acc[4 * T + d] += one / nvec;
                 }
                 // exact C_dist from the perambulator tau_{(k s),(l s')} = P[l*4+s'][t][k][s]
                 cplx cd = 0;

@@ -81,7 +81,7 @@ def load_library(path: str = LIB_PATH):
         "dlma_solve": ([P, I, P, P, P, P], I),
         "dlma_lap_eigs": ([P, I, I, I, P, P, P, P, P], I),
         "dlma_project": ([P, I, I, P, P, P, I, I, P], I),
-        "dlma_correlators": ([P, I, I, P, P, I, P, P, P, P], I),
+        "dlma_correlators": ([P, I, I, P, P, I, I, P, P, P, P], I),
         "dlma_dot": ([P, P, ctypes.c_long, P, P], I),
         "dlma_profile_enable": ([I], I),
         "dlma_profile_reset": ([], I),
@@ -237,8 +237,10 @@ def dlma_project(g: Gauge, t: int, Vt: torch.Tensor, x: torch.Tensor, mode: int,
 
 
 def dlma_correlators(g: Gauge, t_src: int, Vall: torch.Tensor, phi_dist: torch.Tensor,
-                     phi: torch.Tensor | None = None, phibar: torch.Tensor | None = None):
-    """Returns {gamma: {part: complex numpy [T]}} (see dlma.h for the parts)."""
+                     phi: torch.Tensor | None = None, phibar: torch.Tensor | None = None, ndil: int = 1):
+    """Returns {gamma: {part: complex numpy [T]}} (see dlma.h for the parts).
+
+    phi, phibar: solutions for the sources of noise_sources (ndil = dilution_size of its scheme)."""
     import numpy as np
     Vall = _dev(Vall)
     phi_dist = _dev(phi_dist)
@@ -254,7 +256,7 @@ def dlma_correlators(g: Gauge, t_src: int, Vall: torch.Tensor, phi_dist: torch.T
         pb = ctypes.c_void_p(phibar.data_ptr())
     C = np.zeros((2, NPARTS, T, 2), dtype=np.float64)
     _check(load_library().dlma_correlators(g.h, int(t_src), nev, ctypes.c_void_p(Vall.data_ptr()),
-                                           ctypes.c_void_p(phi_dist.data_ptr()), nn, pp, pb,
+                                           ctypes.c_void_p(phi_dist.data_ptr()), nn, int(ndil), pp, pb,
                                            C.ctypes.data_as(ctypes.c_void_p), _stream()))
     Cc = C[..., 0] + 1j * C[..., 1]
     return {GAMMA_NAMES[gi]: {PART_NAMES[p]: Cc[gi, p] for p in range(NPARTS)} for gi in range(2)}
@@ -300,14 +302,39 @@ def dist_sources(Vt: torch.Tensor, T: int, t0: int) -> torch.Tensor:
     return out
 
 
-def noise_sources(xi: torch.Tensor, T: int, t0: int) -> torch.Tensor:
-    """Spin-diluted wall noise xi_r x e_s on timeslice t0, index r*4 + s; xi: [N_r][Z][Y][X][3]."""
+DILUTIONS = {"spin": (1, 1), "spin-colour": (3, 1), "spin-eo": (1, 2), "spin-colour-eo": (3, 2)}
+
+
+def dilution_size(dilution: str) -> int:
+    """Dilution components per noise vector besides spin: colours x wall parities."""
+    nc, npar = DILUTIONS[dilution]
+    return nc * npar
+
+
+def noise_sources(xi: torch.Tensor, T: int, t0: int, dilution: str = "spin") -> torch.Tensor:
+    """Diluted wall noise on timeslice t0: the components P_d xi_r (colour c only and/or
+    wall sites of parity p = (t0 + z + y + x) mod 2 only; d = c * npar + p), each
+    spin-diluted: P_d xi_r x e_s at index (r * ndil + d) * 4 + s.  xi: [N_r][Z][Y][X][3]."""
     if not xi.is_cuda:
         raise ValueError("tensor must be on the GPU")
+    nc, npar = DILUTIONS[dilution]
+    ndil = nc * npar
     nn = xi.shape[0]
-    out = torch.zeros((nn * 4, T) + tuple(xi.shape[1:4]) + (4, 3), dtype=torch.complex128, device=xi.device)
-    for s in range(4):
-        out[s::4, t0, ..., s, :] = xi.to(torch.complex128)
+    Z, Y, X = xi.shape[1:4]
+    xi = xi.to(torch.complex128)
+    out = torch.zeros((nn * ndil * 4, T, Z, Y, X, 4, 3), dtype=torch.complex128, device=xi.device)
+    idx = torch.arange(Z * Y * X, device=xi.device)
+    par = ((t0 + idx // (Y * X) + (idx // X) % Y + idx % X) % 2).reshape(Z, Y, X)
+    for c in range(nc):
+        for p in range(npar):
+            comp = torch.zeros_like(xi)
+            cols = slice(c, c + 1) if nc == 3 else slice(0, 3)
+            comp[..., cols] = xi[..., cols]
+            if npar == 2:
+                comp[:, par != p] = 0
+            d = c * npar + p
+            for s in range(4):
+                out[(d * 4 + s)::(ndil * 4), t0, ..., s, :] = comp
     return out
 
 

@@ -108,15 +108,21 @@ def abelian_flux_gauge(dims, plane=(1, 2), n: int = 1) -> np.ndarray:
     return u, phi
 
 
-def z2_noise(dims, t0: int, nnoise: int, seed: int) -> np.ndarray:
-    """Real Z2 (+-1) noise per (spatial site, colour) on timeslice t0.
+def z2_noise(dims, t0: int, nnoise: int, seed: int, complex_noise: bool = False) -> np.ndarray:
+    """Z2 noise per (spatial site, colour) on timeslice t0: [nnoise][Z][Y][X][3].
 
-    Returns xi with shape [nnoise][Z][Y][X][3] (float64 values +-1).
+    Real Z2: float64 values +-1.  Complex Z2: complex128 values (+-1 +- i)/sqrt(2),
+    real and imaginary signs drawn independently.  Both have unit modulus, so
+    E[xi xi^dag] = 1.
     """
     T, Z, Y, X = (int(d) for d in dims)
     rng = np.random.default_rng(seed)
     bits = rng.integers(0, 2, size=(nnoise, Z, Y, X, 3))
-    return (1.0 - 2.0 * bits).astype(np.float64)
+    re = (1.0 - 2.0 * bits).astype(np.float64)
+    if not complex_noise:
+        return re
+    im = 1.0 - 2.0 * rng.integers(0, 2, size=(nnoise, Z, Y, X, 3))
+    return (re + 1j * im) / np.sqrt(2.0)
 
 
 def gaussian_start(dims, nt: int, seed: int) -> np.ndarray:

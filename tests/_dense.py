@@ -108,3 +108,48 @@ def gauge_transform_links(U, g):
         gp = np.roll(g, -1, axis=AXIS[mu])
         Ug[..., mu, :, :] = g @ U[..., mu, :, :] @ np.conj(np.swapaxes(gp, -1, -2))
     return Ug
+
+
+def wall_noise_matrix(xi, dims, t0, ncol, npar):
+    """sum_d P_d xi xi^dag P_d on the wall t0 in (site, colour) order, for one noise vector
+    xi [Z][Y][X][3] diluted into ncol colour blocks (1 or 3) and npar parity blocks (1 or 2)."""
+    Z, Y, X = dims[1:]
+    L3 = Z * Y * X
+    v = np.asarray(xi, complex).reshape(L3, 3)
+    z, y, x = np.indices((Z, Y, X))
+    par = ((t0 + z + y + x) % 2).reshape(L3)
+    N = np.zeros((L3 * 3, L3 * 3), complex)
+    for c in range(ncol):
+        for p in range(npar):
+            w = v.copy()
+            if ncol == 3:
+                w[:, [k for k in range(3) if k != c]] = 0
+            if npar == 2:
+                w[par != p, :] = 0
+            f = w.reshape(-1)
+            N += np.outer(f, np.conj(f))
+    return N
+
+
+def dense_trace_noise(S, dims, Vall, t, t0, Gam, X, Y, Nwall):
+    """tr[g5 G X_t S(t,t0) (N x 1_spin) Y_t0 G g5 S(t,t0)^dag]: what the one-end
+    estimator computes for one noise vector whose diluted outer product is N."""
+    L3 = int(np.prod(dims[1:]))
+    it = timeslice_index(dims, t)
+    i0 = timeslice_index(dims, t0)
+    Stt = S[np.ix_(it, i0)]
+    n = L3 * 12
+    I = np.eye(n)
+    N4 = Nwall.reshape(L3, 3, L3, 3)
+    Nfull = np.einsum("mcnd,st->mscntd", N4, np.eye(4)).reshape(n, n)
+
+    def proj(which, tt):
+        if which == "1":
+            return I
+        P = dense_box(Vall[tt])
+        return P if which == "P" else I - P
+
+    L = spin_op(G5 @ Gam, L3)
+    R = spin_op(Gam @ G5, L3)
+    M = L @ proj(X, t) @ Stt @ Nfull @ proj(Y, t0) @ R @ np.conj(Stt.T)
+    return np.trace(M)

@@ -55,7 +55,7 @@ def test_argument_validation_without_gpu(lib):
     assert lib.dlma_apply_dw(None, None, None, 1, 0, None) == -1
     assert lib.dlma_lap_eigs(None, 4, 0, 1, None, None, None, None, None) == -1
     assert lib.dlma_project(None, 0, 1, None, None, None, 1, 0, None) == -1
-    assert lib.dlma_correlators(None, 0, 1, None, None, 0, None, None, None, None) == -1
+    assert lib.dlma_correlators(None, 0, 1, None, None, 0, 1, None, None, None, None) == -1
     assert lib.dlma_profile_read(8, None, None, None) == -1  # classes are 0..7
 
 

@@ -132,3 +132,59 @@ def test_z2_estimator_statistics_and_linearity(orc, sys44):
     for i, key in enumerate(("11", "QQ", "PQ")):
         dev = np.abs(mean[i] - ref[key])
         assert np.all(dev <= 4 * np.abs(err[i]) + 1e-12 * np.max(np.abs(ref["11"]))), key
+
+
+@pytest.mark.parametrize("dilution,ncol,npar", [("spin", 1, 1), ("spin-colour", 3, 1), ("spin-eo", 1, 2),
+                                                ("spin-colour-eo", 3, 2)])
+@pytest.mark.parametrize("complex_noise", [False, True])
+def test_diluted_estimator_matches_dense_noise_trace(orc, sys44, dilution, ncol, npar, complex_noise):
+    """One noise vector split into colour and/or even-odd components, each spin-diluted:
+    the oracle's estimator equals the dense trace with the wall identity replaced by
+    sum_d P_d xi xi^dag P_d, for every X, Y (eq. 3 with dilution)."""
+    dims, U, A, S, Vall, nev = sys44
+    T = dims[0]
+    t0 = 3
+    xi = synth.z2_noise(dims, t0, 1, 77, complex_noise=complex_noise)
+    assert orc.dilution_size(dilution) == ncol * npar
+    eta = orc.noise_sources(xi, T, t0, dilution)
+    assert eta.shape[0] == 4 * ncol * npar
+    etab = orc.project(Vall[t0], eta, t0, 1)
+    phi = apply_S(S, eta)
+    phib = apply_S(S, etab)
+    phid = apply_S(S, orc.dist_sources(Vall[t0], T, t0))
+    N = D.wall_noise_matrix(xi[0], dims, t0, ncol, npar)
+    for name in ("PS", "V"):
+        got = orc.correlators(Vall, t0, phid, phi, phib, names=(name,), ndil=ncol * npar)[name]
+        scale = None
+        for part, (X, Y) in (("QQ_est", "QQ"), ("PQ_est", "PQ"), ("QP_est", "QP"), ("PP_est", "PP"), ("11_est", "11")):
+            ref = np.array([np.mean([D.dense_trace_noise(S, dims, Vall, (t0 + d) % T, t0, G, X, Y, N)
+                                     for G in GAM[name]]) for d in range(T)])
+            if scale is None:
+                scale = np.max(np.abs(ref))
+            assert np.max(np.abs(got[part] - ref)) < 1e-11 * scale, (name, part)
+
+
+def test_dilution_components_partition_the_noise(orc):
+    """The diluted components of a noise vector add back up to it, and components of
+    different d do not overlap (they split colour and wall parity)."""
+    dims = (4, 4, 6, 8)
+    T = dims[0]
+    xi = synth.z2_noise(dims, 1, 2, 5, complex_noise=True)
+    for dil in ("spin", "spin-colour", "spin-eo", "spin-colour-eo"):
+        nd = orc.dilution_size(dil)
+        eta = orc.noise_sources(xi, T, 1, dil).reshape((2, nd, 4) + (T,) + dims[1:] + (4, 3))
+        for r in range(2):
+            tot = eta[r].sum(axis=0)  # [4][T][Z][Y][X][4][3]
+            for s in range(4):
+                assert np.array_equal(tot[s, 1, ..., s, :], xi[r])
+                support = np.abs(eta[r, :, s]) > 0
+                assert np.all(support.sum(axis=0) <= 1)
+
+
+def test_complex_z2_noise():
+    xi = synth.z2_noise((4, 4, 4, 4), 0, 3, 9, complex_noise=True)
+    assert np.allclose(np.abs(xi), 1.0)
+    assert set(np.unique(np.round(xi.real * np.sqrt(2)))) == {-1.0, 1.0}
+    assert set(np.unique(np.round(xi.imag * np.sqrt(2)))) == {-1.0, 1.0}
+    # real Z2 draws are unchanged by the option
+    assert np.array_equal(synth.z2_noise((4, 4, 4, 4), 0, 3, 9), np.sign(xi.real) * 1.0)
