@@ -161,3 +161,44 @@ def test_diluted_sources_and_estimators_match_oracle(D, orc, dilution):
         for part in orc.PARTS:
             err = np.max(np.abs(got[name][part] - ref[name][part]))
             assert err < 1e-12 * scale, (name, part, err, scale)
+
+
+def test_all_source_folded_mixed_term_is_exact(D):
+    """On the GPU chain at 4^4 with every source timeslice and full dilution (unit-vector
+    noise, so the one-end estimators are exact traces): summed over sources,
+    C_PQ(Delta) = C_QP(T - Delta), with C_QP exact from the distillation solves, so
+    C_11 = C_QQ + C_PP + 2 fold(C_QP) holds exactly: the all-source folded form of the
+    paper's C_rest + 2 C_mixed + C_dist (eq. 2)."""
+    dims = (4, 4, 4, 4)
+    T = dims[0]
+    L3 = int(np.prod(dims[1:]))
+    U = synth.gauge_field(dims, 0.3, 1)
+    g = D.dlma_load_gauge(cu(U), 0.120, 1.0)
+    nev = 3
+    V, ev = D.dlma_lap_eigs(g, nev, 0, T, cu(synth.gaussian_start(dims, T, 500)), tol=1e-12)
+    xi = cu(np.eye(L3 * 3).reshape((L3 * 3,) + dims[1:] + (3,)))
+    opts = D.default_opts(tol=1e-12, prec="fp64")
+    S = {}
+    for t0 in range(T):
+        src = D.dist_sources(V[t0], T, t0)
+        eta = D.noise_sources(xi, T, t0)
+        etab = D.dlma_project(g, t0, V[t0].contiguous(), eta, 1)
+        (pd, p1, pb), st = D.dlma_solve([g, g, g], [src, eta, etab], opts=opts)
+        assert all(s["converged"] for s in st)
+        C = D.dlma_correlators(g, t0, V, pd, p1, pb)
+        for name in ("PS", "V"):
+            for part, v in C[name].items():
+                S[(name, part)] = S.get((name, part), 0) + v
+        del eta, etab, p1, pb
+    nr = L3 * 3  # unit-vector noise: the estimators average over nr vectors; sums are exact traces
+    rev = [(-d) % T for d in range(T)]
+    for name in ("PS", "V"):
+        full = nr * S[(name, "11_est")]
+        scale = np.max(np.abs(full))
+        qp = S[(name, "QP_exact")]
+        assert np.max(np.abs(nr * S[(name, "PQ_est")] - qp[rev])) < 1e-9 * scale
+        assert np.max(np.abs(nr * S[(name, "QP_est")] - qp)) < 1e-9 * scale
+        assert np.max(np.abs(nr * S[(name, "PP_est")] - S[(name, "PP_exact")])) < 1e-9 * scale
+        folded = 0.5 * (qp + qp[rev])
+        rhs = nr * S[(name, "QQ_est")] + S[(name, "PP_exact")] + 2.0 * folded
+        assert np.max(np.abs(rhs - full)) < 1e-9 * scale
