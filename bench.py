@@ -100,6 +100,9 @@ def main():
                          "orthogonalisation / Ritz split), instead of the headline benchmark")
     ap.add_argument("--lap-nev", default="20,40,80,160,320", help="modes per timeslice for --lap-scaling")
     ap.add_argument("--lap-nt", type=int, default=16, help="timeslices per eigensolver call for --lap-scaling")
+    ap.add_argument("--dist-scan", action="store_true",
+                    help="C_dist / C against the number of Laplacian modes N on 16^3x32 with the cost-model "
+                         "relation of the paper evaluated on measured GPU times, instead of the headline benchmark")
     args = ap.parse_args()
     if args.rhs_block is None:
         args.rhs_block = 1 if args.prec == "fp64" else 2
@@ -108,6 +111,9 @@ def main():
         return
     if args.lap_scaling:
         lap_scaling(args)
+        return
+    if args.dist_scan:
+        dist_scan(args)
         return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build runs the whole hot path on a single MI355X "
@@ -350,6 +356,75 @@ def lap_scaling(args):
             print(json.dumps(row), flush=True)
             log("%s nev %d: %.2f s (matvec %.2f, ortho %.2f, ritz %.2f)" % (variant, nev, wall, row["matvec_s"],
                                                                              row["ortho_s"], row["ritz_s"]))
+
+
+def dist_scan(args):
+    """How much of the correlator the distillation part carries, against N, and what
+    the stochastic part would have to cost for the method to pay off (paper Sec. 3,
+    Figs. 3-5 and the cost relations of eqs. 6-9), on the synthetic 16^3 x 32 field
+    (eps 0.25, seed 3, kappa 0.121, c_sw 1.2), source timeslice 0.
+
+    C is the one-end estimate of the full correlator from R_1 spin-diluted Z2 noise
+    solves; C_dist(N) is exact from the perambulator of the first N modes.  Times are
+    measured on the GPU: t_lap(N) (modes of every timeslice), the per-right-hand-side
+    time of the batched mixed-precision solve, from which t_{N,D} = 4N * t_rhs and
+    t_{R,D} = R * t_rhs.  Equal cost, eq. (6): R_0 = (t_lap + t_{N,D}) / t_rhs + 2 R_1
+    stochastic solves; the method pays off only if 1 - C_dist/C <= R_1 / R_0 (eq. 9)."""
+    import torch
+    from paper_2201_09729_amd import dlma, synth
+    dims = (32, 16, 16, 16)
+    T = dims[0]
+    t0, nnoise = 0, 8
+    nlist = [8, 16, 32, 64, 128]
+    nmax = max(nlist)
+    dlma.load_library()
+    U = torch.from_numpy(synth.gauge_field(dims, 0.25, 3)).to("cuda")
+    g = dlma.dlma_load_gauge(U, 0.121, 1.2)
+    v0 = torch.from_numpy(synth.gaussian_start(dims, T, 603)).to("cuda")
+    t_lap = {}
+    Vall = None
+    for nev in nlist:
+        torch.cuda.synchronize()
+        t = time.time()
+        V, _ = dlma.dlma_lap_eigs(g, nev, 0, T, v0)
+        torch.cuda.synchronize()
+        t_lap[nev] = time.time() - t
+        if nev == nmax:
+            Vall = V
+        else:
+            del V
+        log("modes N = %d on all %d timeslices: %.2f s" % (nev, T, t_lap[nev]))
+    xi = torch.from_numpy(synth.z2_noise(dims, t0, nnoise, 1003)).to("cuda")
+    eta = dlma.noise_sources(xi, T, t0)
+    b = torch.cat([dlma.dist_sources(Vall[t0], T, t0), eta])
+    opts = dlma.default_opts(tol=TOL, prec="mix_fp16")
+    dlma.dlma_solve([g], [b[:8]], opts=opts)  # tuning and warm-up outside the timing
+    torch.cuda.synchronize()
+    t = time.time()
+    (x,), st = dlma.dlma_solve([g], [b], opts=opts)
+    torch.cuda.synchronize()
+    t_rhs = (time.time() - t) / b.shape[0]
+    assert all(s_["converged"] for s_ in st)
+    log("batched solve of %d right-hand sides: %.3f ms per right-hand side" % (b.shape[0], 1e3 * t_rhs))
+    nd = 4 * nmax
+    R1 = 4 * nnoise  # stochastic solves (spin-diluted) per estimate
+    rows = []
+    for nev in nlist:
+        C = dlma.dlma_correlators(g, t0, Vall[:, :nev].contiguous(), x[:4 * nev], x[nd:], x[nd:])
+        tND = 4 * nev * t_rhs
+        R0 = (t_lap[nev] + tND) / t_rhs + 2 * R1
+        row = {"lattice": "16^3x32", "N_modes": nev, "N_solves": 4 * nev, "R1_solves": R1,
+               "t_lap_s": round(t_lap[nev], 3), "t_ND_s": round(tND, 3), "t_rhs_ms": round(1e3 * t_rhs, 3),
+               "R0_equal_cost": round(R0, 1), "payoff_bound_R1_over_R0": round(R1 / R0, 4)}
+        for name in ("PS", "V"):
+            full = C[name]["11_est"].real
+            dist = C[name]["PP_exact"].real
+            row["%s_Cdist_over_C" % name] = [round(float(dist[d] / full[d]), 4) for d in range(1, T // 2 + 1)]
+            row["%s_one_minus_ratio_le_bound" % name] = [bool(1 - dist[d] / full[d] <= R1 / R0) for d in range(1, T // 2 + 1)]
+        rows.append(row)
+        print(json.dumps(row), flush=True)
+        log("N = %d: C_dist/C (PS) at Delta = 1, 4, 8, 16: %s; R_0 = %.0f" % (
+            nev, [row["PS_Cdist_over_C"][d - 1] for d in (1, 4, 8, 16)], R0))
 
 
 def summarize(args):
