@@ -515,9 +515,13 @@ template <int P> int tune_hop(Gauge* g, int nrhs, int fixed_nb, SF<P> vp, SF<P> 
     DLMA_HIP(launch_fill_random<P>(vp, g->Vh, nrhs, 7u, s));
     Tune best{1, 0};
     float bt = 1e30f;
-    hipEvent_t e0, e1;
-    DLMA_HIP(hipEventCreate(&e0));
-    DLMA_HIP(hipEventCreate(&e1));
+    struct Ev {  // released on every return path
+        hipEvent_t e = nullptr;
+        ~Ev() { if (e) (void)hipEventDestroy(e); }
+    } ev0, ev1;
+    DLMA_HIP(hipEventCreate(&ev0.e));
+    DLMA_HIP(hipEventCreate(&ev1.e));
+    hipEvent_t e0 = ev0.e, e1 = ev1.e;
     const int nbs[3] = {1, 2, 4};
     const int sgs[7] = {1, 2, 4, 8, 16, 32, 0};
     for (int nb : nbs) {
@@ -573,8 +577,6 @@ template <int P> int tune_hop(Gauge* g, int nrhs, int fixed_nb, SF<P> vp, SF<P> 
             }
         }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     tuned_store(g->dims, key, nrhs, best.nb | (best.sg << 8));
     out = best;
     return DLMA_OK;
@@ -701,9 +703,13 @@ int bench_impl(Gauge* g, int nrhs, int nb, int napply, double* ms_out, double* b
     DLMA_TRY(run(1));
     DLMA_HIP(hipStreamSynchronize(s));
     if (Profiler::get().on) Profiler::get().collect();
-    hipEvent_t e0, e1;
-    DLMA_HIP(hipEventCreate(&e0));
-    DLMA_HIP(hipEventCreate(&e1));
+    struct Ev {  // released on every return path
+        hipEvent_t e = nullptr;
+        ~Ev() { if (e) (void)hipEventDestroy(e); }
+    } ev0, ev1;
+    DLMA_HIP(hipEventCreate(&ev0.e));
+    DLMA_HIP(hipEventCreate(&ev1.e));
+    hipEvent_t e0 = ev0.e, e1 = ev1.e;
     DLMA_HIP(hipEventRecord(e0, s));
     for (int k = 0; k < napply; ++k) DLMA_TRY(run(k));
     DLMA_HIP(hipEventRecord(e1, s));
