@@ -8,7 +8,12 @@
 //   clover      [block 0/1][18][Vh] per parity       pairs: 3 pairs of diagonal
 //               reals (d0,d1),(d2,d3),(d4,d5) then the 15 lower entries l_ij,
 //               i > j, ordered (1,0),(2,0),(2,1),(3,0),...,(5,4)
-//   half field  [rhs][12 = spin*3+colour][Vh]        pairs (+ [rhs][Vh] scales for FP16)
+//   half field  [rhs][12 = spin*3+colour][Vh]        pairs; FP16 fields instead
+//               [rhs][3][Vh][4]: components 4g .. 4g+3 of a site in one 16-byte
+//               group g (one 128-bit load), plus [rhs][Vh] FP32 scales
+//   FP16 links  [parity][mu][row a][Vh][3]           words (one 96-bit load per row)
+//   FP16 clover [block][5][Vh][4]                    words: the 18 of a block in
+//               groups of 4 (the last group padded with 2 zero words)
 //   full field  [rhs][parity][12][Vh]                FP64 pairs
 // Even-odd index of site (t,z,y,x): parity = (t+z+y+x) & 1,
 //   cb = ((t*Z + z)*Y + y)*(X/2) + x/2.
@@ -119,20 +124,29 @@ template <int P> struct SF {
     long ns;
 };
 
+// word w (0..11, = component) of site cb in an FP16 field's row r: group w/4, slot w%4
+HD size_t f16_word(const SF<P16>& f, int Vh, int r, int cb, int w) {
+    return (size_t)r * f.rs + ((size_t)(w >> 2) * Vh + cb) * 4 + (w & 3);
+}
+
 template <int P, class R> HD void load_spinor(const SF<P>& f, int Vh, int r, int cb, R s[24]) {
-    const typename PT<P>::S* b = f.v + (size_t)r * f.rs + cb;
+    if constexpr (P == P16) {
+        const R n = (R)f.nrm[(size_t)r * f.ns + cb];
 #pragma unroll
-    for (int c = 0; c < 12; ++c) ldp<P>(b, (size_t)c * Vh, s[2 * c], s[2 * c + 1]);
-    if (P == P16) {
-        R n = (R)f.nrm[(size_t)r * f.ns + cb];
+        for (int c = 0; c < 12; ++c) {
+            const uint32_t w = f.v[f16_word(f, Vh, r, cb, c)];
+            s[2 * c] = (R)h_to_f(w & 0xffffu) * n;
+            s[2 * c + 1] = (R)h_to_f(w >> 16) * n;
+        }
+    } else {
+        const typename PT<P>::S* b = f.v + (size_t)r * f.rs + cb;
 #pragma unroll
-        for (int i = 0; i < 24; ++i) s[i] *= n;
+        for (int c = 0; c < 12; ++c) ldp<P>(b, (size_t)c * Vh, s[2 * c], s[2 * c + 1]);
     }
 }
 
 template <int P, class R> HD void store_spinor(const SF<P>& f, int Vh, int r, int cb, const R s[24]) {
-    typename PT<P>::S* b = f.v + (size_t)r * f.rs + cb;
-    if (P == P16) {
+    if constexpr (P == P16) {
         float m = 0.f;
 #pragma unroll
         for (int i = 0; i < 24; ++i) m = fmaxf(m, fabsf((float)s[i]));
@@ -143,8 +157,10 @@ template <int P, class R> HD void store_spinor(const SF<P>& f, int Vh, int r, in
         float inv = m > 0.f ? 1.0f / m : 0.f;
         f.nrm[(size_t)r * f.ns + cb] = m;
 #pragma unroll
-        for (int c = 0; c < 12; ++c) stp<P>(b, (size_t)c * Vh, (typename PT<P>::R)(s[2 * c] * inv), (typename PT<P>::R)(s[2 * c + 1] * inv));
+        for (int c = 0; c < 12; ++c)
+            f.v[f16_word(f, Vh, r, cb, c)] = f_to_h((float)s[2 * c] * inv) | (f_to_h((float)s[2 * c + 1] * inv) << 16);
     } else {
+        typename PT<P>::S* b = f.v + (size_t)r * f.rs + cb;
 #pragma unroll
         for (int c = 0; c < 12; ++c) stp<P>(b, (size_t)c * Vh, (typename PT<P>::R)s[2 * c], (typename PT<P>::R)s[2 * c + 1]);
     }

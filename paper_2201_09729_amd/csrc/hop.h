@@ -53,10 +53,10 @@ template <int P> struct HopJob {
     double* part;         // partial squared norms (F_NORM / F_CG): part[r * pstride + site block]
     int pstride;
     double ca, cb, ch;
-    float one;  // 1.0f, opaque to the compiler (keeps FP16 widening inside FMAs)
 };
 
 template <int P, class R> HD void load_half_spinor(const SF<P>& f, int Vh, int r, int cb, int blk, R s[12]) {
+    static_assert(P != P16, "FP16 fields use the grouped layout of hop16.h");
     const typename PT<P>::S* b = f.v + (size_t)r * f.rs + (size_t)blk * 6 * Vh + cb;
 #pragma unroll
     for (int c = 0; c < 6; ++c) ldp<P>(b, (size_t)c * Vh, s[2 * c], s[2 * c + 1]);
@@ -93,6 +93,7 @@ HD void hop_dir(const HopJob<P>& J, const Nbr& nb, int cb, int g0, bool (&use)[N
 // Per-site body.  Returns the squared norms (of out, or of the updated r) in nrm2.
 template <int P, int NB, int KIND, int FL>
 HD void hop_site(const HopJob<P>& J, int cb, int g0, double (&nrm2)[NB]) {
+    static_assert(P != P16, "FP16 fields take hop_site16");
     using R = typename PT<P>::R;
     const int Vh = J.g.Vh;
     bool use[NB];

@@ -4,9 +4,11 @@
 // binary16 data reaches the FP32 arithmetic, which decides the speed once many
 // right-hand sides share each link (the multi-RHS stencil is bound by vector
 // instruction issue, not by HBM):
-//   * every field is read as raw 32-bit words (one complex binary16 pair each)
-//     through buffer loads whose per-lane operand is just the site's byte offset;
-//     component and right-hand-side offsets travel in scalar registers;
+//   * every field is read through buffer loads whose per-lane operand is just the
+//     site's byte offset (component and right-hand-side offsets travel in scalar
+//     registers), 128 or 96 bits per load: the FP16 layouts keep four components
+//     of a site (spinors, clover) or one link row together, because the memory
+//     pipeline's cost is per load instruction, not per byte;
 //   * the SU(3) products run on packed binary16 pairs: the spin projection
 //     h = a +- b (or a +- i b) is formed in binary16 (one rounding, at storage
 //     precision) and each complex product is two v_dot2 instructions (exact
@@ -72,6 +74,37 @@ template <int CP = CP_DEFAULT> HD float wldf(const WSrc& s, uint32_t v, uint32_t
     return __builtin_bit_cast(float, wld<CP>(s, v, u));
 }
 
+// 128- and 96-bit accesses (one instruction each): the memory pipeline's cost per
+// instruction, not per byte, bounds the multi-RHS stencil, so every field is laid
+// out for the widest load that fits it.
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x3 __attribute__((ext_vector_type(3)));
+
+template <int CP = CP_DEFAULT> HD u32x4 wld4(const WSrc& s, uint32_t v, uint32_t u) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_raw_buffer_load_b128(s.r, (int)v, (int)u, CP);
+#else
+    return *(const u32x4*)(s.p + (size_t)v + u);
+#endif
+}
+
+HD u32x3 wld3(const WSrc& s, uint32_t v, uint32_t u) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_raw_buffer_load_b96(s.r, (int)v, (int)u, 0);
+#else
+    const uint32_t* q = (const uint32_t*)(s.p + (size_t)v + u);
+    return (u32x3){q[0], q[1], q[2]};
+#endif
+}
+
+HD void wst4(const WSrc& s, uint32_t v, uint32_t u, u32x4 w) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    __builtin_amdgcn_raw_buffer_store_b128(w, s.r, (int)v, (int)u, CP_NT);
+#else
+    *(u32x4*)(s.p + (size_t)v + u) = w;
+#endif
+}
+
 // A value the caller knows to be the same on every lane, marked as such so that
 // branches on it and values merged after them stay in scalar registers.
 HD int wave_uniform(int v) {
@@ -95,6 +128,26 @@ HD F16Field f16_field(const SF<P16>& f, int Vh, int r) {
     o.v = wsrc(f.v + (size_t)r * f.rs, 12u * 4u * (uint32_t)Vh);
     o.n = wsrc(f.nrm + (size_t)r * f.ns, 4u * (uint32_t)Vh);
     return o;
+}
+
+// The 12 words of one site: three 16-byte groups (layout [3][Vh][4]); site16 = 16 site,
+// G16 = 16 Vh bytes per group plane.
+template <int CP = CP_DEFAULT> HD void load_words(const F16Field& f, uint32_t site16, uint32_t G16, uint32_t w[12]) {
+#pragma unroll
+    for (int g = 0; g < 3; ++g) {
+        const u32x4 v = wld4<CP>(f.v, site16, (uint32_t)g * G16);
+        w[4 * g] = v.x; w[4 * g + 1] = v.y; w[4 * g + 2] = v.z; w[4 * g + 3] = v.w;
+    }
+}
+
+// Link U_mu at parity par, site offset site12 = 12 site: rows a = 0..2 of three words
+// each (layout [par][mu][3][Vh][3]); R12 = 12 Vh bytes per row plane.
+HD void load_link16(const WSrc& U, uint32_t site12, uint32_t R12, int par, int mu, uint32_t u[9]) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const u32x3 v = wld3(U, site12, (uint32_t)((par * 4 + mu) * 3 + a) * R12);
+        u[3 * a] = v.x; u[3 * a + 1] = v.y; u[3 * a + 2] = v.z;
+    }
 }
 
 // ---------------------------------------------------------------- spin structure
@@ -179,8 +232,7 @@ template <int E> HD void recon16(float n, float gr, float gi, float& ar, float& 
 // One hopping term on raw words: acc += n (1 -/+ g_mu) U' psi, U' = U (forward) or
 // U^dag (backward); w[spin*3 + colour] are the neighbour's words, u[a*3 + b] the link's.
 template <int MU, bool FWD, bool G5IN, bool G5OUT>
-HD void hop_term16(const uint32_t u[9], const uint32_t w[12], float n, float one, float acc[24]) {
-    (void)one;
+HD void hop_term16(const uint32_t u[9], const uint32_t w[12], float n, float acc[24]) {
     using S = Spin<MU>;
     constexpr int fc = (FWD ? 0 : 1) ^ (G5IN ? 1 : 0);
     constexpr int fe = (FWD ? 0 : 1) ^ (G5OUT ? 1 : 0);
@@ -253,70 +305,71 @@ struct XW {
     HD float fma(float c, int i, float y) const { return __builtin_fmaf(c, val(i), y); }
 };
 
-HD void load_clover16(const WSrc& C, uint32_t VB, int blk, uint32_t lo, uint32_t c[18]) {
+// The 18 words of one clover block (layout [block][5][Vh][4], the fifth group padded):
+// site16 = 16 site, G16 = 16 Vh.
+HD void load_clover16(const WSrc& C, uint32_t G16, int blk, uint32_t site16, uint32_t c[20]) {
 #pragma unroll
-    for (int q = 0; q < 18; ++q) c[q] = wld(C, lo, (uint32_t)(blk * 18 + q) * VB);
+    for (int q = 0; q < 5; ++q) {
+        const u32x4 v = wld4(C, site16, (uint32_t)(blk * 5 + q) * G16);
+        c[4 * q] = v.x; c[4 * q + 1] = v.y; c[4 * q + 2] = v.z; c[4 * q + 3] = v.w;
+    }
 }
 
 // ---------------------------------------------------------------- spinor store
 
 // Stores 24 FP32 values as binary16 words scaled by their largest magnitude
 // (the rule of store_spinor in common.h) and returns the sum of their squares.
-HD float store16(const F16Field& f, uint32_t VB, uint32_t lo, const float s[24]) {
+HD float store16(const F16Field& f, uint32_t G16, uint32_t site, const float s[24]) {
     float m = 0.f;
 #pragma unroll
     for (int i = 0; i < 24; ++i) m = fmaxf(m, fabsf(s[i]));
     if (!(m >= 1e-30f)) m = 0.f;
     const float inv = m > 0.f ? 1.0f / m : 0.f;
-    wst(f.n, lo, 0, __builtin_bit_cast(uint32_t, m));
+    wst(f.n, 4u * site, 0, __builtin_bit_cast(uint32_t, m));
     float q = 0.f;
+    uint32_t w[12];
 #pragma unroll
     for (int c = 0; c < 12; ++c) {
-        const uint32_t w = f_to_h(s[2 * c] * inv) | (f_to_h(s[2 * c + 1] * inv) << 16);
-        wst(f.v, lo, (uint32_t)c * VB, w);
+        w[c] = f_to_h(s[2 * c] * inv) | (f_to_h(s[2 * c + 1] * inv) << 16);
         q = __builtin_fmaf(s[2 * c], s[2 * c], q);
         q = __builtin_fmaf(s[2 * c + 1], s[2 * c + 1], q);
     }
+#pragma unroll
+    for (int g = 0; g < 3; ++g) wst4(f.v, 16u * site, (uint32_t)g * G16, (u32x4){w[4 * g], w[4 * g + 1], w[4 * g + 2], w[4 * g + 3]});
     return q;
 }
 
 // ---------------------------------------------------------------- site body
 
 template <int NB, int MU, bool G5IN, bool G5OUT>
-HD void hop_dir16(const HopJob<P16>& J, const WSrc& U, const F16Field (&in)[NB], const Nbr& nb, uint32_t lo,
+HD void hop_dir16(const HopJob<P16>& J, const WSrc& U, const F16Field (&in)[NB], const Nbr& nb, uint32_t site,
                   const bool (&use)[NB], const float (&sc)[NB], float (&acc)[NB][24]) {
-    const uint32_t VB = 4u * (uint32_t)J.g.Vh;
-    const float one = J.one;
+    const uint32_t Vh = (uint32_t)J.g.Vh;
     uint32_t u[9], w[12];
-    const uint32_t f = 4u * (uint32_t)nb.n[2 * MU], bk = 4u * (uint32_t)nb.n[2 * MU + 1];
-#pragma unroll
-    for (int k = 0; k < 9; ++k) u[k] = wld(U, lo, (uint32_t)((J.par * 4 + MU) * 9 + k) * VB);
+    const uint32_t nf = (uint32_t)nb.n[2 * MU], nbk = (uint32_t)nb.n[2 * MU + 1];
+    load_link16(U, 12u * site, 12u * Vh, J.par, MU, u);
 #pragma unroll
     for (int j = 0; j < NB; ++j)
         if (use[j]) {
-#pragma unroll
-            for (int c = 0; c < 12; ++c) w[c] = wld(in[j].v, f, (uint32_t)c * VB);
-            const float n = wldf(in[j].n, f, 0) * sc[j];
-            hop_term16<MU, true, G5IN, G5OUT>(u, w, n, one, acc[j]);
+            load_words(in[j], 16u * nf, 16u * Vh, w);
+            const float n = wldf(in[j].n, 4u * nf, 0) * sc[j];
+            hop_term16<MU, true, G5IN, G5OUT>(u, w, n, acc[j]);
         }
-#pragma unroll
-    for (int k = 0; k < 9; ++k) u[k] = wld(U, bk, (uint32_t)(((1 - J.par) * 4 + MU) * 9 + k) * VB);
+    load_link16(U, 12u * nbk, 12u * Vh, 1 - J.par, MU, u);
 #pragma unroll
     for (int j = 0; j < NB; ++j)
         if (use[j]) {
-#pragma unroll
-            for (int c = 0; c < 12; ++c) w[c] = wld(in[j].v, bk, (uint32_t)c * VB);
-            const float n = wldf(in[j].n, bk, 0) * sc[j];
-            hop_term16<MU, false, G5IN, G5OUT>(u, w, n, one, acc[j]);
+            load_words(in[j], 16u * nbk, 16u * Vh, w);
+            const float n = wldf(in[j].n, 4u * nbk, 0) * sc[j];
+            hop_term16<MU, false, G5IN, G5OUT>(u, w, n, acc[j]);
         }
 }
 
 // out = ... as in hop_site (hop.h) for P16 fields; nrm2 as there.
 template <int NB, int KIND, int FL>
 HD void hop_site16(const HopJob<P16>& J, int cb, int g0, double (&nrm2)[NB]) {
-    const uint32_t VB = 4u * (uint32_t)J.g.Vh;
-    const uint32_t lo = 4u * (uint32_t)cb;
-    const float one = J.one;
+    const uint32_t G16 = 16u * (uint32_t)J.g.Vh;  // bytes per 16-byte group plane
+    const uint32_t site = (uint32_t)cb, lo = 4u * site, s16 = 16u * site;
     constexpr bool G5IN = (FL & F_G5IN) != 0;
     constexpr bool G5OUT = (FL & F_G5OUT) != 0;
     constexpr bool CG = (KIND == K2) && (FL & F_CG);
@@ -339,14 +392,14 @@ HD void hop_site16(const HopJob<P16>& J, int cb, int g0, double (&nrm2)[NB]) {
 #pragma unroll
         for (int i = 0; i < 24; ++i) acc[j][i] = 0.f;
 
-    const WSrc U = wsrc(J.U, 72u * VB);
+    const WSrc U = wsrc(J.U, 288u * (uint32_t)J.g.Vh);
     const Nbr nb = neighbours(J.g, J.par, cb);
-    hop_dir16<NB, 0, G5IN, G5OUT>(J, U, in, nb, lo, use, sc, acc);
-    hop_dir16<NB, 1, G5IN, G5OUT>(J, U, in, nb, lo, use, sc, acc);
-    hop_dir16<NB, 2, G5IN, G5OUT>(J, U, in, nb, lo, use, sc, acc);
-    hop_dir16<NB, 3, G5IN, G5OUT>(J, U, in, nb, lo, use, sc, acc);
+    hop_dir16<NB, 0, G5IN, G5OUT>(J, U, in, nb, site, use, sc, acc);
+    hop_dir16<NB, 1, G5IN, G5OUT>(J, U, in, nb, site, use, sc, acc);
+    hop_dir16<NB, 2, G5IN, G5OUT>(J, U, in, nb, site, use, sc, acc);
+    hop_dir16<NB, 3, G5IN, G5OUT>(J, U, in, nb, site, use, sc, acc);
 
-    const WSrc C = wsrc(J.C, 36u * VB);
+    const WSrc C = wsrc(J.C, 10u * G16);
     if (KIND == K1) {
         if (FL & F_HASD) {
 #pragma unroll
@@ -354,9 +407,11 @@ HD void hop_site16(const HopJob<P16>& J, int cb, int g0, double (&nrm2)[NB]) {
                 if (use[j]) {
                     const F16Field d = f16_field(J.x, J.g.Vh, g0 + j);
                     const float n = wldf<CP_NT>(d.n, lo, 0);
+                    uint32_t ow[12];
+                    load_words<CP_NT>(d, s16, G16, ow);
 #pragma unroll
                     for (int c = 0; c < 12; ++c) {
-                        const uint32_t w = wld<CP_NT>(d.v, lo, (uint32_t)c * VB);
+                        const uint32_t w = ow[c];
                         acc[j][2 * c] = __builtin_fmaf(lo16(w), n, acc[j][2 * c]);
                         acc[j][2 * c + 1] = __builtin_fmaf(hi16(w), n, acc[j][2 * c + 1]);
                     }
@@ -364,8 +419,8 @@ HD void hop_site16(const HopJob<P16>& J, int cb, int g0, double (&nrm2)[NB]) {
         }
 #pragma unroll
         for (int blk = 0; blk < 2; ++blk) {
-            uint32_t c[18];
-            load_clover16(C, VB, blk, lo, c);
+            uint32_t c[20];
+            load_clover16(C, G16, blk, s16, c);
 #pragma unroll
             for (int j = 0; j < NB; ++j)
                 if (use[j]) {
@@ -381,14 +436,16 @@ HD void hop_site16(const HopJob<P16>& J, int cb, int g0, double (&nrm2)[NB]) {
                 const F16Field o = f16_field(J.out, J.g.Vh, g0 + j);
                 if (FL & F_ACCUM) {
                     const float n = wldf<CP_NT>(o.n, lo, 0);
+                    uint32_t ow[12];
+                    load_words<CP_NT>(o, s16, G16, ow);
 #pragma unroll
                     for (int c = 0; c < 12; ++c) {
-                        const uint32_t w = wld<CP_NT>(o.v, lo, (uint32_t)c * VB);
+                        const uint32_t w = ow[c];
                         acc[j][2 * c] = __builtin_fmaf(lo16(w), n, acc[j][2 * c]);
                         acc[j][2 * c + 1] = __builtin_fmaf(hi16(w), n, acc[j][2 * c + 1]);
                     }
                 }
-                const float q = store16(o, VB, lo, acc[j]);
+                const float q = store16(o, G16, site, acc[j]);
                 if (FL & F_NORM) nrm2[j] = (double)q;
             }
     } else {
@@ -400,13 +457,12 @@ HD void hop_site16(const HopJob<P16>& J, int cb, int g0, double (&nrm2)[NB]) {
             if (use[j]) {
                 const F16Field xf = f16_field(J.x, J.g.Vh, g0 + j);
                 nx[j] = wldf<CP_NT>(xf.n, lo, 0);
-#pragma unroll
-                for (int c = 0; c < 12; ++c) xw[j][c] = wld<CP_NT>(xf.v, lo, (uint32_t)c * VB);
+                load_words<CP_NT>(xf, s16, G16, xw[j]);
             }
 #pragma unroll
         for (int blk = 0; blk < 2; ++blk) {
-            uint32_t c[18];
-            if (!(FL & F_NOA)) load_clover16(C, VB, blk, lo, c);
+            uint32_t c[20];
+            if (!(FL & F_NOA)) load_clover16(C, G16, blk, s16, c);
 #pragma unroll
             for (int j = 0; j < NB; ++j)
                 if (use[j]) {
@@ -432,9 +488,11 @@ HD void hop_site16(const HopJob<P16>& J, int cb, int g0, double (&nrm2)[NB]) {
                 if (FL & F_HASB) {
                     const F16Field bf = f16_field(J.b, J.g.Vh, g0 + j);
                     const float n = wldf<CP_NT>(bf.n, lo, 0) * (float)J.cb;
+                    uint32_t ow[12];
+                    load_words<CP_NT>(bf, s16, G16, ow);
 #pragma unroll
                     for (int c = 0; c < 12; ++c) {
-                        const uint32_t w = wld<CP_NT>(bf.v, lo, (uint32_t)c * VB);
+                        const uint32_t w = ow[c];
                         acc[j][2 * c] = __builtin_fmaf(lo16(w), n, acc[j][2 * c]);
                         acc[j][2 * c + 1] = __builtin_fmaf(hi16(w), n, acc[j][2 * c + 1]);
                     }
@@ -443,26 +501,29 @@ HD void hop_site16(const HopJob<P16>& J, int cb, int g0, double (&nrm2)[NB]) {
                     // r -= alpha out  (acc already holds -alpha out)
                     const F16Field rf = f16_field(J.r, J.g.Vh, g0 + j);
                     const float nr = wldf<CP_NT>(rf.n, lo, 0);
+                    uint32_t ow[12];
+                    load_words<CP_NT>(rf, s16, G16, ow);
 #pragma unroll
                     for (int c = 0; c < 12; ++c) {
-                        const uint32_t w = wld<CP_NT>(rf.v, lo, (uint32_t)c * VB);
+                        const uint32_t w = ow[c];
                         acc[j][2 * c] = __builtin_fmaf(lo16(w), nr, acc[j][2 * c]);
                         acc[j][2 * c + 1] = __builtin_fmaf(hi16(w), nr, acc[j][2 * c + 1]);
                     }
-                    nrm2[j] = (double)store16(rf, VB, lo, acc[j]);
+                    nrm2[j] = (double)store16(rf, G16, site, acc[j]);
                     // xs += alpha x
                     const F16Field sf = f16_field(J.xs, J.g.Vh, g0 + j);
                     const float ns = wldf<CP_NT>(sf.n, lo, 0), ax = al[j] * nx[j];
+                    load_words<CP_NT>(sf, s16, G16, ow);
 #pragma unroll
                     for (int c = 0; c < 12; ++c) {
-                        const uint32_t w = wld<CP_NT>(sf.v, lo, (uint32_t)c * VB);
+                        const uint32_t w = ow[c];
                         acc[j][2 * c] = __builtin_fmaf(lo16(xw[j][c]), ax, __builtin_fmaf(lo16(w), ns, 0.f));
                         acc[j][2 * c + 1] = __builtin_fmaf(hi16(xw[j][c]), ax, __builtin_fmaf(hi16(w), ns, 0.f));
                     }
-                    (void)store16(sf, VB, lo, acc[j]);
+                    (void)store16(sf, G16, site, acc[j]);
                 } else {
                     const F16Field o = f16_field(J.out, J.g.Vh, g0 + j);
-                    const float q = store16(o, VB, lo, acc[j]);
+                    const float q = store16(o, G16, site, acc[j]);
                     if (FL & F_NORM) nrm2[j] = (double)q;
                 }
             }

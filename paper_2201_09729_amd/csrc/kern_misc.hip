@@ -323,6 +323,35 @@ template hipError_t launch_convert_pairs<P32>(const double2*, void*, long, hipSt
 template hipError_t launch_convert_pairs<P16>(const double2*, void*, long, hipStream_t);
 template hipError_t launch_convert_pairs<PB16>(const double2*, void*, long, hipStream_t);
 
+// FP64 pairs in planes [M][K][Vh] to binary16 words in groups of G components per
+// site, [M][ceil(K/G)][Vh][G], the last group padded with zero words: the FP16
+// links (M = 8 parity x direction planes, K = 9, G = 3: one row per group) and
+// clover blocks (M = 2, K = 18, G = 4) of the stencil's wide loads.
+__global__ void k_regroup16(const double2* __restrict__ src, uint32_t* __restrict__ dst, int M, int K, int G, int Vh) {
+    const int NQ = (K + G - 1) / G;
+    const long n = (long)M * NQ * Vh * G;
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int w = (int)(i % G);
+    const long r = i / G;
+    const int site = (int)(r % Vh);
+    const long mq = r / Vh;
+    const int q = (int)(mq % NQ), m = (int)(mq / NQ);
+    const int k = q * G + w;
+    uint32_t out = 0;
+    if (k < K) {
+        const double2 v = src[((long)m * K + k) * Vh + site];
+        out = f_to_h((float)v.x) | (f_to_h((float)v.y) << 16);
+    }
+    dst[i] = out;
+}
+
+hipError_t launch_regroup16(const double2* src, void* dst, int M, int K, int G, int Vh, hipStream_t s) {
+    const long n = (long)M * ((K + G - 1) / G) * Vh * G;
+    hipLaunchKernelGGL(k_regroup16, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, src, (uint32_t*)dst, M, K, G, Vh);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- canonical <-> even-odd
 
 __global__ void k_canon_to_eo(const double2* __restrict__ can, double2* __restrict__ eo, Geo g, int nrhs, int g5) {

@@ -47,6 +47,7 @@ hipError_t launch_clover_build(const double2* Ucan, const Geo& g, double m0, dou
 hipError_t launch_clover_invert(const double2* C, double2* Ci, int Vh, int* err, hipStream_t s);
 hipError_t launch_add_diag(double2* C, int Vh, double delta, hipStream_t s);
 template <int P> hipError_t launch_convert_pairs(const double2* src, void* dst, long n, hipStream_t s);
+hipError_t launch_regroup16(const double2* src, void* dst, int M, int K, int G, int Vh, hipStream_t s);
 
 // full FP64 fields <-> canonical
 hipError_t launch_canon_to_eo(const double2* can, double2* eo, const Geo& g, int nrhs, hipStream_t s, int g5 = 0);

@@ -78,6 +78,16 @@ int gauge_prepare(Gauge* g, int prec, hipStream_t s) {
     if (prec == P64 || g->lo_ready[prec]) return DLMA_OK;
     long nl = 2L * 4 * 9 * g->Vh, nc = 2L * 18 * g->Vh;
     size_t pb = pair_bytes(prec);
+    if (prec == P16) {  // grouped layouts of the FP16 stencil (common.h)
+        DLMA_TRY(g->Ulo[prec].allocate(nl * pb));
+        DLMA_TRY(g->Cee[prec].allocate(2L * 20 * g->Vh * pb));
+        DLMA_TRY(g->Cio[prec].allocate(2L * 20 * g->Vh * pb));
+        DLMA_HIP(launch_regroup16(g->U64.as<double2>(), g->Ulo[prec].p, 8, 9, 3, g->Vh, s));
+        DLMA_HIP(launch_regroup16(g->Cl64[0].as<double2>(), g->Cee[prec].p, 2, 18, 4, g->Vh, s));
+        DLMA_HIP(launch_regroup16(g->Ci64.as<double2>(), g->Cio[prec].p, 2, 18, 4, g->Vh, s));
+        g->lo_ready[prec] = true;
+        return DLMA_OK;
+    }
     DLMA_TRY(g->Ulo[prec].allocate(nl * pb));
     DLMA_TRY(g->Cee[prec].allocate(nc * pb));
     DLMA_TRY(g->Cio[prec].allocate(nc * pb));

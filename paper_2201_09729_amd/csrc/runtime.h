@@ -114,7 +114,6 @@ template <int P> HopJob<P> hop_job(const Gauge* g, int par, int nrhs, int nb) {
     j.nsb = hop_nsb(g->geo);
     j.nxb = ceil_div(g->geo.T, 8) * j.nbt;
     j.pstride = j.nsb;
-    j.one = 1.0f;
     return j;
 }
 
