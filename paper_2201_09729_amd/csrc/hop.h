@@ -261,8 +261,14 @@ HD void site_body(const HopJob<P>& J, int cb, int g0, double (&nrm2)[NB]) {
     else hop_site<P, NB, KIND, FL>(J, cb, g0, nrm2);
 }
 
+// Occupancy floor per instantiation: the FP16 kernels with up to two right-hand
+// sides per thread stay within 128 registers (four waves per SIMD), which their
+// long-latency gathers need; the compiler's own choice lands just above it for some.
+template <int P, int NB> constexpr int hop_min_waves() { return (P == P16 && NB <= 2) ? 4 : 1; }
+
 template <int P, int NB, int KIND, int FL, int BS>
-__global__ void __launch_bounds__(BS) hop_kernel(const HopJob<P>* __restrict__ jobs, int njob) {
+__global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(hop_min_waves<P, NB>())))
+hop_kernel(const HopJob<P>* __restrict__ jobs, int njob) {
     const int bid = blockIdx.x;
     int jb = 0;
     while (jb + 1 < njob && bid >= jobs[jb + 1].blk0) ++jb;
