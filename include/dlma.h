@@ -104,6 +104,30 @@ int dlma_gauge_info(dlma_gauge_t g, int dims_out[4], double* kappa_out, double* 
  */
 int dlma_apply_dw(dlma_gauge_t g, const void* in, void* out, int nrhs, int dagger, void* stream);
 
+/*
+ * The operator of the solver's inner iterations, for checking them: the
+ * Schur complement of D's even-odd blocks (the even-odd reduced system that
+ * dlma_solve iterates on; the paper needs D^-1 only, Sec. 2 and eq. (4)),
+ *   Dhat = A_ee - D_eo A_oo^-1 D_oe   on the even sites (t + z + y + x even),
+ * or Dhat^dag = g5 Dhat g5 (dagger = 1), applied by the inner stencil kernels of
+ * precision prec (DLMA_PREC_*).  The even sites of `in` are rounded to the
+ * storage precision (FP16: one FP32 scale per site), the links and clover
+ * matrices are the storage-precision copies, A_oo^-1 D_oe in is stored at that
+ * precision, and the result is rounded once more before it is widened to FP64.
+ *   in, out      device, [nrhs][T][Z][Y][X][4][3] complex128; must not overlap.
+ *                Odd sites of in are ignored; odd sites of out are set to 0.
+ *   rhs_block    right-hand sides per thread (1, 2, 4), or 0 for the launch shape
+ *                the solver's autotuner picks (super_group and lds_window ignored)
+ *   super_group  right-hand-side groups per super-group of the block order (0 = all)
+ *   lds_window   FP16 only: 1 = stage the +-x, +-y neighbours of each block through
+ *                LDS when they fit, 0 = read every neighbour from memory
+ * Synchronises the stream before returning.
+ * Errors: DLMA_EINVAL (handle, pointers, overlap, dagger, prec, rhs_block,
+ * super_group, lds_window), DLMA_ENOMEM, DLMA_EHIP.
+ */
+int dlma_apply_schur(dlma_gauge_t g, const void* in, void* out, int nrhs, int dagger, int prec, int rhs_block,
+                     int super_group, int lds_window, void* stream);
+
 typedef struct {
     double tol;        /* target true relative residual |b - D x|_2 / |b|_2, FP64 (e.g. 1e-10) */
     int maxiter;       /* cap on inner CG iterations per right-hand side, all passes together */

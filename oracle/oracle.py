@@ -120,6 +120,38 @@ def dirac(U, A, psi, dagger: bool = False) -> np.ndarray:
     return out
 
 
+def even_mask(dims) -> np.ndarray:
+    """[T][Z][Y][X]: 1.0 on even sites (t + z + y + x even), 0.0 on odd sites."""
+    T, Z, Y, X = dims
+    t, z, y, x = np.meshgrid(np.arange(T), np.arange(Z), np.arange(Y), np.arange(X), indexing="ij")
+    return ((t + z + y + x) % 2 == 0).astype(np.float64)
+
+
+def schur(U, A, psi, dagger: bool = False) -> np.ndarray:
+    """Even-odd reduced operator on the even sites of psi [n][T][Z][Y][X][4][3]:
+        Dhat psi_e = D_ee psi_e - D_eo D_oo^-1 D_oe psi_e,
+    the Schur complement of D's blocks between even and odd sites.  The hopping term
+    of D only links sites of opposite parity, so D_ee = A_ee and D_oo = A_oo.  With
+    dagger, the same complement of D^dag (whose odd-odd block is A_oo^dag).
+    Odd sites of psi are ignored; odd sites of the result are zero.
+
+    The paper needs only D^-1 (Sec. 2, eq. (4)); this is the definition of the
+    reduced system that an even-odd preconditioned solver iterates on (a reading:
+    the paper does not fix the solver), written out from the full operator."""
+    psi = _c(psi)
+    n, T, Z, Y, X = psi.shape[:5]
+    ev = even_mask((T, Z, Y, X))[None, :, :, :, :, None, None]
+    od = 1.0 - ev
+    xe = psi * ev
+    dx = dirac(U, A, xe, dagger)              # A_ee x_e on even sites, D_oe x_e on odd sites
+    Ainv = np.linalg.inv(_c(A).reshape(T, Z, Y, X, 12, 12))
+    if dagger:
+        Ainv = np.conj(np.swapaxes(Ainv, -1, -2))   # (A^dag)^-1
+    y = (dx * od).reshape(n, T, Z, Y, X, 12)
+    z = np.einsum("tzyxab,ntzyxb->ntzyxa", Ainv, y).reshape(psi.shape) * od   # D_oo^-1 D_oe x_e
+    return (dx - dirac(U, A, z, dagger)) * ev
+
+
 def solve(U, A, b, tol: float = 1e-10, maxiter: int = 20000, x0=None):
     """x = D^-1 b per right-hand side by CG on the normal equations (CGLS).
 

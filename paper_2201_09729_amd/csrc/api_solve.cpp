@@ -71,6 +71,7 @@ template <int P> struct Tables {
     int bresid = 0, bprep = 0, brecon = 0, bvnB = 0, bclov = 0, bconv = 0, bxpay = 0, bvnE = 0;
     int bk1 = 0, bk2 = 0, bfin = 0;
     int nb64 = 1;                      // right-hand sides per thread of the FP64 outer stencils
+    int wn = 0;                        // largest LDS window of the inner stencil jobs
     std::vector<FinJob> hfinI, hfinAB;  // kept for per-pass updates
 };
 
@@ -123,7 +124,7 @@ template <int P> int alloc_cfg(Cfg& c, hipStream_t s) {
 
 template <int P> float* nrm_of(const Buf& b) { return P == P16 ? b.as<float>() : nullptr; }
 
-template <int P> int build_tables(std::vector<Cfg>& cs, Tables<P>& t, int nb, int sg_in, int nb64, int sg64, hipStream_t s) {
+template <int P> int build_tables(std::vector<Cfg>& cs, Tables<P>& t, int nb, int sg_in, int win, int nb64, int sg64, hipStream_t s) {
     std::vector<HopJob<P64>> resid, prep, recon;
     std::vector<VecJob<P64>> vnB, clov, conv64, acc64, vnE;
     std::vector<VecJob<P>> conv, acc, xpay;
@@ -221,15 +222,16 @@ template <int P> int build_tables(std::vector<Cfg>& cs, Tables<P>& t, int nb, in
             SF<P> vp = half_view<P>(c.p.p, nrm_of<P>(c.np), Vh), vy = half_view<P>(c.y.p, nrm_of<P>(c.ny), Vh);
             SF<P> vw = half_view<P>(c.w.p, nrm_of<P>(c.nw), Vh), vr = half_view<P>(c.r.p, nrm_of<P>(c.nr), Vh);
             SF<P> vx = half_view<P>(c.xs.p, nrm_of<P>(c.nxs), Vh);
-            HopJob<P> j1 = hop_job<P>(g, 1, n, nb);
+            HopJob<P> j1 = hop_job<P>(g, 1, n, nb, win != 0);
             j1.U = U; j1.C = Cio; j1.ch = -0.5; j1.active = c.active; j1.sg = sg_in;
-            HopJob<P> j2 = hop_job<P>(g, 0, n, nb);
+            HopJob<P> j2 = hop_job<P>(g, 0, n, nb, win != 0);
             j2.U = U; j2.C = Cee; j2.ca = 1.0; j2.ch = 0.5; j2.active = c.active; j2.sg = sg_in;
             j2.part = c.part.as<double>(); j2.pstride = c.hnsb;
             HopJob<P> a = j1; a.in = vp; a.out = vy; k1d.push_back(a);
             HopJob<P> b = j2; b.x = vp; b.in = vy; b.out = vw; k2d.push_back(b);
             HopJob<P> d = j1; d.in = vw; d.out = vy; k1.push_back(d);
             HopJob<P> e = j2; e.x = vw; e.in = vy; e.r = vr; e.xs = vx; e.alpha = c.alpha; k2cg.push_back(e);
+            t.wn = std::max(t.wn, std::max(j1.wn, j2.wn));
         }
         FinJob f = {};
         f.nrhs = n; f.part = c.part.as<double>();
@@ -306,14 +308,14 @@ template <int P> int cg_iteration(std::vector<Cfg>& cs, Tables<P>& t, int nb, co
         }
     Cfg& c0 = cs[0];
     if (dbg) DLMA_TRY(debug_field<P>(c0, c0.p, c0.np, "p", s));
-    DLMA_TRY(hop_launch<P>(HopCfg{K1, F_G5IN, nb}, t.dk1d.p, t.nk, t.bk1, KC_K1DAG, b1, s));
+    DLMA_TRY(hop_launch<P>(HopCfg{K1, F_G5IN, nb, t.wn}, t.dk1d.p, t.nk, t.bk1, KC_K1DAG, b1, s));
     if (dbg) DLMA_TRY(debug_field<P>(c0, c0.y, c0.ny, "y1", s));
-    DLMA_TRY(hop_launch<P>(HopCfg{K2, F_G5OUT | F_NORM, nb}, t.dk2d.p, t.nk, t.bk2, KC_K2DAGN, b2, s));
+    DLMA_TRY(hop_launch<P>(HopCfg{K2, F_G5OUT | F_NORM, nb, t.wn}, t.dk2d.p, t.nk, t.bk2, KC_K2DAGN, b2, s));
     if (dbg) DLMA_TRY(debug_field<P>(c0, c0.w, c0.nw, "w", s));
     DLMA_HIP(launch_finish(t.dfinAB.template as<FinJob>(), t.nfin, t.bfin, FIN_ALPHA, s));
-    DLMA_TRY(hop_launch<P>(HopCfg{K1, 0, nb}, t.dk1.p, t.nk, t.bk1, KC_K1, b1, s));
+    DLMA_TRY(hop_launch<P>(HopCfg{K1, 0, nb, t.wn}, t.dk1.p, t.nk, t.bk1, KC_K1, b1, s));
     if (dbg) DLMA_TRY(debug_field<P>(c0, c0.y, c0.ny, "y2", s));
-    DLMA_TRY(hop_launch<P>(HopCfg{K2, F_CG, nb}, t.dk2cg.p, t.nk, t.bk2, KC_K2CG, b3, s));
+    DLMA_TRY(hop_launch<P>(HopCfg{K2, F_CG, nb, t.wn}, t.dk2cg.p, t.nk, t.bk2, KC_K2CG, b3, s));
     if (dbg) DLMA_TRY(debug_field<P>(c0, c0.r, c0.nr, "r", s));
     if (dbg) DLMA_TRY(debug_field<P>(c0, c0.xs, c0.nxs, "xs", s));
     DLMA_HIP(launch_finish(t.dfinAB.template as<FinJob>(), t.nfin, t.bfin, FIN_BETA, s));
@@ -353,7 +355,7 @@ int capture_iterations(std::vector<Cfg>& cs, Tables<P>& t, int nb, const std::ve
     return DLMA_OK;
 }
 
-struct Tune { int nb, sg; };
+struct Tune { int nb, sg, win; };  // win: FP16 stencils stage their LDS window
 template <int P> int tune_hop(Gauge* g, int nrhs, int fixed_nb, SF<P> vp, SF<P> vy, SF<P> vw, Tune& out, hipStream_t s);
 
 template <int P>
@@ -369,7 +371,7 @@ int solve_impl(std::vector<Cfg>& cs, const dlma_solve_opts& o, hipStream_t s) {
     size_t big = 0;
     for (size_t i = 1; i < cs.size(); ++i)
         if ((long)cs[i].g->Vh * cs[i].nrhs > (long)cs[big].g->Vh * cs[big].nrhs) big = i;
-    Tune tin{1, 0}, t64{1, 0};
+    Tune tin{1, 0, 1}, t64{1, 0, 0};
     {
         Cfg& c = cs[big];
         int Vh = c.g->Vh;
@@ -380,7 +382,7 @@ int solve_impl(std::vector<Cfg>& cs, const dlma_solve_opts& o, hipStream_t s) {
     }
     const int nb = tin.nb;
     Tables<P> t;
-    DLMA_TRY(build_tables<P>(cs, t, nb, tin.sg, t64.nb, t64.sg, s));
+    DLMA_TRY(build_tables<P>(cs, t, nb, tin.sg, tin.win, t64.nb, t64.sg, s));
     int ncfg = (int)cs.size();
     // load sources and start vectors
     for (auto& c : cs) {
@@ -501,20 +503,20 @@ int solve_impl(std::vector<Cfg>& cs, const dlma_solve_opts& o, hipStream_t s) {
 
 // Autotuner of the stencil launch shape: right-hand sides per thread (nb; fixed
 // when the caller gives one) and right-hand-side groups per super-group (sg, the
-// block order of hop_kernel).  Each candidate times the Schur pair K1 + K2 on the
-// caller's buffers (vp filled with random numbers): one warm-up and five timed
-// repetitions, median.  Results are cached per lattice, precision, right-hand
-// sides and fixed nb for the life of the process.
+// block order of hop_kernel); for FP16 fields also whether the stencils stage their
+// LDS window (tried for the best nb and sg).  Each candidate times the Schur pair
+// K1 + K2 on the caller's buffers (vp filled with random numbers): one warm-up and
+// five timed repetitions, median.  Results are cached per lattice, precision,
+// right-hand sides and fixed nb for the life of the process.
 template <int P> int tune_hop(Gauge* g, int nrhs, int fixed_nb, SF<P> vp, SF<P> vy, SF<P> vw, Tune& out, hipStream_t s) {
     const int key = P * 16 + fixed_nb;
     if (int v = tuned_lookup(g->dims, key, nrhs)) {
         out.nb = v & 255;
-        out.sg = v >> 8;
+        out.sg = (v >> 8) & 255;
+        out.win = v >> 16;
         return DLMA_OK;
     }
     DLMA_HIP(launch_fill_random<P>(vp, g->Vh, nrhs, 7u, s));
-    Tune best{1, 0};
-    float bt = 1e30f;
     struct Ev {  // released on every return path
         hipEvent_t e = nullptr;
         ~Ev() { if (e) (void)hipEventDestroy(e); }
@@ -522,6 +524,52 @@ template <int P> int tune_hop(Gauge* g, int nrhs, int fixed_nb, SF<P> vp, SF<P> 
     DLMA_HIP(hipEventCreate(&ev0.e));
     DLMA_HIP(hipEventCreate(&ev1.e));
     hipEvent_t e0 = ev0.e, e1 = ev1.e;
+    static const bool tlog = std::getenv("DLMA_LOG") != nullptr;
+    auto time_cfg = [&](const Tune& c, float& med) -> int {
+        std::vector<HopJob<P>> k1v, k2v;
+        HopJob<P> j1 = hop_job<P>(g, 1, nrhs, c.nb, c.win != 0);
+        j1.U = (const typename PT<P>::S*)gauge_links(g, P);
+        j1.C = (const typename PT<P>::S*)gauge_clover_oo_inv(g, P);
+        j1.ch = -0.5;
+        j1.in = vp;
+        j1.out = vy;
+        j1.sg = c.sg;
+        HopJob<P> j2 = hop_job<P>(g, 0, nrhs, c.nb, c.win != 0);
+        j2.U = j1.U;
+        j2.C = (const typename PT<P>::S*)gauge_clover_ee(g, P);
+        j2.ca = 1.0;
+        j2.ch = 0.5;
+        j2.x = vp;
+        j2.in = vy;
+        j2.out = vw;
+        j2.sg = c.sg;
+        k1v.push_back(j1);
+        k2v.push_back(j2);
+        int b1 = assign_blocks(k1v), b2 = assign_blocks(k2v);
+        Buf d1, d2;
+        DLMA_TRY(upload(d1, k1v, s));
+        DLMA_TRY(upload(d2, k2v, s));
+        std::vector<float> ts;
+        for (int rep = 0; rep < 6; ++rep) {
+            DLMA_HIP(hipEventRecord(e0, s));
+            DLMA_HIP(launch_hop<P>(HopCfg{K1, 0, c.nb, j1.wn}, d1.as<HopJob<P>>(), 1, b1, s));
+            DLMA_HIP(launch_hop<P>(HopCfg{K2, 0, c.nb, j2.wn}, d2.as<HopJob<P>>(), 1, b2, s));
+            DLMA_HIP(hipEventRecord(e1, s));
+            DLMA_HIP(hipEventSynchronize(e1));
+            float ms = 0;
+            DLMA_HIP(hipEventElapsedTime(&ms, e0, e1));
+            if (rep > 0) ts.push_back(ms);
+        }
+        DLMA_HIP(hipStreamSynchronize(s));
+        std::sort(ts.begin(), ts.end());
+        med = ts[ts.size() / 2];
+        if (tlog)
+            std::fprintf(stderr, "[dlma] tune prec %d nrhs %d Vh %d: nb %d sg %d window %d -> %.3f ms (K1+K2)\n", P, nrhs, g->Vh,
+                         c.nb, c.sg, j1.wn > 0 ? 1 : 0, med);
+        return DLMA_OK;
+    };
+    Tune best{1, 0, 1};
+    float bt = 1e30f;
     const int nbs[3] = {1, 2, 4};
     const int sgs[7] = {1, 2, 4, 8, 16, 32, 0};
     for (int nb : nbs) {
@@ -530,54 +578,20 @@ template <int P> int tune_hop(Gauge* g, int nrhs, int fixed_nb, SF<P> vp, SF<P> 
         const int G = ceil_div(nrhs, nb);
         for (int sg : sgs) {
             if (sg >= G) continue;  // same order as sg = 0 (all groups)
-            std::vector<HopJob<P>> k1v, k2v;
-            HopJob<P> j1 = hop_job<P>(g, 1, nrhs, nb);
-            j1.U = (const typename PT<P>::S*)gauge_links(g, P);
-            j1.C = (const typename PT<P>::S*)gauge_clover_oo_inv(g, P);
-            j1.ch = -0.5;
-            j1.in = vp;
-            j1.out = vy;
-            j1.sg = sg;
-            HopJob<P> j2 = hop_job<P>(g, 0, nrhs, nb);
-            j2.U = j1.U;
-            j2.C = (const typename PT<P>::S*)gauge_clover_ee(g, P);
-            j2.ca = 1.0;
-            j2.ch = 0.5;
-            j2.x = vp;
-            j2.in = vy;
-            j2.out = vw;
-            j2.sg = sg;
-            k1v.push_back(j1);
-            k2v.push_back(j2);
-            int b1 = assign_blocks(k1v), b2 = assign_blocks(k2v);
-            Buf d1, d2;
-            DLMA_TRY(upload(d1, k1v, s));
-            DLMA_TRY(upload(d2, k2v, s));
-            std::vector<float> ts;
-            for (int rep = 0; rep < 6; ++rep) {
-                DLMA_HIP(hipEventRecord(e0, s));
-                DLMA_HIP(launch_hop<P>(HopCfg{K1, 0, nb}, d1.as<HopJob<P>>(), 1, b1, s));
-                DLMA_HIP(launch_hop<P>(HopCfg{K2, 0, nb}, d2.as<HopJob<P>>(), 1, b2, s));
-                DLMA_HIP(hipEventRecord(e1, s));
-                DLMA_HIP(hipEventSynchronize(e1));
-                float ms = 0;
-                DLMA_HIP(hipEventElapsedTime(&ms, e0, e1));
-                if (rep > 0) ts.push_back(ms);
-            }
-            DLMA_HIP(hipStreamSynchronize(s));
-            std::sort(ts.begin(), ts.end());
-            float med = ts[ts.size() / 2];
-            static const bool tlog = std::getenv("DLMA_LOG") != nullptr;
-            if (tlog)
-                std::fprintf(stderr, "[dlma] tune prec %d nrhs %d Vh %d: nb %d sg %d -> %.3f ms (K1+K2)\n", P, nrhs, g->Vh, nb, sg,
-                             med);
+            float med = 0;
+            DLMA_TRY(time_cfg(Tune{nb, sg, 1}, med));
             if (med < bt) {
                 bt = med;
-                best = Tune{nb, sg};
+                best = Tune{nb, sg, 1};
             }
         }
     }
-    tuned_store(g->dims, key, nrhs, best.nb | (best.sg << 8));
+    if (P == P16 && hop_job<P>(g, 0, nrhs, best.nb).wn > 0) {
+        float med = 0;
+        DLMA_TRY(time_cfg(Tune{best.nb, best.sg, 0}, med));
+        if (med < bt) best.win = 0;
+    }
+    tuned_store(g->dims, key, nrhs, best.nb | (best.sg << 8) | (best.win << 16));
     out = best;
     return DLMA_OK;
 }
@@ -666,18 +680,18 @@ int bench_impl(Gauge* g, int nrhs, int nb, int napply, double* ms_out, double* b
     SF<P> va = half_view<P>(a.p, nrm_of<P>(na), Vh), vy = half_view<P>(y.p, nrm_of<P>(ny), Vh),
           vw = half_view<P>(w.p, nrm_of<P>(nw), Vh);
     DLMA_HIP(launch_fill_random<P>(va, Vh, nrhs, 11u, s));
-    Tune tn{nb ? nb : 1, 0};
+    Tune tn{nb ? nb : 1, 0, 1};
     DLMA_TRY(tune_hop<P>(g, nrhs, nb, va, vy, vw, tn, s));
     nb = tn.nb;
     DLMA_HIP(launch_fill_random<P>(va, Vh, nrhs, 11u, s));
     // alternate Dhat and Dhat^dag: a -> w -> a
     std::vector<HopJob<P>> j1f, j2f, j1b, j2b;
-    HopJob<P> j1 = hop_job<P>(g, 1, nrhs, nb);
+    HopJob<P> j1 = hop_job<P>(g, 1, nrhs, nb, tn.win != 0);
     j1.U = (const typename PT<P>::S*)gauge_links(g, P);
     j1.C = (const typename PT<P>::S*)gauge_clover_oo_inv(g, P);
     j1.ch = -0.5;
     j1.sg = tn.sg;
-    HopJob<P> j2 = hop_job<P>(g, 0, nrhs, nb);
+    HopJob<P> j2 = hop_job<P>(g, 0, nrhs, nb, tn.win != 0);
     j2.sg = tn.sg;
     j2.U = j1.U;
     j2.C = (const typename PT<P>::S*)gauge_clover_ee(g, P);
@@ -695,8 +709,8 @@ int bench_impl(Gauge* g, int nrhs, int nb, int napply, double* ms_out, double* b
     double by1 = hop_bytes(P, K1, 0, Vh, nrhs), by2 = hop_bytes(P, K2, 0, Vh, nrhs);
     auto run = [&](int k) -> int {
         bool fwd = (k & 1) == 0;
-        DLMA_TRY(hop_launch<P>(HopCfg{K1, fwd ? 0 : F_G5IN, nb}, (fwd ? d1f : d1b).p, 1, b1, fwd ? KC_K1 : KC_K1DAG, by1, s));
-        DLMA_TRY(hop_launch<P>(HopCfg{K2, fwd ? 0 : F_G5OUT, nb}, (fwd ? d2f : d2b).p, 1, b2, KC_K2, by2, s));
+        DLMA_TRY(hop_launch<P>(HopCfg{K1, fwd ? 0 : F_G5IN, nb, j1.wn}, (fwd ? d1f : d1b).p, 1, b1, fwd ? KC_K1 : KC_K1DAG, by1, s));
+        DLMA_TRY(hop_launch<P>(HopCfg{K2, fwd ? 0 : F_G5OUT, nb, j2.wn}, (fwd ? d2f : d2b).p, 1, b2, KC_K2, by2, s));
         return DLMA_OK;
     };
     DLMA_TRY(run(0));
@@ -725,6 +739,116 @@ int bench_impl(Gauge* g, int nrhs, int nb, int napply, double* ms_out, double* b
     return DLMA_OK;
 }
 }  // namespace
+
+// ---------------------------------------------------------------- Schur operator
+
+namespace {
+// out_e = Dhat in_e (or Dhat^dag in_e) with the inner stencils of precision P: the
+// even sites of `in` rounded to P at scale 1 by the solver's conversion kernel, the
+// solver's K1 and K2 launches, the result widened to FP64; odd sites of out are 0.
+template <int P>
+int schur_impl(Gauge* g, const void* in, void* out, int nrhs, int dagger, int nb, int sg, int win, hipStream_t s) {
+    DLMA_TRY(gauge_prepare(g, P, s));
+    const int Vh = g->Vh;
+    const size_t full64 = sizeof(double2) * (size_t)nrhs * 24 * Vh;
+    const size_t halfP = pair_bytes(P) * (size_t)nrhs * 12 * Vh;
+    const int vnsb = ceil_div(Vh, VEC_BS);
+    Buf a64, b64, a, y, w, na, ny, nw, ones, part;
+    DLMA_TRY(a64.allocate(full64));
+    DLMA_TRY(b64.allocate(full64));
+    DLMA_TRY(a.allocate(halfP));
+    DLMA_TRY(y.allocate(halfP));
+    DLMA_TRY(w.allocate(halfP));
+    if (P == P16) {
+        DLMA_TRY(na.allocate(sizeof(float) * nrhs * Vh));
+        DLMA_TRY(ny.allocate(sizeof(float) * nrhs * Vh));
+        DLMA_TRY(nw.allocate(sizeof(float) * nrhs * Vh));
+    }
+    DLMA_TRY(part.allocate(sizeof(double) * (size_t)nrhs * vnsb));
+    DLMA_TRY(upload(ones, std::vector<double>((size_t)nrhs, 1.0), s));
+    SF<P> va = half_view<P>(a.p, nrm_of<P>(na), Vh), vy = half_view<P>(y.p, nrm_of<P>(ny), Vh),
+          vw = half_view<P>(w.p, nrm_of<P>(nw), Vh);
+    if (nb == 0) {  // the solver's launch shape (the tuner overwrites va)
+        Tune tn{1, 0, 1};
+        DLMA_TRY(tune_hop<P>(g, nrhs, 0, va, vy, vw, tn, s));
+        nb = tn.nb;
+        sg = tn.sg;
+        win = tn.win;
+    }
+    DLMA_HIP(launch_canon_to_eo((const double2*)in, a64.as<double2>(), g->geo, nrhs, s));
+    VecJob<P> cv = {};
+    cv.Vh = Vh; cv.nrhs = nrhs; cv.nsb = vnsb;
+    cv.a = va; cv.b = vw; cv.c = vy;  // b and c are scratch here
+    cv.s = ones.as<double>();
+    cv.part = part.as<double>(); cv.pstride = vnsb;
+    VecJob<P64> cv64 = {};
+    cv64.Vh = Vh; cv64.nrhs = nrhs; cv64.nsb = vnsb;
+    cv64.a = full_view(a64.p, Vh, 0);
+    VecJob<P> ac = cv;
+    ac.a = vw;
+    VecJob<P64> ac64 = cv64;
+    ac64.a = full_view(b64.p, Vh, 0);
+    ac64.b = full_view(a64.p, Vh, 0);  // accumulator of the kernel, scratch here
+    std::vector<VecJob<P>> cvv{cv}, acv{ac};
+    std::vector<VecJob<P64>> cv64v{cv64}, ac64v{ac64};
+    const int bconv = assign_vec_blocks(cvv);
+    assign_vec_blocks(acv); assign_vec_blocks(cv64v); assign_vec_blocks(ac64v);
+    HopJob<P> j1 = hop_job<P>(g, 1, nrhs, nb, win != 0);
+    j1.U = (const typename PT<P>::S*)gauge_links(g, P);
+    j1.C = (const typename PT<P>::S*)gauge_clover_oo_inv(g, P);
+    j1.ch = -0.5;
+    j1.sg = sg;
+    j1.in = va;
+    j1.out = vy;
+    HopJob<P> j2 = hop_job<P>(g, 0, nrhs, nb, win != 0);
+    j2.U = j1.U;
+    j2.C = (const typename PT<P>::S*)gauge_clover_ee(g, P);
+    j2.ca = 1.0;
+    j2.ch = 0.5;
+    j2.sg = sg;
+    j2.x = va;
+    j2.in = vy;
+    j2.out = vw;
+    std::vector<HopJob<P>> k1v{j1}, k2v{j2};
+    const int b1 = assign_blocks(k1v), b2 = assign_blocks(k2v);
+    Buf dcv, dac, dcv64, dac64, d1, d2;
+    DLMA_TRY(upload(dcv, cvv, s)); DLMA_TRY(upload(dac, acv, s));
+    DLMA_TRY(upload(dcv64, cv64v, s)); DLMA_TRY(upload(dac64, ac64v, s));
+    DLMA_TRY(upload(d1, k1v, s)); DLMA_TRY(upload(d2, k2v, s));
+    DLMA_HIP(launch_conv_from64<P>(dcv.as<VecJob<P>>(), 1, bconv, dcv64.as<VecJob<P64>>(), s));
+    DLMA_HIP(launch_hop<P>(HopCfg{K1, dagger ? F_G5IN : 0, nb, j1.wn}, d1.as<HopJob<P>>(), 1, b1, s));
+    DLMA_HIP(launch_hop<P>(HopCfg{K2, dagger ? F_G5OUT : 0, nb, j2.wn}, d2.as<HopJob<P>>(), 1, b2, s));
+    DLMA_HIP(hipMemsetAsync(b64.p, 0, full64, s));
+    DLMA_HIP(launch_accum_to64<P>(dac.as<VecJob<P>>(), dac64.as<VecJob<P64>>(), 1, bconv, s));
+    DLMA_HIP(launch_eo_to_canon(b64.as<double2>(), (double2*)out, g->geo, nrhs, s));
+    DLMA_HIP(hipStreamSynchronize(s));
+    return DLMA_OK;
+}
+}  // namespace
+
+extern "C" int dlma_apply_schur(dlma_gauge_t h, const void* in, void* out, int nrhs, int dagger, int prec, int rhs_block,
+                                int super_group, int lds_window, void* stream) {
+    Gauge* g = (Gauge*)h;
+    if (!g) return fail(DLMA_EINVAL, "NULL handle");
+    if (nrhs < 0) return fail(DLMA_EINVAL, "nrhs < 0");
+    if (nrhs == 0) return DLMA_OK;
+    if (!in || !out) return fail(DLMA_EINVAL, "NULL field pointer");
+    const size_t bytes = sizeof(double2) * (size_t)nrhs * 24 * g->Vh;
+    const char *pi = (const char*)in, *po = (const char*)out;
+    if (pi < po + bytes && po < pi + bytes) return fail(DLMA_EINVAL, "in and out must not overlap");
+    if (dagger != 0 && dagger != 1) return fail(DLMA_EINVAL, "dagger must be 0 or 1");
+    if (rhs_block != 0 && rhs_block != 1 && rhs_block != 2 && rhs_block != 4) return fail(DLMA_EINVAL, "rhs_block must be 0, 1, 2 or 4");
+    if (super_group < 0) return fail(DLMA_EINVAL, "super_group must be >= 0");
+    if (lds_window != 0 && lds_window != 1) return fail(DLMA_EINVAL, "lds_window must be 0 or 1");
+    hipStream_t s = S(stream);
+    switch (prec) {
+    case DLMA_PREC_FP64: return schur_impl<P64>(g, in, out, nrhs, dagger, rhs_block, super_group, lds_window, s);
+    case DLMA_PREC_MIX_FP32: return schur_impl<P32>(g, in, out, nrhs, dagger, rhs_block, super_group, lds_window, s);
+    case DLMA_PREC_MIX_FP16: return schur_impl<P16>(g, in, out, nrhs, dagger, rhs_block, super_group, lds_window, s);
+    case DLMA_PREC_MIX_BF16: return schur_impl<PB16>(g, in, out, nrhs, dagger, rhs_block, super_group, lds_window, s);
+    default: return fail(DLMA_EINVAL, "prec must be one of DLMA_PREC_*");
+    }
+}
 
 extern "C" int dlma_bench_schur(dlma_gauge_t h, int prec, int nrhs, int rhs_block, int napply, double* ms_out,
                                 double* bytes_out, void* stream) {

@@ -52,6 +52,7 @@ template <int P> struct HopJob {
     const int* active;    // [nrhs] or nullptr: inactive right-hand sides are skipped
     double* part;         // partial squared norms (F_NORM / F_CG): part[r * pstride + site block]
     int pstride;
+    int wn;     // FP16 stencils: sites in the block's LDS window of +-x, +-y neighbours (0 = none)
     double ca, cb, ch;
 };
 
@@ -254,11 +255,11 @@ template <int BS> __device__ __forceinline__ double block_sum(double v, double* 
     return s;
 }
 
-// The per-site body for precision P: FP16 fields take the raw-word path of hop16.h.
+// The per-site body for the FP64, FP32 and BF16 fields (FP16 fields take the
+// raw-word path of hop16.h, called from the kernel directly).
 template <int P, int NB, int KIND, int FL>
 HD void site_body(const HopJob<P>& J, int cb, int g0, double (&nrm2)[NB]) {
-    if constexpr (P == P16) hop_site16<NB, KIND, FL>(J, cb, g0, nrm2);
-    else hop_site<P, NB, KIND, FL>(J, cb, g0, nrm2);
+    hop_site<P, NB, KIND, FL>(J, cb, g0, nrm2);
 }
 
 // Occupancy floor per instantiation: the FP16 kernels with up to two right-hand
@@ -266,9 +267,11 @@ HD void site_body(const HopJob<P>& J, int cb, int g0, double (&nrm2)[NB]) {
 // long-latency gathers need; the compiler's own choice lands just above it for some.
 template <int P, int NB> constexpr int hop_min_waves() { return (P == P16 && NB <= 2) ? 4 : 1; }
 
+// wn_cap: window sites per right-hand side that the launch's dynamic LDS holds
+// (NB * wn_cap * 52 bytes); a job stages its window only if it fits.
 template <int P, int NB, int KIND, int FL, int BS>
 __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(hop_min_waves<P, NB>())))
-hop_kernel(const HopJob<P>* __restrict__ jobs, int njob) {
+hop_kernel(const HopJob<P>* __restrict__ jobs, int njob, int wn_cap) {
     const int bid = blockIdx.x;
     int jb = 0;
     while (jb + 1 < njob && bid >= jobs[jb + 1].blk0) ++jb;
@@ -306,21 +309,29 @@ hop_kernel(const HopJob<P>* __restrict__ jobs, int njob) {
     // right-hand-side groups with nothing active skip the block (partials written as 0)
     bool live = false;
 #pragma unroll
-    for (int j = 0; j < NB; ++j) {
-        const int r = g0 + j;
-        live = live || (r < J.nrhs && (J.active == nullptr || J.active[r] != 0));
-    }
+    for (int j = 0; j < NB; ++j) live = live || rhs_active(J, g0 + j);
     if (!live) {
         if ((FL & (F_NORM | F_CG)) && threadIdx.x < NB && g0 + (int)threadIdx.x < J.nrhs)
             J.part[(size_t)(g0 + threadIdx.x) * J.pstride + sb] = 0.0;
         return;
     }
     double nrm2[NB];
-    if (sx < J.vt) {
-        site_body<P, NB, KIND, FL>(J, cb, g0, nrm2);
+    if constexpr (P == P16) {
+        // Every thread runs the body, whose LDS staging has a block barrier: a thread
+        // past the timeslice's last site works on that site and stores nothing.
+        extern __shared__ __attribute__((aligned(16))) uint32_t hop_window[];
+        const bool valid = sx < J.vt;
+        const int ts0 = t * J.vt;
+        const int wn = (J.wn > 0 && J.wn <= wn_cap) ? J.wn : 0;
+        const Window16 win{wn, ts0 + s * BS - J.g.Xh, ts0, ts0 + J.vt, (LdsWords)hop_window};
+        hop_site16<NB, KIND, FL, BS>(J, valid ? cb : ts0 + J.vt - 1, g0, valid, win, nrm2);
     } else {
+        if (sx < J.vt) {
+            site_body<P, NB, KIND, FL>(J, cb, g0, nrm2);
+        } else {
 #pragma unroll
-        for (int j = 0; j < NB; ++j) nrm2[j] = 0.0;
+            for (int j = 0; j < NB; ++j) nrm2[j] = 0.0;
+        }
     }
     if (FL & (F_NORM | F_CG)) {
         __shared__ double lds[BS / 64];

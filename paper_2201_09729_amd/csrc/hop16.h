@@ -115,6 +115,15 @@ HD int wave_uniform(int v) {
 #endif
 }
 
+// Whether right-hand side r of job J is still iterating.  Every branch here is on
+// a wave-uniform value (the flag is read once and marked uniform), so the values
+// that meet after it (field addresses, buffer resources) stay in scalar registers.
+template <class Job> HD bool rhs_active(const Job& J, int r) {
+    if (r >= J.nrhs) return false;
+    if (J.active == nullptr) return true;
+    return wave_uniform(J.active[r]) != 0;
+}
+
 // binary16 halves of a word, widened where they are consumed
 HD float lo16(uint32_t w) { return (float)__builtin_bit_cast(_Float16, (uint16_t)(w & 0xffffu)); }
 HD float hi16(uint32_t w) { return (float)__builtin_bit_cast(_Float16, (uint16_t)(w >> 16)); }
@@ -339,35 +348,124 @@ HD float store16(const F16Field& f, uint32_t G16, uint32_t site, const float s[2
     return q;
 }
 
-// ---------------------------------------------------------------- site body
+// ---------------------------------------------------------------- LDS window
 
-template <int NB, int MU, bool G5IN, bool G5OUT>
-HD void hop_dir16(const HopJob<P16>& J, const WSrc& U, const F16Field (&in)[NB], const Nbr& nb, uint32_t site,
-                  const bool (&use)[NB], const float (&sc)[NB], float (&acc)[NB][24]) {
-    const uint32_t Vh = (uint32_t)J.g.Vh;
-    uint32_t u[9], w[12];
-    const uint32_t nf = (uint32_t)nb.n[2 * MU], nbk = (uint32_t)nb.n[2 * MU + 1];
-    load_link16(U, 12u * site, 12u * Vh, J.par, MU, u);
+// The +-x and +-y neighbours of a block's sites lie within one y row of the block's
+// own site range on the same timeslice (except across the periodic y boundary).
+// The block copies that window of the input field into LDS once, with loads that
+// write LDS directly (no registers), and takes those four neighbours from there:
+// each input word then crosses the L1 data path, which bounds this stencil, about
+// 5 times per use instead of 8.  Sites: w0 .. w0 + wn - 1 (clamped to the timeslice
+// [lo, hi) when loaded: entries outside it are never read).  Layout per
+// right-hand side j: word groups g = 0..2 as planes of wn 16-byte entries at word
+// ((j*3 + g)*wn)*4, then the scales as planes of wn words at NB*12*wn + j*wn.
+#if defined(__HIP_DEVICE_COMPILE__)
+typedef __attribute__((address_space(3))) uint32_t* LdsWords;
+typedef __attribute__((address_space(3))) const u32x4* LdsQuads;
+#else
+typedef uint32_t* LdsWords;
+typedef const u32x4* LdsQuads;
+#endif
+struct Window16 {
+    int wn, w0, lo, hi;
+    LdsWords lds;
+};
+
+// Issues the window's loads for every right-hand side in use; the caller waits for
+// them (window_ready) before reading.  Each wave fills 64 consecutive entries of a
+// plane per load: the LDS address of lane l is the wave's base + l times the load size.
+template <int NB, int BS>
+HD void stage_window16(const Window16& W, const F16Field (&in)[NB], const bool (&use)[NB], uint32_t G16) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    const int lane = (int)threadIdx.x & 63;
+    for (int e0 = wave_uniform((int)threadIdx.x & ~63); e0 < W.wn; e0 += BS) {
+        const int e = e0 + lane;
+        if (e < W.wn) {
+            int site = W.w0 + e;
+            site = site < W.lo ? W.lo : (site >= W.hi ? W.hi - 1 : site);
 #pragma unroll
-    for (int j = 0; j < NB; ++j)
-        if (use[j]) {
-            load_words(in[j], 16u * nf, 16u * Vh, w);
-            const float n = wldf(in[j].n, 4u * nf, 0) * sc[j];
-            hop_term16<MU, true, G5IN, G5OUT>(u, w, n, acc[j]);
-        }
-    load_link16(U, 12u * nbk, 12u * Vh, 1 - J.par, MU, u);
+            for (int j = 0; j < NB; ++j)
+                if (use[j]) {
 #pragma unroll
-    for (int j = 0; j < NB; ++j)
-        if (use[j]) {
-            load_words(in[j], 16u * nbk, 16u * Vh, w);
-            const float n = wldf(in[j].n, 4u * nbk, 0) * sc[j];
-            hop_term16<MU, false, G5IN, G5OUT>(u, w, n, acc[j]);
+                    for (int g = 0; g < 3; ++g)
+                        __builtin_amdgcn_raw_ptr_buffer_load_lds(in[j].v.r, (__attribute__((address_space(3))) void*)(W.lds + ((j * 3 + g) * W.wn + e0) * 4),
+                                                                 16, 16 * site, g * (int)G16, 0, 0);
+                    __builtin_amdgcn_raw_ptr_buffer_load_lds(in[j].n.r, (__attribute__((address_space(3))) void*)(W.lds + NB * 12 * W.wn + j * W.wn + e0),
+                                                             4, 4 * site, 0, 0, 0);
+                }
         }
+    }
+#else
+    (void)W; (void)in; (void)use; (void)G16;
+#endif
 }
 
-// out = ... as in hop_site (hop.h) for P16 fields; nrm2 as there.
-template <int NB, int KIND, int FL>
-HD void hop_site16(const HopJob<P16>& J, int cb, int g0, double (&nrm2)[NB]) {
+// Makes the window visible to the block: every wave waits for its own LDS loads,
+// then the block meets.
+HD void window_ready() {
+#if defined(__HIP_DEVICE_COMPILE__)
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0); other counters unconstrained
+    __syncthreads();
+#endif
+}
+
+// Words and scale of neighbour site nsite of right-hand side j: from the window
+// when the site lies in it, else from the field.
+template <int NB>
+HD float window_words(const Window16& W, const F16Field& f, int j, uint32_t nsite, uint32_t G16, uint32_t w[12]) {
+    const uint32_t i = nsite - (uint32_t)W.w0;
+    const bool inw = i < (uint32_t)W.wn;
+    float n = 0.f;
+    if (W.wn > 0) {
+        const uint32_t li = inw ? i : 0u;
+#pragma unroll
+        for (int g = 0; g < 3; ++g) {
+            const u32x4 v = ((LdsQuads)W.lds)[(uint32_t)((j * 3 + g) * W.wn) + li];
+            w[4 * g] = v.x; w[4 * g + 1] = v.y; w[4 * g + 2] = v.z; w[4 * g + 3] = v.w;
+        }
+        n = __builtin_bit_cast(float, W.lds[(uint32_t)(NB * 12 * W.wn + j * W.wn) + li]);
+    }
+    if (!inw) {
+        load_words(f, 16u * nsite, G16, w);
+        n = wldf(f.n, 4u * nsite, 0);
+    }
+    return n;
+}
+
+// ---------------------------------------------------------------- site body
+
+// Both hops in direction MU; WIN: the neighbours come through the LDS window.
+template <int NB, int MU, bool G5IN, bool G5OUT, bool WIN>
+HD void hop_dir16(const HopJob<P16>& J, const WSrc& U, const F16Field (&in)[NB], const Nbr& nb, uint32_t site,
+                  const bool (&use)[NB], const float (&sc)[NB], const Window16& W, float (&acc)[NB][24]) {
+    const uint32_t Vh = (uint32_t)J.g.Vh;
+    uint32_t u[9], w[12];
+#pragma unroll
+    for (int d = 0; d < 2; ++d) {
+        const uint32_t ns = (uint32_t)nb.n[2 * MU + d];
+        // forward hop: the link of this site; backward: the neighbour's, of the other parity
+        load_link16(U, 12u * (d == 0 ? site : ns), 12u * Vh, d == 0 ? J.par : 1 - J.par, MU, u);
+#pragma unroll
+        for (int j = 0; j < NB; ++j)
+            if (use[j]) {
+                float n;
+                if (WIN) {
+                    n = window_words<NB>(W, in[j], j, ns, 16u * Vh, w);
+                } else {
+                    load_words(in[j], 16u * ns, 16u * Vh, w);
+                    n = wldf(in[j].n, 4u * ns, 0);
+                }
+                if (d == 0) hop_term16<MU, true, G5IN, G5OUT>(u, w, n * sc[j], acc[j]);
+                else hop_term16<MU, false, G5IN, G5OUT>(u, w, n * sc[j], acc[j]);
+            }
+    }
+}
+
+// out = ... as in hop_site (hop.h) for P16 fields; nrm2 as there.  Every thread of
+// the block calls it (W's staging has a block barrier); a thread with !valid works on
+// a real site but stores nothing and returns nrm2 = 0.
+template <int NB, int KIND, int FL, int BS>
+HD void hop_site16(const HopJob<P16>& J, int cb, int g0, bool valid, const Window16& W, double (&nrm2)[NB]) {
     const uint32_t G16 = 16u * (uint32_t)J.g.Vh;  // bytes per 16-byte group plane
     const uint32_t site = (uint32_t)cb, lo = 4u * site, s16 = 16u * site;
     constexpr bool G5IN = (FL & F_G5IN) != 0;
@@ -379,7 +477,7 @@ HD void hop_site16(const HopJob<P16>& J, int cb, int g0, double (&nrm2)[NB]) {
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
         const int r = g0 + j;
-        use[j] = wave_uniform(r < J.nrhs && (J.active == nullptr || J.active[r] != 0)) != 0;
+        use[j] = rhs_active(J, r);
         nrm2[j] = 0.0;
         in[j] = f16_field(J.in, J.g.Vh, r);
         al[j] = CG ? (float)J.alpha[r < J.nrhs ? r : 0] : 0.f;
@@ -394,10 +492,13 @@ HD void hop_site16(const HopJob<P16>& J, int cb, int g0, double (&nrm2)[NB]) {
 
     const WSrc U = wsrc(J.U, 288u * (uint32_t)J.g.Vh);
     const Nbr nb = neighbours(J.g, J.par, cb);
-    hop_dir16<NB, 0, G5IN, G5OUT>(J, U, in, nb, site, use, sc, acc);
-    hop_dir16<NB, 1, G5IN, G5OUT>(J, U, in, nb, site, use, sc, acc);
-    hop_dir16<NB, 2, G5IN, G5OUT>(J, U, in, nb, site, use, sc, acc);
-    hop_dir16<NB, 3, G5IN, G5OUT>(J, U, in, nb, site, use, sc, acc);
+    // the window's loads fly while the t and z hops run on loads of their own
+    if (W.wn > 0) stage_window16<NB, BS>(W, in, use, G16);
+    hop_dir16<NB, 0, G5IN, G5OUT, false>(J, U, in, nb, site, use, sc, W, acc);
+    hop_dir16<NB, 3, G5IN, G5OUT, false>(J, U, in, nb, site, use, sc, W, acc);
+    if (W.wn > 0) window_ready();
+    hop_dir16<NB, 1, G5IN, G5OUT, true>(J, U, in, nb, site, use, sc, W, acc);
+    hop_dir16<NB, 2, G5IN, G5OUT, true>(J, U, in, nb, site, use, sc, W, acc);
 
     const WSrc C = wsrc(J.C, 10u * G16);
     if (KIND == K1) {
@@ -445,8 +546,10 @@ HD void hop_site16(const HopJob<P16>& J, int cb, int g0, double (&nrm2)[NB]) {
                         acc[j][2 * c + 1] = __builtin_fmaf(hi16(w), n, acc[j][2 * c + 1]);
                     }
                 }
-                const float q = store16(o, G16, site, acc[j]);
-                if (FL & F_NORM) nrm2[j] = (double)q;
+                if (valid) {
+                    const float q = store16(o, G16, site, acc[j]);
+                    if (FL & F_NORM) nrm2[j] = (double)q;
+                }
             }
     } else {
         // clover (or identity) term on x: acc += ca' * n_x * (A x^)
@@ -509,7 +612,7 @@ HD void hop_site16(const HopJob<P16>& J, int cb, int g0, double (&nrm2)[NB]) {
                         acc[j][2 * c] = __builtin_fmaf(lo16(w), nr, acc[j][2 * c]);
                         acc[j][2 * c + 1] = __builtin_fmaf(hi16(w), nr, acc[j][2 * c + 1]);
                     }
-                    nrm2[j] = (double)store16(rf, G16, site, acc[j]);
+                    if (valid) nrm2[j] = (double)store16(rf, G16, site, acc[j]);
                     // xs += alpha x
                     const F16Field sf = f16_field(J.xs, J.g.Vh, g0 + j);
                     const float ns = wldf<CP_NT>(sf.n, lo, 0), ax = al[j] * nx[j];
@@ -520,8 +623,8 @@ HD void hop_site16(const HopJob<P16>& J, int cb, int g0, double (&nrm2)[NB]) {
                         acc[j][2 * c] = __builtin_fmaf(lo16(xw[j][c]), ax, __builtin_fmaf(lo16(w), ns, 0.f));
                         acc[j][2 * c + 1] = __builtin_fmaf(hi16(xw[j][c]), ax, __builtin_fmaf(hi16(w), ns, 0.f));
                     }
-                    (void)store16(sf, G16, site, acc[j]);
-                } else {
+                    if (valid) (void)store16(sf, G16, site, acc[j]);
+                } else if (valid) {
                     const F16Field o = f16_field(J.out, J.g.Vh, g0 + j);
                     const float q = store16(o, G16, site, acc[j]);
                     if (FL & F_NORM) nrm2[j] = (double)q;

@@ -8,7 +8,7 @@ namespace dlma {
 #define DLMA_HOP_CASE(KIND, FL, NB)                                                                   \
     if (c.kind == (KIND) && c.flags == (FL) && c.nb == (NB)) {                                      \
         hipLaunchKernelGGL((hop_kernel<DLMA_PREC, NB, KIND, (FL), HOP_BS>), dim3(nblocks), dim3(HOP_BS), \
-                           0, s, djobs, njob);                                                       \
+                           hop_window_bytes(NB, wn), s, djobs, njob, wn);                            \
         return hipGetLastError();                                                                    \
     }
 
@@ -20,6 +20,7 @@ namespace dlma {
 template <>
 hipError_t launch_hop<DLMA_PREC>(const HopCfg& c, const HopJob<DLMA_PREC>* djobs, int njob, int nblocks, hipStream_t s) {
     if (nblocks <= 0) return hipSuccess;
+    const int wn = DLMA_PREC == P16 ? c.wn : 0;  // LDS window of the FP16 stencils
     // Schur operator and the fused CG steps
     DLMA_HOP_ALLNB(K1, 0)
     DLMA_HOP_ALLNB(K1, F_G5IN)

@@ -35,8 +35,18 @@ struct FinJob {
 };
 enum FinMode { FIN_NORM = 0, FIN_ALPHA = 1, FIN_BETA = 2, FIN_INIT = 3 };
 
-struct HopCfg { int kind, flags, nb; };
+// wn: LDS window sites per right-hand side of the launch's FP16 jobs (the largest
+// HopJob::wn among them; 0 = none, and always 0 for other precisions)
+struct HopCfg { int kind, flags, nb, wn = 0; };
 constexpr int HOP_BS = 128;
+
+// Dynamic LDS of an FP16 stencil launch: per right-hand side and window site, three
+// 16-byte word groups and the 4-byte scale.
+constexpr unsigned hop_window_bytes(int nb, int wn) { return (unsigned)(nb * wn * 52); }
+// Largest dynamic LDS a stencil block may take: with up to two right-hand sides per
+// thread, eight blocks of two waves (four waves per SIMD) share a CU's 160 KiB; with
+// four, the registers allow two waves per SIMD and four blocks.
+constexpr int hop_window_max_bytes(int nb) { return nb <= 2 ? 20 * 1024 : 40 * 1024; }
 
 template <int P> hipError_t launch_hop(const HopCfg& c, const HopJob<P>* djobs, int njob, int nblocks, hipStream_t s);
 

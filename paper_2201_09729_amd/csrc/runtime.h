@@ -103,7 +103,8 @@ inline int ceil_div(long a, long b) { return (int)((a + b - 1) / b); }
 // site blocks of a stencil launch: whole blocks per timeslice (see the block decode)
 inline int hop_nsb(const Geo& g) { return g.T * ceil_div(g.Z * g.Y * g.Xh, HOP_BS); }
 
-template <int P> HopJob<P> hop_job(const Gauge* g, int par, int nrhs, int nb) {
+// window: FP16 stencils may stage the +-x, +-y neighbours through LDS (when they fit)
+template <int P> HopJob<P> hop_job(const Gauge* g, int par, int nrhs, int nb, bool window = true) {
     HopJob<P> j = {};
     j.g = g->geo;
     j.par = par;
@@ -114,6 +115,9 @@ template <int P> HopJob<P> hop_job(const Gauge* g, int par, int nrhs, int nb) {
     j.nsb = hop_nsb(g->geo);
     j.nxb = ceil_div(g->geo.T, 8) * j.nbt;
     j.pstride = j.nsb;
+    // FP16 stencils: the block's sites and one y row on either side, if LDS has room
+    const int wn = HOP_BS + 2 * g->geo.Xh;
+    j.wn = (window && P == P16 && (int)hop_window_bytes(nb, wn) <= hop_window_max_bytes(nb)) ? wn : 0;
     return j;
 }
 

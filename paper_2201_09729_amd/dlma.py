@@ -77,6 +77,7 @@ def load_library(path: str = LIB_PATH):
         "dlma_free_gauge": ([P], I),
         "dlma_gauge_info": ([P, P, P, P], I),
         "dlma_apply_dw": ([P, P, P, I, I, P], I),
+        "dlma_apply_schur": ([P, P, P, I, I, I, I, I, I, P], I),
         "dlma_solve_opts_default": ([P], None),
         "dlma_solve": ([P, I, P, P, P, P], I),
         "dlma_lap_eigs": ([P, I, I, I, P, P, P, P, P], I),
@@ -164,6 +165,19 @@ def dlma_apply_dw(g: Gauge, x: torch.Tensor, dagger: bool = False) -> torch.Tens
     n = x.shape[0]
     _check(load_library().dlma_apply_dw(g.h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
                                         int(n), int(bool(dagger)), _stream()))
+    return out
+
+
+def dlma_apply_schur(g: Gauge, x: torch.Tensor, dagger: bool = False, prec="mix_fp16", rhs_block: int = 0,
+                     super_group: int = 0, lds_window: bool = True) -> torch.Tensor:
+    """Dhat x_e (or Dhat^dag x_e) through the solver's inner stencils of precision prec,
+    x of shape [n][T][Z][Y][X][4][3] (complex128, GPU); odd sites of the result are 0."""
+    x = _dev(x)
+    out = torch.empty_like(x)
+    p = PREC[prec] if isinstance(prec, str) else int(prec)
+    _check(load_library().dlma_apply_schur(g.h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                           int(x.shape[0]), int(bool(dagger)), p, int(rhs_block), int(super_group),
+                                           int(bool(lds_window)), _stream()))
     return out
 
 

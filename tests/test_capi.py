@@ -53,6 +53,7 @@ def test_argument_validation_without_gpu(lib):
     assert lib.dlma_load_gauge(d, None, ctypes.c_double(0.12), ctypes.c_double(1.0), None, ctypes.byref(h)) == -1
     assert lib.dlma_solve(None, 1, None, None, None, None) == -1
     assert lib.dlma_apply_dw(None, None, None, 1, 0, None) == -1
+    assert lib.dlma_apply_schur(None, None, None, 1, 0, 2, 0, 0, 1, None) == -1
     assert lib.dlma_lap_eigs(None, 4, 0, 1, None, None, None, None, None) == -1
     assert lib.dlma_project(None, 0, 1, None, None, None, 1, 0, None) == -1
     assert lib.dlma_correlators(None, 0, 1, None, None, 0, 1, None, None, None, None) == -1
