@@ -141,6 +141,8 @@ typedef struct {
                           Direct launches are also used while dlma_profile_enable is on. */
     int check_every;   /* CG iterations between host convergence checks (>= 1); 0 = default */
     int dagger;        /* 1: solve D^dag x = b (x = g5 D^-1 g5 b), the adjoint solve of a backward pass */
+    int lds_window;    /* FP16 stencils stage their +-x, +-y neighbours through LDS: -1 = autotuned
+                          (with rhs_block), 0 = never, 1 = when they fit */
 } dlma_solve_opts;
 
 /* Fill opts with the defaults (tol 1e-10, FP64, autotuned blocks, graph_iters 8, ...). */

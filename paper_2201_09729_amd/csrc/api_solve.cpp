@@ -35,6 +35,7 @@ extern "C" void dlma_solve_opts_default(dlma_solve_opts* o) {
     o->graph_iters = 8;
     o->check_every = 0;
     o->dagger = 0;
+    o->lds_window = -1;
 }
 
 namespace {
@@ -380,6 +381,7 @@ int solve_impl(std::vector<Cfg>& cs, const dlma_solve_opts& o, hipStream_t s) {
         DLMA_TRY(tune_hop<P64>(c.g, c.nrhs, 0, half_view<P64>(c.E.p, nullptr, Vh), half_view<P64>(c.T.p, nullptr, Vh),
                                full_view(c.R.p, Vh, 0), t64, s));
     }
+    if (o.lds_window >= 0) tin.win = o.lds_window;
     const int nb = tin.nb;
     Tables<P> t;
     DLMA_TRY(build_tables<P>(cs, t, nb, tin.sg, tin.win, t64.nb, t64.sg, s));
@@ -610,6 +612,7 @@ extern "C" int dlma_solve(const dlma_gauge_t* gs, int ngauge, const dlma_rhs_set
     if (o.inner_tol < 0 || o.inner_tol >= 1) return fail(DLMA_EINVAL, "inner_tol must be in [0, 1)");
     if (o.check_every < 0 || o.graph_iters < 0) return fail(DLMA_EINVAL, "check_every and graph_iters must be >= 0");
     if (o.dagger != 0 && o.dagger != 1) return fail(DLMA_EINVAL, "dagger must be 0 or 1");
+    if (o.lds_window < -1 || o.lds_window > 1) return fail(DLMA_EINVAL, "lds_window must be -1, 0 or 1");
     std::vector<Cfg> cs;
     cs.reserve(ngauge);
     int total = 0;

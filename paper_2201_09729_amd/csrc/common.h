@@ -49,6 +49,25 @@ HD float h_to_f(uint32_t bits16) {
 }
 HD uint32_t f_to_h(float f) { return (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)f); }
 
+// Scheduling fences around a group of vector-memory stores with more than 64 bits of
+// data each, closed by two wait states.  Such a store reads its data registers after
+// it issues; a vector ALU instruction that overwrites them in the next cycle corrupts
+// the stored value, and the compiler in use emits that sequence without the wait
+// state (seen as stored values that changed from run to run).  The build checks the
+// machine code of every kernel for the pattern.
+HD void wide_store_begin() {
+#if defined(__HIP_DEVICE_COMPILE__)
+    __builtin_amdgcn_sched_barrier(0);
+#endif
+}
+HD void wide_store_end() {
+#if defined(__HIP_DEVICE_COMPILE__)
+    __builtin_amdgcn_sched_barrier(0);
+    __asm__ volatile("s_nop 1");
+    __builtin_amdgcn_sched_barrier(0);
+#endif
+}
+
 // load / store one complex element
 template <int P> HD void ldp(const typename PT<P>::S* a, size_t i, typename PT<P>::R& re, typename PT<P>::R& im);
 template <> HD void ldp<P64>(const double2* a, size_t i, double& re, double& im) { double2 v = a[i]; re = v.x; im = v.y; }

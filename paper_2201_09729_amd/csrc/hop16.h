@@ -343,8 +343,10 @@ HD float store16(const F16Field& f, uint32_t G16, uint32_t site, const float s[2
         q = __builtin_fmaf(s[2 * c], s[2 * c], q);
         q = __builtin_fmaf(s[2 * c + 1], s[2 * c + 1], q);
     }
+    wide_store_begin();
 #pragma unroll
     for (int g = 0; g < 3; ++g) wst4(f.v, 16u * site, (uint32_t)g * G16, (u32x4){w[4 * g], w[4 * g + 1], w[4 * g + 2], w[4 * g + 3]});
+    wide_store_end();
     return q;
 }
 

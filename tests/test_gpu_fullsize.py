@@ -171,10 +171,19 @@ def test_headline_launch_configuration(D, orc):
     eta = D.noise_sources(cu(synth.z2_noise(dims, t0, nn, 1006)), T, t0)
     b = torch.cat([D.dist_sources(V[0], T, t0), eta, D.dlma_project(g, t0, V[0], eta, 1)])
     del eta
+    # one defect-correction pass brings every right-hand side to the inner tolerance's
+    # level (2e-3): a corrupted store in the solution update of some RHS shows as a
+    # few times worse residuals there and extra passes
+    opts1 = D.default_opts(tol=TOL, prec="mix_fp16", rhs_block=2, max_outer=1)
+    _, st1 = D.dlma_solve([g], [b], opts=opts1, allow_notconv=True)
+    worst = max(s["relres"] for s in st1)
+    print("one pass: worst relres %.3e" % worst, flush=True)
+    assert worst <= 5e-3, worst
     opts = D.default_opts(tol=TOL, prec="mix_fp16", rhs_block=2)
     (x,), st = D.dlma_solve([g], [b], opts=opts)
     assert len(st) == 192
     assert all(s["converged"] and s["relres"] <= TOL for s in st)
+    assert max(s["outer"] for s in st) <= 5, sorted(set(s["outer"] for s in st))
     A = orc.clover(U, kappa, csw)
     for i in (0, 63, 127, 128, 159, 160, 191):
         assert oracle_relres(orc, U, A, x[i].cpu().numpy(), b[i].cpu().numpy()) <= TOL * RES_SLACK, i
