@@ -460,7 +460,7 @@ def summarize(args):
 
     def hop_name(kc, nb):
         kind, fl = KTEMPLATE[kc]
-        return "void dlma::hop_kernel<%d, %d, %d, %d, 128>(dlma::HopJob<%d> const*, int)" % (pid, nb, kind, fl, pid)
+        return "void dlma::hop_kernel<%d, %d, %d, %d, 128>(dlma::HopJob<%d> const*, int, int)" % (pid, nb, kind, fl, pid)
 
     by_name = {r["Name"]: r for r in stats}
     nb = args.rhs_block
