@@ -116,7 +116,7 @@ int dlma_apply_dw(dlma_gauge_t g, const void* in, void* out, int nrhs, int dagge
  * precision, and the result is rounded once more before it is widened to FP64.
  *   in, out      device, [nrhs][T][Z][Y][X][4][3] complex128; must not overlap.
  *                Odd sites of in are ignored; odd sites of out are set to 0.
- *   rhs_block    right-hand sides per thread (1, 2, 4), or 0 for the launch shape
+ *   rhs_block    right-hand sides per thread (1 .. 4), or 0 for the launch shape
  *                the solver's autotuner picks (super_group and lds_window ignored)
  *   super_group  right-hand-side groups per super-group of the block order (0 = all)
  *   lds_window   FP16 only: 1 = stage the +-x, +-y neighbours of each block through
@@ -134,7 +134,7 @@ typedef struct {
     int max_outer;     /* cap on defect-correction passes */
     int prec;          /* DLMA_PREC_* */
     double inner_tol;  /* relative reduction of the inner residual per pass; 0 = default */
-    int rhs_block;     /* right-hand sides per thread in the stencil kernels: 0 = autotune, 1, 2 or 4 */
+    int rhs_block;     /* right-hand sides per thread in the stencil kernels: 0 = autotune, or 1 .. 4 */
     int use_x0;        /* 1: x holds the start vector on entry; 0: start from x = 0 */
     int graph_iters;   /* inner CG iterations captured in one hipGraph and replayed between host
                           convergence checks (replaces check_every); 0 = direct launches.
@@ -276,7 +276,7 @@ int dlma_profile_read(int kclass, long long* launches, double* total_ms, double*
 /*
  * Apply the Schur operator Dhat (and Dhat^dag alternately) napply times to nrhs
  * internal random vectors in precision prec (DLMA_PREC_*: FP64, FP32, FP16, BF16
- * storage), rhs_block right-hand sides per thread (1, 2, 4; 0 = autotuned).
+ * storage), rhs_block right-hand sides per thread (1 .. 4; 0 = autotuned).
  * Returns milliseconds per application in ms_out (host) and algorithmic bytes per
  * application in bytes_out (host).  For bandwidth measurements.
  */

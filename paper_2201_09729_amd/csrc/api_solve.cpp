@@ -365,8 +365,8 @@ int solve_impl(std::vector<Cfg>& cs, const dlma_solve_opts& o, hipStream_t s) {
         DLMA_TRY(gauge_prepare(c.g, P, s));
         DLMA_TRY(alloc_cfg<P>(c, s));
     }
-    if (o.rhs_block != 0 && o.rhs_block != 1 && o.rhs_block != 2 && o.rhs_block != 4)
-        return fail(DLMA_EINVAL, "rhs_block must be 0, 1, 2 or 4");
+    if (o.rhs_block < 0 || o.rhs_block > 4)
+        return fail(DLMA_EINVAL, "rhs_block must be 0 .. 4");
     // launch shapes, tuned on the largest configuration: inner stencils (precision P) and
     // the FP64 outer stencils (one right-hand side per thread)
     size_t big = 0;
@@ -572,7 +572,7 @@ template <int P> int tune_hop(Gauge* g, int nrhs, int fixed_nb, SF<P> vp, SF<P> 
     };
     Tune best{1, 0, 1};
     float bt = 1e30f;
-    const int nbs[3] = {1, 2, 4};
+    const int nbs[4] = {1, 2, 3, 4};
     const int sgs[7] = {1, 2, 4, 8, 16, 32, 0};
     for (int nb : nbs) {
         if (fixed_nb && nb != fixed_nb) continue;
@@ -840,7 +840,7 @@ extern "C" int dlma_apply_schur(dlma_gauge_t h, const void* in, void* out, int n
     const char *pi = (const char*)in, *po = (const char*)out;
     if (pi < po + bytes && po < pi + bytes) return fail(DLMA_EINVAL, "in and out must not overlap");
     if (dagger != 0 && dagger != 1) return fail(DLMA_EINVAL, "dagger must be 0 or 1");
-    if (rhs_block != 0 && rhs_block != 1 && rhs_block != 2 && rhs_block != 4) return fail(DLMA_EINVAL, "rhs_block must be 0, 1, 2 or 4");
+    if (rhs_block < 0 || rhs_block > 4) return fail(DLMA_EINVAL, "rhs_block must be 0 .. 4");
     if (super_group < 0) return fail(DLMA_EINVAL, "super_group must be >= 0");
     if (lds_window != 0 && lds_window != 1) return fail(DLMA_EINVAL, "lds_window must be 0 or 1");
     hipStream_t s = S(stream);
@@ -858,7 +858,7 @@ extern "C" int dlma_bench_schur(dlma_gauge_t h, int prec, int nrhs, int rhs_bloc
     Gauge* g = (Gauge*)h;
     if (!g) return fail(DLMA_EINVAL, "NULL handle");
     if (nrhs < 1 || napply < 1) return fail(DLMA_EINVAL, "nrhs and napply must be >= 1");
-    if (rhs_block != 0 && rhs_block != 1 && rhs_block != 2 && rhs_block != 4) return fail(DLMA_EINVAL, "rhs_block must be 0, 1, 2 or 4");
+    if (rhs_block < 0 || rhs_block > 4) return fail(DLMA_EINVAL, "rhs_block must be 0 .. 4");
     hipStream_t s = S(stream);
     switch (prec) {
     case DLMA_PREC_FP64: return bench_impl<P64>(g, nrhs, rhs_block, napply, ms_out, bytes_out, s);

@@ -15,6 +15,7 @@ namespace dlma {
 #define DLMA_HOP_ALLNB(KIND, FL) \
     DLMA_HOP_CASE(KIND, FL, 1)   \
     DLMA_HOP_CASE(KIND, FL, 2)   \
+    DLMA_HOP_CASE(KIND, FL, 3)   \
     DLMA_HOP_CASE(KIND, FL, 4)
 
 template <>

@@ -58,7 +58,7 @@ def test_set_mass_matches_oracle(D, orc):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mix_fp32", "mix_fp16", "mix_bf16"])
-@pytest.mark.parametrize("rhs_block", [1, 2, 4])
+@pytest.mark.parametrize("rhs_block", [1, 2, 3, 4])
 def test_solve_true_residual(D, orc, prec, rhs_block):
     """8^3x16, kappa 0.120, csw 1.0: five right-hand sides (ragged for blocks of 2 and 4);
     the oracle re-evaluates |b - D x_gpu| / |b| <= 1e-10 for every precision."""

@@ -75,7 +75,7 @@ def _errors(y, ref):
 @pytest.mark.parametrize("case", LATTICES, ids=["4x6x10x12", "8x4x4x4", "4x8x8x20"])
 def test_schur_operator_matches_oracle(D, orc, case, dagger):
     dims, eps, seed, kappa, csw = case
-    nrhs = 5  # ragged for 2 and 4 right-hand sides per thread
+    nrhs = 5  # ragged for 2, 3 and 4 right-hand sides per thread
     U = synth.gauge_field(dims, eps, seed)
     x = synth.random_spinor(dims, nrhs, seed + 50)
     ref = orc.schur(U, orc.clover(U, kappa, csw), x, dagger=dagger)
@@ -84,7 +84,7 @@ def test_schur_operator_matches_oracle(D, orc, case, dagger):
     xd = cu(x)
     for prec, tol in TOL.items():
         outs = {}
-        for nb in (1, 2, 4):
+        for nb in (1, 2, 3, 4):
             for sg in (0, 1, 2):
                 for win in ((True, False) if prec == "mix_fp16" else (True,)):
                     print("schur", dims, "dagger", dagger, prec, "nb", nb, "sg", sg, "window", win, flush=True)
