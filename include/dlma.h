@@ -185,6 +185,10 @@ typedef struct {
     int max_basis;     /* cap on the Krylov dimension (0 = default) */
     int check_every;   /* Lanczos steps between convergence checks (0 = default) */
     int cheb_degree;   /* degree of the Chebyshev filter; 0 = automatic (none for 3 L^3 < 4096), < 0 = off */
+    int restart_basis; /* thick restart: basis size at which the Lanczos run keeps its best Ritz vectors
+                          and continues (0 = no restarts: the basis grows to max_basis) */
+    int restart_keep;  /* Ritz vectors kept per restart, nev < keep < restart_basis (0 = nev + half the rest) */
+    int max_restarts;  /* cap on restarts (0 = 200) */
 } dlma_eig_opts;
 
 /*
@@ -195,7 +199,10 @@ typedef struct {
  * Lanczos operator is a Chebyshev polynomial p(-lap) that damps the spectrum
  * above a cut estimated from a short unfiltered run (p has the same eigenvectors;
  * the eigenvalues returned are Rayleigh quotients of lap itself, and the
- * stopping test is the explicit residual |lap v - lambda v|).
+ * stopping test is the explicit residual |lap v - lambda v|).  With
+ * opts->restart_basis the run is thick-restarted: the basis never exceeds that
+ * many vectors, and each restart keeps the best Ritz vectors and the last Lanczos
+ * vector (the projected matrix becomes arrowhead plus tridiagonal).
  *   v0       device, [nt][Z][Y][X][3] complex128 start vectors (any nonzero vectors)
  *   V_out    device, [nt][nev][Z][Y][X][3] complex128 orthonormal eigenvectors; the
  *            component of largest modulus of each vector is real and positive

@@ -24,11 +24,14 @@ namespace {
 // as a chase of plane rotations from the bottom of the unreduced block upwards,
 // with deflation when an off-diagonal element becomes negligible.
 //   Z (m x m, row-major) receives the eigenvector matrix (columns), last its last row.
-bool tridiag_ql(std::vector<double>& d, std::vector<double> e, std::vector<double>* Z, std::vector<double>* last) {
+// zinit: Z holds an orthogonal matrix Q on entry and receives Q times the
+// eigenvector matrix (the back-transformation of a reduction to tridiagonal form).
+bool tridiag_ql(std::vector<double>& d, std::vector<double> e, std::vector<double>* Z, std::vector<double>* last,
+                bool zinit = false) {
     const int n = (int)d.size();
     e.resize(n, 0.0);
     e[n - 1] = 0.0;
-    if (Z) {
+    if (Z && !zinit) {
         Z->assign((size_t)n * n, 0.0);
         for (int i = 0; i < n; ++i) (*Z)[(size_t)i * n + i] = 1.0;
     }
@@ -92,6 +95,65 @@ bool tridiag_ql(std::vector<double>& d, std::vector<double> e, std::vector<doubl
     return true;
 }
 
+// Eigenpairs of a dense real symmetric matrix A (n x n, row-major): Householder
+// reflections reduce A to tridiagonal form T = Q^T A Q, working from the last row
+// upwards (the reflection of step i zeroes A[i][0..i-2] and acts on indices < i),
+// and the implicit QL iteration of tridiag_ql diagonalises T, its rotations applied
+// to Q.  d receives the eigenvalues, Z (row-major) the eigenvectors as columns.
+bool sym_eig(std::vector<double> A, int n, std::vector<double>& d, std::vector<double>& Z) {
+    std::vector<double> e(n, 0.0), v(n), p(n);
+    Z.assign((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i) Z[(size_t)i * n + i] = 1.0;
+    for (int i = n - 1; i >= 2; --i) {
+        double* ai = &A[(size_t)i * n];
+        double sc = 0;
+        for (int k = 0; k < i; ++k) sc += ai[k] * ai[k];
+        double x = std::sqrt(sc);
+        if (x == 0.0) { e[i - 1] = 0.0; continue; }
+        // reflection H = 1 - v v^T / h on indices 0..i-1 mapping row i's part onto e_{i-1}
+        const double alpha = ai[i - 1] > 0 ? -x : x;
+        for (int k = 0; k < i; ++k) v[k] = ai[k];
+        v[i - 1] -= alpha;
+        double h = 0;
+        for (int k = 0; k < i; ++k) h += v[k] * v[k];
+        h *= 0.5;
+        if (h == 0.0) { e[i - 1] = ai[i - 1]; continue; }
+        // A' = H A H on the leading i x i block: p = A v / h, K = v.p / (2h), q = p - K v, A' = A - v q^T - q v^T
+        double K = 0;
+        for (int r = 0; r < i; ++r) {
+            const double* ar = &A[(size_t)r * n];
+            double acc = 0;
+            for (int c = 0; c < i; ++c) acc += ar[c] * v[c];
+            p[r] = acc / h;
+            K += v[r] * p[r];
+        }
+        K /= 2.0 * h;
+        for (int r = 0; r < i; ++r) p[r] -= K * v[r];
+        for (int r = 0; r < i; ++r) {
+            double* ar = &A[(size_t)r * n];
+            for (int c = 0; c < i; ++c) ar[c] -= v[r] * p[c] + p[r] * v[c];
+        }
+        for (int k = 0; k < i - 1; ++k) { ai[k] = 0.0; A[(size_t)k * n + i] = 0.0; }
+        ai[i - 1] = alpha;
+        A[(size_t)(i - 1) * n + i] = alpha;
+        e[i - 1] = alpha;
+        // Q = Q H (columns 0..i-1)
+        for (int r = 0; r < n; ++r) {
+            double* zr = &Z[(size_t)r * n];
+            double acc = 0;
+            for (int k = 0; k < i; ++k) acc += zr[k] * v[k];
+            acc /= h;
+            if (acc != 0.0)
+                for (int k = 0; k < i; ++k) zr[k] -= acc * v[k];
+        }
+    }
+    if (n >= 2) e[0] = A[1];
+    d.resize(n);
+    for (int i = 0; i < n; ++i) d[i] = A[(size_t)i * n + i];
+    e.resize(n - 1 > 0 ? n - 1 : 0);
+    return tridiag_ql(d, e, &Z, nullptr, true);
+}
+
 std::vector<int> argsort(const std::vector<double>& v) {
     std::vector<int> idx(v.size());
     std::iota(idx.begin(), idx.end(), 0);
@@ -129,22 +191,33 @@ extern "C" int dlma_lap_eigs(dlma_gauge_t h, int nev, int t0, int nt, const void
     if (nt < 1 || t0 < 0 || t0 + nt > T) return fail(DLMA_EINVAL, "timeslices t0..t0+nt-1 must lie in [0, T)");
     if (nev < 1 || nev > n) return fail(DLMA_EINVAL, "nev must be in [1, 3 L^3]");
     const double tol = (opts && opts->tol > 0) ? opts->tol : 1e-10;
-    int maxm = (opts && opts->max_basis > 0) ? opts->max_basis : (int)std::min<long>(n, 20L * nev + 200);
+    // thick restart: the basis holds at most restart_basis vectors; at that size the
+    // run keeps `keep` Ritz vectors of the wanted end and the last Lanczos vector
+    const bool restart = opts && opts->restart_basis > 0;
+    int maxm = restart ? opts->restart_basis
+                       : ((opts && opts->max_basis > 0) ? opts->max_basis : (int)std::min<long>(n, 20L * nev + 200));
     maxm = (int)std::min<long>(maxm, n);
     if (maxm < nev) return fail(DLMA_EINVAL, "max_basis must be >= nev");
+    int keep = 0, max_restarts = 0;
+    if (restart) {
+        keep = opts->restart_keep > 0 ? opts->restart_keep : nev + (maxm - nev) / 2;
+        max_restarts = opts->max_restarts > 0 ? opts->max_restarts : 200;
+        if (!(keep > nev && keep < maxm - 1)) return fail(DLMA_EINVAL, "need nev < restart_keep < restart_basis - 1");
+    }
     const int check = (opts && opts->check_every > 0) ? opts->check_every : 10;
     int deg = opts ? opts->cheb_degree : 0;
     if (deg == 0) deg = n >= 4096 ? 24 : 0;
     if (deg < 0) deg = 0;
     hipStream_t s = S(stream);
     const long isq = n, tsq = (long)(maxm + 1) * n;
-    Buf Q, R[3], Hc, AB, AY, LR;
+    Buf Q, R[3], Hc, AB, AY, LR, RZ;
     DLMA_TRY(Q.allocate(sizeof(double2) * tsq * nt));
     for (auto& b : R) DLMA_TRY(b.allocate(sizeof(double2) * n * nt));
     DLMA_TRY(Hc.allocate(sizeof(double2) * (size_t)(maxm + 1) * nt));
     DLMA_TRY(AB.allocate(sizeof(double) * 2 * (size_t)maxm * nt + 64));
     DLMA_TRY(AY.allocate(sizeof(double2) * (size_t)nt * nev * n));
     DLMA_TRY(LR.allocate(sizeof(double) * 2 * (size_t)nt * nev));
+    if (restart) DLMA_TRY(RZ.allocate(sizeof(double2) * (size_t)nt * keep * n));
     double2* q = Q.as<double2>();
     double* alpha = AB.as<double>();
     double* beta = alpha + (size_t)maxm * nt;
@@ -153,6 +226,10 @@ extern "C" int dlma_lap_eigs(dlma_gauge_t h, int nev, int t0, int nt, const void
     double2* Vo = (double2*)V_out;
     const double2* U64 = g->U64.as<double2>();
     std::vector<double> ha((size_t)maxm * nt), hb((size_t)maxm * nt), hlam((size_t)nt * nev), hres((size_t)nt * nev);
+    // after a thick restart: kept Ritz values theta and their couplings sigma to the
+    // basis vector at position karrow (the Lanczos vector carried over)
+    int karrow = 0;
+    std::vector<double> theta, sigma;
     int cur_deg = 0;
     double cc = 0, ee = 1;
     // phase timing for the profiler (events bracket each phase on the stream);
@@ -189,7 +266,33 @@ extern "C" int dlma_lap_eigs(dlma_gauge_t h, int nev, int t0, int nt, const void
         w = b;
         return DLMA_OK;
     };
-    // Ritz vectors of the m-step tridiagonal matrices (the nev smallest or largest Ritz
+    // Eigenpairs of timeslice t's m-column projected matrix: the Lanczos tridiagonal
+    // (alpha, beta) until the first thick restart; after it the kept Ritz values on the
+    // diagonal, coupled to column karrow by sigma, then the tridiagonal continuation.
+    // ha, hb hold alpha, beta (copied from the device by the caller).
+    auto proj_eig = [&](int t, int m, std::vector<double>& d, std::vector<double>* Z, std::vector<double>* last) -> bool {
+        const double* at = ha.data() + (size_t)t * maxm;
+        const double* bt = hb.data() + (size_t)t * maxm;
+        if (karrow == 0) {
+            d.assign(at, at + m);
+            std::vector<double> e(bt, bt + std::max(0, m - 1));
+            return tridiag_ql(d, e, Z, last);
+        }
+        std::vector<double> A((size_t)m * m, 0.0), Zl;
+        for (int i = 0; i < karrow; ++i) {
+            A[(size_t)i * m + i] = theta[(size_t)t * keep + i];
+            A[(size_t)i * m + karrow] = A[(size_t)karrow * m + i] = sigma[(size_t)t * keep + i];
+        }
+        for (int j = karrow; j < m; ++j) {
+            A[(size_t)j * m + j] = at[j];
+            if (j + 1 < m) A[(size_t)j * m + j + 1] = A[(size_t)(j + 1) * m + j] = bt[j];
+        }
+        if (!sym_eig(std::move(A), m, d, Zl)) return false;
+        if (last) last->assign(Zl.begin() + (size_t)(m - 1) * m, Zl.begin() + (size_t)m * m);
+        if (Z) *Z = std::move(Zl);
+        return true;
+    };
+    // Ritz vectors of the m-column projected matrices (the nev smallest or largest Ritz
     // values) into V_out, then their Rayleigh quotients and residuals for -lap
     auto ritz_check = [&](int m, bool largest, bool& ok) -> int {
         DLMA_HIP(hipMemcpyAsync(ha.data(), alpha, sizeof(double) * maxm * nt, hipMemcpyDeviceToHost, s));
@@ -197,10 +300,8 @@ extern "C" int dlma_lap_eigs(dlma_gauge_t h, int nev, int t0, int nt, const void
         DLMA_HIP(hipStreamSynchronize(s));
         std::vector<double> Sall((size_t)nt * m * nev);
         const bool solved = parallel_for(nt, [&](int t) {
-            std::vector<double> d(ha.begin() + (size_t)t * maxm, ha.begin() + (size_t)t * maxm + m);
-            std::vector<double> e(hb.begin() + (size_t)t * maxm, hb.begin() + (size_t)t * maxm + m - 1);
-            std::vector<double> Z;
-            if (!tridiag_ql(d, e, &Z, nullptr)) return false;
+            std::vector<double> d, Z;
+            if (!proj_eig(t, m, d, &Z, nullptr)) return false;
             std::vector<int> idx = argsort(d);
             if (largest) std::reverse(idx.begin(), idx.end());
             for (int k = 0; k < nev; ++k)
@@ -226,62 +327,111 @@ extern "C" int dlma_lap_eigs(dlma_gauge_t h, int nev, int t0, int nt, const void
             if (!(r <= tol * 12.0)) ok = false;
         return DLMA_OK;
     };
-    // msteps Lanczos steps with the current operator from q_0 = v0/|v0|
-    auto lanczos = [&](int msteps, bool largest, bool checks, int& m, bool& conv) -> int {
+    // Up to msteps Lanczos steps with the current operator from q_0 = v0/|v0|.  With
+    // thick restart the basis never exceeds maxm vectors: when it is full, the keep
+    // Ritz vectors of the wanted end replace it, the last Lanczos vector follows them,
+    // and the run continues from there (convergence is tested once per cycle).
+    auto lanczos = [&](long msteps, bool largest, bool checks, int& m, bool& conv) -> int {
         conv = false;
         m = 0;
-        int next_check = check;
+        karrow = 0;
+        int next_check = check, restarts = 0;
         DLMA_HIP(launch_normalize_into((const double2*)v0, n, q, tsq, n, beta, maxm, 0, nt, s));
         DLMA_HIP(hipMemcpyAsync(hb.data(), beta, sizeof(double) * maxm * nt, hipMemcpyDeviceToHost, s));
         DLMA_HIP(hipStreamSynchronize(s));
         for (int t = 0; t < nt; ++t)
             if (!(hb[(size_t)t * maxm] > 0) || !std::isfinite(hb[(size_t)t * maxm]))
                 return fail(DLMA_EINVAL, "start vector is zero or not finite");
-        for (int j = 0; j < msteps; ++j) {
+        int j = 0;  // position of the vector the next step expands
+        for (long step = 0; step < msteps; ++step) {
             double2* w = nullptr;
             hipEvent_t ev = nullptr;
             t_begin(ev);
             DLMA_TRY(apply_op(q + (long)j * isq, w));
             t_end(ev, KC_LAP_MATVEC, (cur_deg > 0 ? cur_deg : 1) * (link_b + 2.0 * vec_b));
             t_begin(ev);
-            DLMA_HIP(launch_lanczos_three(q, tsq, isq, w, n, n, alpha, beta, maxm, j, nt, s));
+            DLMA_HIP(launch_lanczos_three(q, tsq, isq, w, n, n, alpha, beta, maxm, j, nt, s, j > karrow));
             for (int pass = 0; pass < 2; ++pass) {  // classical Gram-Schmidt against all q_i, twice
                 DLMA_HIP(launch_dots(q, tsq, isq, w, n, n, Hc.as<double2>(), maxm + 1, j + 1, nt, s));
                 DLMA_HIP(launch_sub_combo(q, tsq, isq, Hc.as<double2>(), maxm + 1, j + 1, w, n, n, nt, s));
             }
             DLMA_HIP(launch_normalize_into(w, n, q + (long)(j + 1) * isq, tsq, n, beta, maxm, j, nt, s));
             t_end(ev, KC_LAP_ORTHO, (4.0 * (j + 1) + 8.0) * vec_b);
-            m = j + 1;
-            // convergence checks every `check` steps, spaced out to m/16 on long runs
-            // (each one solves the m x m tridiagonal problems on the host)
-            if (!checks || m < nev || (m < next_check && m != msteps)) continue;
-            next_check = m + std::max(check, m / 16);
+            m = ++j;
+            const bool last_step = step + 1 == msteps;
+            if (!checks) continue;
+            if (restart) {
+                if (m < maxm && !last_step) continue;
+            } else {
+                // convergence checks every `check` steps, spaced out to m/16 on long runs
+                // (each one solves the m x m tridiagonal problems on the host)
+                if (m < nev || (m < next_check && !last_step)) continue;
+                next_check = m + std::max(check, m / 16);
+            }
             DLMA_HIP(hipMemcpyAsync(ha.data(), alpha, sizeof(double) * maxm * nt, hipMemcpyDeviceToHost, s));
             DLMA_HIP(hipMemcpyAsync(hb.data(), beta, sizeof(double) * maxm * nt, hipMemcpyDeviceToHost, s));
             DLMA_HIP(hipStreamSynchronize(s));
-            // cheap test first: Ritz residual estimates |beta_m s_mi| of the Lanczos operator
+            // cheap test first: Ritz residual estimates |beta_m s_mi| of the Lanczos operator;
+            // at a restart also the kept Ritz pairs and their couplings
+            const bool do_restart = restart && m == maxm && !last_step && restarts < max_restarts;
+            std::vector<double> Skeep, th_new, sg_new;
+            if (do_restart) {
+                Skeep.assign((size_t)nt * m * keep, 0.0);
+                th_new.assign((size_t)nt * keep, 0.0);
+                sg_new.assign((size_t)nt * keep, 0.0);
+            }
             std::atomic<bool> trigger(true), solved(true);
             parallel_for(nt, [&](int t) {
-                if (!trigger) return true;
-                std::vector<double> d(ha.begin() + (size_t)t * maxm, ha.begin() + (size_t)t * maxm + m);
-                std::vector<double> e(hb.begin() + (size_t)t * maxm, hb.begin() + (size_t)t * maxm + m - 1);
-                double bm = hb[(size_t)t * maxm + m - 1];
-                if (bm < 1e-12) return true;  // invariant subspace reached: Ritz pairs exact
-                std::vector<double> last;
-                if (!tridiag_ql(d, e, nullptr, &last)) { solved = false; return false; }
+                if (!trigger && !do_restart) return true;
+                const double bm = hb[(size_t)t * maxm + m - 1];
+                std::vector<double> d, Z, last;
+                if (!(do_restart ? proj_eig(t, m, d, &Z, nullptr) : proj_eig(t, m, d, nullptr, &last))) {
+                    solved = false;
+                    return false;
+                }
+                if (do_restart) last.assign(Z.begin() + (size_t)(m - 1) * m, Z.end());
                 std::vector<int> idx = argsort(d);
                 if (largest) std::reverse(idx.begin(), idx.end());
-                for (int k = 0; k < nev; ++k) {
-                    double scale = largest ? std::fabs(d[idx[k]]) : 12.0;
-                    if (std::fabs(bm * last[idx[k]]) > tol * scale) { trigger = false; break; }
-                }
+                if (bm >= 1e-12)  // else an invariant subspace was reached: Ritz pairs exact
+                    for (int k = 0; k < nev; ++k) {
+                        double scale = largest ? std::fabs(d[idx[k]]) : 12.0;
+                        if (std::fabs(bm * last[idx[k]]) > tol * scale) { trigger = false; break; }
+                    }
+                if (do_restart)
+                    for (int c = 0; c < keep; ++c) {
+                        th_new[(size_t)t * keep + c] = d[idx[c]];
+                        sg_new[(size_t)t * keep + c] = bm * last[idx[c]];
+                        for (int i = 0; i < m; ++i) Skeep[((size_t)t * m + i) * keep + c] = Z[(size_t)i * m + idx[c]];
+                    }
                 return true;
             });
-            if (!solved) return fail(DLMA_EHIP, "tridiagonal eigensolver did not converge");
-            if (!trigger && m != msteps) continue;
-            bool ok = false;
-            DLMA_TRY(ritz_check(m, largest, ok));
-            if (ok) { conv = true; return DLMA_OK; }
+            if (!solved) return fail(DLMA_EHIP, "projected eigenproblem did not converge");
+            if (trigger || last_step || (restart && !do_restart)) {
+                bool ok = false;
+                DLMA_TRY(ritz_check(m, largest, ok));
+                if (ok) { conv = true; return DLMA_OK; }
+            }
+            if (!do_restart) {
+                if (restart) break;  // out of restarts
+                continue;
+            }
+            // restart: q_0..q_{keep-1} = kept Ritz vectors, q_keep = q_m
+            Buf Sd;
+            DLMA_TRY(Sd.allocate(sizeof(double) * Skeep.size()));
+            DLMA_HIP(hipMemcpyAsync(Sd.p, Skeep.data(), sizeof(double) * Skeep.size(), hipMemcpyHostToDevice, s));
+            t_begin(ev);
+            DLMA_HIP(launch_ritz(q, tsq, isq, Sd.as<double>(), m, keep, RZ.as<double2>(), (long)keep * n, n, nt, s));
+            DLMA_HIP(hipMemcpy2DAsync(q, tsq * sizeof(double2), RZ.p, (size_t)keep * n * sizeof(double2),
+                                      (size_t)keep * n * sizeof(double2), nt, hipMemcpyDeviceToDevice, s));
+            DLMA_HIP(hipMemcpy2DAsync(q + (long)keep * isq, tsq * sizeof(double2), q + (long)m * isq, tsq * sizeof(double2),
+                                      n * sizeof(double2), nt, hipMemcpyDeviceToDevice, s));
+            t_end(ev, KC_LAP_RITZ, ((double)m + 2.0 * keep + 2.0) * vec_b);
+            DLMA_HIP(hipStreamSynchronize(s));  // Skeep's device copy lives in this scope
+            theta = std::move(th_new);
+            sigma = std::move(sg_new);
+            karrow = keep;
+            j = keep;
+            ++restarts;
         }
         return DLMA_OK;
     };
@@ -311,7 +461,7 @@ extern "C" int dlma_lap_eigs(dlma_gauge_t h, int nev, int t0, int nt, const void
             ee = 0.5 * (12.0 - cut);
         }
     }
-    DLMA_TRY(lanczos(maxm, cur_deg > 0, true, m, conv));
+    DLMA_TRY(lanczos(restart ? (long)(max_restarts + 1) * maxm : (long)maxm, cur_deg > 0, true, m, conv));
     if (!conv) {  // basis cap reached: report the last Ritz pairs
         bool ok = false;
         DLMA_TRY(ritz_check(m, cur_deg > 0, ok));

@@ -13,8 +13,10 @@ hipError_t launch_dots(const double2* a, long tsa, long isa, const double2* b, l
                        int ni, int nt, hipStream_t s);
 hipError_t launch_sub_combo(const double2* q, long tsq, long isq, const double2* h, int hstride, int ni, double2* w, long tsw,
                             long n, int nt, hipStream_t s);
+// prev = false: no beta_{j-1} q_{j-1} term (the first step after a thick restart,
+// whose couplings to the kept Ritz vectors the Gram-Schmidt passes remove)
 hipError_t launch_lanczos_three(const double2* q, long tsq, long isq, double2* w, long tsw, long n, double* alpha, double* beta,
-                                int astride, int j, int nt, hipStream_t s);
+                                int astride, int j, int nt, hipStream_t s, bool prev = true);
 hipError_t launch_normalize_into(const double2* w, long tsw, double2* q, long tsq, long n, double* nrm, int ostride, int j, int nt,
                                  hipStream_t s);
 hipError_t launch_ritz(const double2* q, long tsq, long isq, const double* S, int m, int nev, double2* y, long tsy, long n, int nt,

@@ -206,7 +206,7 @@ __global__ void __launch_bounds__(256) k_lanczos_alpha(const double2* __restrict
 
 __global__ void k_lanczos_three(const double2* __restrict__ qj, const double2* __restrict__ qjm, long tsq,
                                 double2* __restrict__ w, long tsw, long n, const double* __restrict__ alpha,
-                                const double* __restrict__ beta, int astride, int j) {
+                                const double* __restrict__ beta, int astride, int j, int prev) {
     long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
     int t = blockIdx.y;
     if (e >= n) return;
@@ -215,7 +215,7 @@ __global__ void k_lanczos_three(const double2* __restrict__ qj, const double2* _
     double2 c = qj[t * tsq + e];
     v.x -= a * c.x;
     v.y -= a * c.y;
-    if (j > 0) {
+    if (prev) {
         double b = beta[(long)t * astride + j - 1];
         double2 d = qjm[t * tsq + e];
         v.x -= b * d.x;
@@ -225,11 +225,11 @@ __global__ void k_lanczos_three(const double2* __restrict__ qj, const double2* _
 }
 
 hipError_t launch_lanczos_three(const double2* q, long tsq, long isq, double2* w, long tsw, long n, double* alpha, double* beta,
-                                int astride, int j, int nt, hipStream_t s) {
+                                int astride, int j, int nt, hipStream_t s, bool prev) {
     hipLaunchKernelGGL(k_lanczos_alpha, dim3(nt), dim3(256), 0, s, q + (long)j * isq, tsq, w, tsw, n, alpha, astride, j);
     const double2* qjm = j > 0 ? q + (long)(j - 1) * isq : q;
     hipLaunchKernelGGL(k_lanczos_three, dim3((unsigned)((n + 255) / 256), nt), dim3(256), 0, s, q + (long)j * isq, qjm, tsq, w, tsw,
-                       n, alpha, beta, astride, j);
+                       n, alpha, beta, astride, j, (prev && j > 0) ? 1 : 0);
     return hipGetLastError();
 }
 
