@@ -90,6 +90,8 @@ def main():
     ap.add_argument("--no-variants", action="store_true", help="skip the FP64 / BF16 / single-RHS comparisons")
     ap.add_argument("--copy-probe", action="store_true", help="also run a plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--inner-solver", type=int, default=1, choices=(0, 1),
+                    help="Krylov method of the inner solves: 1 = BiCGStab on Dhat, 0 = CG on Dhat Dhat^dag")
     ap.add_argument("--rhs-block", type=int, default=None,
                     help="right-hand sides per thread in the stencil kernels (0 = autotune; default 2, 1 for fp64)")
     ap.add_argument("--summarize", nargs=3, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR"),
@@ -146,7 +148,7 @@ def main():
             b[s:nd:4, T0, ..., s, :] = V[0]
             b[nd + s:nd + nn:4, T0, ..., s, :] = xi
         dlma.dlma_project(g, T0, V[0], b[nd:nd + nn], 1, out=b[nd + nn:])  # (1 - box(t')) eta
-        opts = dlma.default_opts(tol=TOL, prec=prec, rhs_block=args.rhs_block)
+        opts = dlma.default_opts(tol=TOL, prec=prec, rhs_block=args.rhs_block, inner_solver=args.inner_solver)
         xs, st = dlma.dlma_solve([g], [b], xs=[x], opts=opts)
         if timed_stats is not None:
             timed_stats.append(st)
@@ -182,12 +184,14 @@ def main():
     # dominant stencil kernel of the timed region (HIP events around each launch).  Its
     # algorithmic bytes count only right-hand sides still iterating: a launch reads
     # every link and clover entry once, plus the spinor passes of each active
-    # right-hand side; a right-hand side is active in exactly inner_iters launches
-    # of each class (one per inner CG iteration).
+    # right-hand side; a right-hand side is active in inner_iters launches of each
+    # class per inner iteration of the solver: one for CG on the normal equations, two
+    # for BiCGStab (v = Dhat p and t = Dhat s).
     kc = max(prof, key=lambda k: prof[k][1])
     n_l, ms_tot, by_all = prof[kc]
     fixed, per_rhs = hop_bytes_split(args.prec, *KTEMPLATE[kc], DIMS)
-    rhs_launches = sum(s["inner_iters"] for stp in stats for s in stp)
+    per_iter = 2 if args.inner_solver == 1 else 1
+    rhs_launches = per_iter * sum(s["inner_iters"] for stp in stats for s in stp)
     by_tot = n_l * fixed + rhs_launches * per_rhs
     achieved = by_tot / (ms_tot * 1e-3) / 1e9
     roofline = {"kernel": KCLASS[kc], "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
@@ -213,10 +217,12 @@ def main():
            "config": {"workload": "24^3x48 Wilson-clover solves, 128 distillation + 64 Z2-noise RHS to rel. residual 1e-10",
                       "lattice": "24^3x48", "eps": EPS, "seed": SEED, "kappa": KAPPA, "csw": CSW, "t_src": T0,
                       "nev": NEV, "nnoise": NNOISE, "nrhs": nrhs,
-                      "precision": {"mix_fp16": "FP16 storage (FP32 scale per site), FP32 inner CG, FP64 defect correction",
-                                    "mix_bf16": "BF16 storage, FP32 inner CG, FP64 defect correction",
-                                    "mix_fp32": "FP32 storage and inner CG, FP64 defect correction",
+                      "precision": {"mix_fp16": "FP16 storage (FP32 scale per site), FP32 arithmetic, FP64 defect correction",
+                                    "mix_bf16": "BF16 storage, FP32 arithmetic, FP64 defect correction",
+                                    "mix_fp32": "FP32 storage and arithmetic, FP64 defect correction",
                                     "fp64": "FP64 everywhere"}[args.prec],
+                      "inner_solver": "BiCGStab on the even-odd operator" if args.inner_solver == 1
+                      else "CG on the even-odd normal equations",
                       "step": "gauge load + clover + Laplacian modes on t' + sources + projection + batched solve"},
            "roofline": roofline,
            "iterations": {"inner_min": min(iters), "inner_max": max(iters), "outer_max": max(outer)},
@@ -232,23 +238,27 @@ def main():
             if prec == args.prec:
                 continue
             # one short capped solve first, so the RHS-block autotuner's search is not timed
-            dlma.dlma_solve([g], [b], xs=[x], opts=dlma.default_opts(tol=TOL, prec=prec, maxiter=8, max_outer=1),
+            dlma.dlma_solve([g], [b], xs=[x], opts=dlma.default_opts(tol=TOL, prec=prec, maxiter=8, max_outer=1,
+                                                                     inner_solver=args.inner_solver),
                             allow_notconv=True)
             torch.cuda.synchronize()
             t = time.time()
-            (xx,), st2 = dlma.dlma_solve([g], [b], xs=[x], opts=dlma.default_opts(tol=TOL, prec=prec))
+            (xx,), st2 = dlma.dlma_solve([g], [b], xs=[x], opts=dlma.default_opts(tol=TOL, prec=prec,
+                                                                                  inner_solver=args.inner_solver))
             torch.cuda.synchronize()
             dt = time.time() - t
             var[prec] = {"rhs_per_s": round(nrhs / dt, 3), "solve_s": round(dt, 3),
                          "inner_iters_max": max(s["inner_iters"] for s in st2),
                          "max_relres": max(s["relres"] for s in st2)}
             log("variant %s: %.2f RHS/s (batched solve only)" % (prec, nrhs / dt))
-        # plain single-RHS FP64 even-odd CG, one right-hand side at a time (sample of 4)
+        # plain single-RHS FP64 even-odd CG (CG on the normal equations), one right-hand
+        # side at a time (sample of 4)
         sample = [0, 1, nd, nd + nn]
         torch.cuda.synchronize()
         t = time.time()
         for i in sample:
-            dlma.dlma_solve([g], [b[i:i + 1]], xs=[x[i:i + 1]], opts=dlma.default_opts(tol=TOL, prec="fp64", rhs_block=1))
+            dlma.dlma_solve([g], [b[i:i + 1]], xs=[x[i:i + 1]], opts=dlma.default_opts(tol=TOL, prec="fp64", rhs_block=1,
+                                                                                       inner_solver=0))
         torch.cuda.synchronize()
         dt = (time.time() - t) / len(sample)
         var["fp64_single_rhs"] = {"rhs_per_s": round(1.0 / dt, 3), "sample": "4 right-hand sides solved one at a time"}
@@ -439,7 +449,10 @@ def dist_scan(args):
 def summarize(args):
     """rocprofv3 CSVs -> profiles/: per-kernel time summary and HBM traffic of the
     stencil kernels, with FETCH_SIZE / WRITE_SIZE scaled by what the counters read for
-    the 1 GiB device copy of --copy-probe (kernel __amd_rocclr_copyBuffer)."""
+    the 1 GiB device copy of --copy-probe (kernel __amd_rocclr_copyBuffer).  The
+    per-class averages and counters cover the timed step only: the dispatches after
+    its gauge load (the last k_pack_links), so that the autotuner's and the warm-up's
+    launches of the same kernels do not enter them."""
     import csv
     import collections
     trace, fetch, write = args.summarize
@@ -452,11 +465,20 @@ def summarize(args):
         raise FileNotFoundError(suffix)
 
     stats = list(csv.DictReader(open(find(trace, "kernel_stats.csv"))))
+
+    def timed_step(rows):
+        rows = sorted(rows, key=lambda r: int(r["Start_Timestamp"]))
+        starts = [i for i, r in enumerate(rows) if "k_pack_links" in r["Kernel_Name"]]
+        return rows[starts[-1]:] if starts else rows
+
+    step_ms = collections.defaultdict(list)
+    for r in timed_step(list(csv.DictReader(open(find(trace, "kernel_trace.csv"))))):
+        step_ms[r["Kernel_Name"]].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6)
     counters = {}
     copy_ref = {}
     for name, d in (("FETCH_SIZE", fetch), ("WRITE_SIZE", write)):
         agg = collections.defaultdict(list)
-        for row in csv.DictReader(open(find(d, "counter_collection.csv"))):
+        for row in timed_step(list(csv.DictReader(open(find(d, "counter_collection.csv"))))):
             agg[row["Kernel_Name"]].append(float(row["Counter_Value"]))
         counters[name] = agg
         # the calibration copy is the last device copy of the run (bench.py --copy-probe)
@@ -483,17 +505,18 @@ def summarize(args):
     lines += ["", "## HBM traffic per dispatch (rocprofv3 --pmc, one counter per run)", "",
               "Copy calibration (1 GiB device copy): FETCH_SIZE reads %.0f KiB (scale %.4f), WRITE_SIZE %.0f KiB (scale %.4f)."
               % (copy_ref["FETCH_SIZE"] or 0, scale["FETCH_SIZE"] or 0, copy_ref["WRITE_SIZE"] or 0, scale["WRITE_SIZE"] or 0), "",
+              "Classes below: dispatches of the timed step only (after its gauge load).", "",
               "| class | kernel | dispatches | FETCH KiB | WRITE KiB | scaled traffic GB | avg ms |", "|---|---|---|---|---|---|---|"]
     out = {}
     for kc in KCLASS:
         nm = hop_name(kc, nb)
         f = counters["FETCH_SIZE"].get(nm)
         w = counters["WRITE_SIZE"].get(nm)
-        if not f or not w or nm not in by_name:
+        if not f or not w or not step_ms.get(nm):
             continue
         fk, wk = sum(f) / len(f), sum(w) / len(w)
         tb = (fk * scale["FETCH_SIZE"] + wk * scale["WRITE_SIZE"]) * 1024.0
-        avg_ms = float(by_name[nm]["AverageNs"]) / 1e6
+        avg_ms = sum(step_ms[nm]) / len(step_ms[nm])
         lines.append("| %s | `hop_kernel<%d,%d,%d,%d>` | %d | %.0f | %.0f | %.3f | %.4f |"
                      % (KCLASS[kc].split()[0], pid, nb, KTEMPLATE[kc][0], KTEMPLATE[kc][1], len(f), fk, wk, tb / 1e9, avg_ms))
         out[kc] = {"kernel": nm, "precision": prec, "rhs_block": nb, "source_sha": sources_sha(),

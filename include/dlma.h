@@ -143,9 +143,12 @@ typedef struct {
     int dagger;        /* 1: solve D^dag x = b (x = g5 D^-1 g5 b), the adjoint solve of a backward pass */
     int lds_window;    /* FP16 stencils stage their +-x, +-y neighbours through LDS: -1 = autotuned
                           (with rhs_block), 0 = never, 1 = when they fit */
+    int inner_solver;  /* Krylov method of the inner solves on Dhat: 1 = BiCGStab on Dhat (default),
+                          0 = CG on the normal equations Dhat Dhat^dag (CGNE) */
 } dlma_solve_opts;
 
-/* Fill opts with the defaults (tol 1e-10, FP64, autotuned blocks, graph_iters 8, ...). */
+/* Fill opts with the defaults (tol 1e-10, FP64, autotuned blocks, graph_iters 8,
+ * BiCGStab inner solver, ...). */
 void dlma_solve_opts_default(dlma_solve_opts* opts);
 
 typedef struct {

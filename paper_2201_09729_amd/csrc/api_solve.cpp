@@ -36,6 +36,7 @@ extern "C" void dlma_solve_opts_default(dlma_solve_opts* o) {
     o->check_every = 0;
     o->dagger = 0;
     o->lds_window = -1;
+    o->inner_solver = 1;
 }
 
 namespace {
@@ -51,6 +52,9 @@ struct Cfg {
     Buf r, p, w, xs, y;              // inner vectors (precision P), half fields
     Buf nr, np, nw, nxs, ny;         // FP16 scales
     Buf part;                        // partial norms
+    Buf bs, bt, brh, nbs, nbt, nbrh;    // BiCGStab: s, t, shadow residual (precision P) and FP16 scales
+    Buf bstate;                      // BiCGStab: rho alpha omega beta (complex, per rhs)
+    double2 *brho = nullptr, *balpha = nullptr, *bomega = nullptr, *bbeta = nullptr;
     Buf dstate;                      // rr rr0 alpha beta tol2 abs2 nrm (double) | active iters (int)
     int hnsb, vnsb;                  // site blocks of stencil and vector kernels
     double *rr, *rr0, *alpha, *beta, *tol2, *abs2, *nrm, *enrm;
@@ -74,6 +78,11 @@ template <int P> struct Tables {
     int nb64 = 1;                      // right-hand sides per thread of the FP64 outer stencils
     int wn = 0;                        // largest LDS window of the inner stencil jobs
     std::vector<FinJob> hfinI, hfinAB;  // kept for per-pass updates
+    // BiCGStab: stencils p -> y -> v and s -> y -> t, the vector steps, the finishers
+    bool bicg = false;
+    Buf dbk1p, dbk2v, dbk1s, dbk2t, dbv, dbf;
+    int nbv = 0, bbv = 0, bbf = 0;
+    std::vector<BiFinJob> hbf;           // kept for per-pass updates (maxit)
 };
 
 template <class T> int upload(Buf& b, const std::vector<T>& v, hipStream_t s) {
@@ -82,7 +91,7 @@ template <class T> int upload(Buf& b, const std::vector<T>& v, hipStream_t s) {
     return DLMA_OK;
 }
 
-template <int P> int alloc_cfg(Cfg& c, hipStream_t s) {
+template <int P> int alloc_cfg(Cfg& c, bool bicg, hipStream_t s) {
     Gauge* g = c.g;
     size_t n = c.nrhs;
     int Vh = g->Vh;
@@ -106,9 +115,26 @@ template <int P> int alloc_cfg(Cfg& c, hipStream_t s) {
         DLMA_TRY(c.nxs.allocate(nb));
         DLMA_TRY(c.ny.allocate(nb));
     }
+    if (bicg) {
+        DLMA_TRY(c.bs.allocate(halfP));
+        DLMA_TRY(c.bt.allocate(halfP));
+        DLMA_TRY(c.brh.allocate(halfP));
+        if (P == P16) {
+            size_t nb = sizeof(float) * n * Vh;
+            DLMA_TRY(c.nbs.allocate(nb));
+            DLMA_TRY(c.nbt.allocate(nb));
+            DLMA_TRY(c.nbrh.allocate(nb));
+        }
+        DLMA_TRY(c.bstate.allocate(sizeof(double2) * 4 * n));
+        c.brho = c.bstate.as<double2>();
+        c.balpha = c.brho + n;
+        c.bomega = c.brho + 2 * n;
+        c.bbeta = c.brho + 3 * n;
+        DLMA_HIP(hipMemsetAsync(c.bstate.p, 0, sizeof(double2) * 4 * n, s));
+    }
     c.hnsb = hop_nsb(g->geo);
     c.vnsb = ceil_div(Vh, VEC_BS);
-    int pmax = std::max(2 * c.hnsb, 2 * c.vnsb);
+    int pmax = std::max(std::max(2 * c.hnsb, 2 * c.vnsb), 3 * c.vnsb);
     DLMA_TRY(c.part.allocate(sizeof(double) * n * pmax));
     DLMA_TRY(c.dstate.allocate(sizeof(double) * 8 * n + sizeof(int) * 2 * n + 256));
     double* d = c.dstate.as<double>();
@@ -129,9 +155,11 @@ template <int P> int build_tables(std::vector<Cfg>& cs, Tables<P>& t, int nb, in
     std::vector<HopJob<P64>> resid, prep, recon;
     std::vector<VecJob<P64>> vnB, clov, conv64, acc64, vnE;
     std::vector<VecJob<P>> conv, acc, xpay;
-    std::vector<HopJob<P>> k1d, k2d, k1, k2cg;
+    std::vector<HopJob<P>> k1d, k2d, k1, k2cg, bk1p, bk2v, bk1s, bk2t;
     std::vector<FinJob> finB, finR, finI, finAB, finE;
-    int rhs0B = 0, rhs0R = 0, rhs0I = 0, rhs0AB = 0, rhs0E = 0;
+    std::vector<BiVecJob<P>> bvv;
+    std::vector<BiFinJob> bfv;
+    int rhs0B = 0, rhs0R = 0, rhs0I = 0, rhs0AB = 0, rhs0E = 0, rhs0BF = 0;
     for (auto& c : cs) {
         Gauge* g = c.g;
         int Vh = g->Vh, n = c.nrhs;
@@ -233,6 +261,27 @@ template <int P> int build_tables(std::vector<Cfg>& cs, Tables<P>& t, int nb, in
             HopJob<P> d = j1; d.in = vw; d.out = vy; k1.push_back(d);
             HopJob<P> e = j2; e.x = vw; e.in = vy; e.r = vr; e.xs = vx; e.alpha = c.alpha; k2cg.push_back(e);
             t.wn = std::max(t.wn, std::max(j1.wn, j2.wn));
+            if (t.bicg) {  // BiCGStab: v = w's storage, x = xs's
+                SF<P> vs = half_view<P>(c.bs.p, nrm_of<P>(c.nbs), Vh), vt = half_view<P>(c.bt.p, nrm_of<P>(c.nbt), Vh);
+                SF<P> vrh = half_view<P>(c.brh.p, nrm_of<P>(c.nbrh), Vh);
+                HopJob<P> k1 = j1; k1.part = nullptr;
+                HopJob<P> k2 = j2; k2.part = nullptr;
+                HopJob<P> a1 = k1; a1.in = vp; a1.out = vy; bk1p.push_back(a1);
+                HopJob<P> a2 = k2; a2.x = vp; a2.in = vy; a2.out = vw; bk2v.push_back(a2);
+                HopJob<P> a3 = k1; a3.in = vs; a3.out = vy; bk1s.push_back(a3);
+                HopJob<P> a4 = k2; a4.x = vs; a4.in = vy; a4.out = vt; bk2t.push_back(a4);
+                BiVecJob<P> bv = {};
+                bv.Vh = Vh; bv.nrhs = n; bv.nsb = c.vnsb;
+                bv.r = vr; bv.rh = vrh; bv.p = vp; bv.v = vw; bv.s = vs; bv.t = vt; bv.x = vx;
+                bv.alpha = c.balpha; bv.omega = c.bomega; bv.beta = c.bbeta;
+                bv.active = c.active; bv.part = c.part.as<double>(); bv.pstride = c.vnsb;
+                bvv.push_back(bv);
+                BiFinJob bf = {};
+                bf.nrhs = n; bf.rhs0 = rhs0BF; rhs0BF += n; bf.npart = c.vnsb; bf.part = c.part.as<double>();
+                bf.rho = c.brho; bf.alpha = c.balpha; bf.omega = c.bomega; bf.beta = c.bbeta;
+                bf.rr = c.rr; bf.tol2 = c.tol2; bf.active = c.active; bf.iters = c.iters; bf.maxit = 1 << 30;
+                bfv.push_back(bf);
+            }
         }
         FinJob f = {};
         f.nrhs = n; f.part = c.part.as<double>();
@@ -252,6 +301,18 @@ template <int P> int build_tables(std::vector<Cfg>& cs, Tables<P>& t, int nb, in
     t.bk1 = assign_blocks(k1d); assign_blocks(k1);
     t.bk2 = assign_blocks(k2d); assign_blocks(k2cg);
     t.bfin = rhs0AB;
+    if (t.bicg) {
+        assign_blocks(bk1p); assign_blocks(bk2v); assign_blocks(bk1s); assign_blocks(bk2t);
+        int b = 0;
+        for (auto& v : bvv) { v.blk0 = b; b += v.nsb * v.nrhs; }
+        t.bbv = b;
+        t.nbv = (int)bvv.size();
+        t.bbf = rhs0BF;
+        t.hbf = bfv;
+        DLMA_TRY(upload(t.dbk1p, bk1p, s)); DLMA_TRY(upload(t.dbk2v, bk2v, s));
+        DLMA_TRY(upload(t.dbk1s, bk1s, s)); DLMA_TRY(upload(t.dbk2t, bk2t, s));
+        DLMA_TRY(upload(t.dbv, bvv, s)); DLMA_TRY(upload(t.dbf, bfv, s));
+    }
     t.nb64 = nb64;
     t.nresid = (int)resid.size(); t.nprep = (int)prep.size(); t.nrecon = (int)recon.size();
     t.nvnB = (int)vnB.size(); t.nclov = (int)clov.size(); t.nconv = (int)conv.size(); t.nk = (int)k1d.size();
@@ -324,6 +385,36 @@ template <int P> int cg_iteration(std::vector<Cfg>& cs, Tables<P>& t, int nb, co
     return DLMA_OK;
 }
 
+// One BiCGStab iteration on Dhat for every configuration (the steps of bicg.hip with
+// the solver's stencil kernels for the two operator applications).
+template <int P> int bicg_iteration(std::vector<Cfg>& cs, Tables<P>& t, int nb, const std::vector<int>& nact, hipStream_t s) {
+    double b1 = 0, b2 = 0;
+    if (Profiler::get().on)
+        for (size_t i = 0; i < cs.size(); ++i) {
+            b1 += hop_bytes(P, K1, 0, cs[i].g->Vh, nact[i]);
+            b2 += hop_bytes(P, K2, 0, cs[i].g->Vh, nact[i]);
+        }
+    const BiVecJob<P>* bv = t.dbv.template as<BiVecJob<P>>();
+    const BiFinJob* bf = t.dbf.template as<BiFinJob>();
+    DLMA_TRY(hop_launch<P>(HopCfg{K1, 0, nb, t.wn}, t.dbk1p.p, t.nk, t.bk1, KC_K1, b1, s));
+    DLMA_TRY(hop_launch<P>(HopCfg{K2, 0, nb, t.wn}, t.dbk2v.p, t.nk, t.bk2, KC_K2, b2, s));
+    DLMA_HIP(launch_bivec<P>(bv, t.nbv, t.bbv, BV_RV, s));
+    DLMA_HIP(launch_bifinish(bf, t.nbv, t.bbf, BF_ALPHA, s));
+    DLMA_HIP(launch_bivec<P>(bv, t.nbv, t.bbv, BV_S, s));
+    DLMA_TRY(hop_launch<P>(HopCfg{K1, 0, nb, t.wn}, t.dbk1s.p, t.nk, t.bk1, KC_K1, b1, s));
+    DLMA_TRY(hop_launch<P>(HopCfg{K2, 0, nb, t.wn}, t.dbk2t.p, t.nk, t.bk2, KC_K2, b2, s));
+    DLMA_HIP(launch_bivec<P>(bv, t.nbv, t.bbv, BV_TS, s));
+    DLMA_HIP(launch_bifinish(bf, t.nbv, t.bbf, BF_OMEGA, s));
+    DLMA_HIP(launch_bivec<P>(bv, t.nbv, t.bbv, BV_XR, s));
+    DLMA_HIP(launch_bifinish(bf, t.nbv, t.bbf, BF_BETA, s));
+    DLMA_HIP(launch_bivec<P>(bv, t.nbv, t.bbv, BV_P, s));
+    return DLMA_OK;
+}
+
+template <int P> int inner_iteration(std::vector<Cfg>& cs, Tables<P>& t, int nb, const std::vector<int>& nact, hipStream_t s) {
+    return t.bicg ? bicg_iteration<P>(cs, t, nb, nact, s) : cg_iteration<P>(cs, t, nb, nact, s);
+}
+
 // The inner iterations as one HIP graph: `iters` consecutive CG iterations are
 // captured once per solve on a library stream and replayed with one launch.  Every
 // parameter the kernels read lives in device memory (job tables, per-RHS scalars,
@@ -348,7 +439,7 @@ int capture_iterations(std::vector<Cfg>& cs, Tables<P>& t, int nb, const std::ve
     DLMA_HIP(hipStreamCreateWithFlags(&ig.cap, hipStreamNonBlocking));
     DLMA_HIP(hipStreamBeginCapture(ig.cap, hipStreamCaptureModeRelaxed));
     int rc = DLMA_OK;
-    for (int k = 0; k < iters && rc == DLMA_OK; ++k) rc = cg_iteration<P>(cs, t, nb, nact, ig.cap);
+    for (int k = 0; k < iters && rc == DLMA_OK; ++k) rc = inner_iteration<P>(cs, t, nb, nact, ig.cap);
     hipError_t e = hipStreamEndCapture(ig.cap, &ig.graph);
     if (rc != DLMA_OK) return rc;
     if (e != hipSuccess) return fail(DLMA_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
@@ -363,7 +454,7 @@ template <int P>
 int solve_impl(std::vector<Cfg>& cs, const dlma_solve_opts& o, hipStream_t s) {
     for (auto& c : cs) {
         DLMA_TRY(gauge_prepare(c.g, P, s));
-        DLMA_TRY(alloc_cfg<P>(c, s));
+        DLMA_TRY(alloc_cfg<P>(c, o.inner_solver == 1, s));
     }
     if (o.rhs_block < 0 || o.rhs_block > 4)
         return fail(DLMA_EINVAL, "rhs_block must be 0 .. 4");
@@ -384,6 +475,11 @@ int solve_impl(std::vector<Cfg>& cs, const dlma_solve_opts& o, hipStream_t s) {
     if (o.lds_window >= 0) tin.win = o.lds_window;
     const int nb = tin.nb;
     Tables<P> t;
+    t.bicg = o.inner_solver == 1;
+    if (t.bicg)  // BiCGStab's shadow residual: a fixed seeded random field per configuration
+        for (auto& c : cs)
+            DLMA_HIP(launch_fill_random<P>(half_view<P>(c.brh.p, nrm_of<P>(c.nbrh), c.g->Vh), c.g->Vh, c.nrhs,
+                                           0x5eedu + (unsigned)c.gidx, s));
     DLMA_TRY(build_tables<P>(cs, t, nb, tin.sg, tin.win, t64.nb, t64.sg, s));
     int ncfg = (int)cs.size();
     // load sources and start vectors
@@ -464,6 +560,12 @@ int solve_impl(std::vector<Cfg>& cs, const dlma_solve_opts& o, hipStream_t s) {
         DLMA_HIP(hipMemcpyAsync(t.dfinI.p, t.hfinI.data(), sizeof(FinJob) * t.hfinI.size(), hipMemcpyHostToDevice, s));
         DLMA_HIP(hipMemcpyAsync(t.dfinAB.p, t.hfinAB.data(), sizeof(FinJob) * t.hfinAB.size(), hipMemcpyHostToDevice, s));
         DLMA_HIP(launch_finish(t.dfinI.template as<FinJob>(), t.nfin, t.bfin, FIN_INIT, s));
+        if (t.bicg) {  // rho = (rh, r) (p = r already), per-pass iteration caps
+            for (auto& f : t.hbf) f.maxit = std::max(1, o.maxiter - maxused);
+            DLMA_HIP(hipMemcpyAsync(t.dbf.p, t.hbf.data(), sizeof(BiFinJob) * t.hbf.size(), hipMemcpyHostToDevice, s));
+            DLMA_HIP(launch_bivec<P>(t.dbv.template as<BiVecJob<P>>(), t.nbv, t.bbv, BV_RR, s));
+            DLMA_HIP(launch_bifinish(t.dbf.template as<BiFinJob>(), t.nbv, t.bbf, BF_INIT, s));
+        }
         std::vector<int> nact(ncfg);
         for (int i = 0; i < ncfg; ++i) nact[i] = (int)std::count(cs[i].hact.begin(), cs[i].hact.end(), 1);
         // inner CG
@@ -471,7 +573,7 @@ int solve_impl(std::vector<Cfg>& cs, const dlma_solve_opts& o, hipStream_t s) {
         for (;;) {
             if (use_graph) DLMA_HIP(hipGraphLaunch(ig.exec, s));
             else
-                for (int k = 0; k < check; ++k) DLMA_TRY(cg_iteration<P>(cs, t, nb, nact, s));
+                for (int k = 0; k < check; ++k) DLMA_TRY(inner_iteration<P>(cs, t, nb, nact, s));
             int tot = 0;
             for (int i = 0; i < ncfg; ++i)
                 DLMA_HIP(hipMemcpyAsync(cs[i].hact.data(), cs[i].active, sizeof(int) * cs[i].nrhs, hipMemcpyDeviceToHost, s));
@@ -613,6 +715,7 @@ extern "C" int dlma_solve(const dlma_gauge_t* gs, int ngauge, const dlma_rhs_set
     if (o.check_every < 0 || o.graph_iters < 0) return fail(DLMA_EINVAL, "check_every and graph_iters must be >= 0");
     if (o.dagger != 0 && o.dagger != 1) return fail(DLMA_EINVAL, "dagger must be 0 or 1");
     if (o.lds_window < -1 || o.lds_window > 1) return fail(DLMA_EINVAL, "lds_window must be -1, 0 or 1");
+    if (o.inner_solver < 0 || o.inner_solver > 1) return fail(DLMA_EINVAL, "inner_solver must be 0 (CGNE) or 1 (BiCGStab)");
     std::vector<Cfg> cs;
     cs.reserve(ngauge);
     int total = 0;

@@ -1,0 +1,213 @@
+// Site-local steps and scalar finishers of BiCGStab on the even-odd reduced operator
+// Dhat (the alternative inner solver of dlma_solve).  One iteration is
+//   v = Dhat p;            alpha = rho / (rh, v)
+//   s = r - alpha v;       t = Dhat s;       omega = (t, s) / (t, t)
+//   x += alpha p + omega s;  r = s - omega t;  rho' = (rh, r);  beta = (rho'/rho)(alpha/omega)
+//   p = r + beta (p - omega v)
+// with (a, b) = sum conj(a_i) b_i over the even sites.  The operator applications
+// are the solver's stencil kernels; everything here is a streaming pass over fields
+// of the storage precision, in FP64 arithmetic, with deterministic two-stage sums.
+// The shadow residual rh is a fixed seeded random field rather than the initial
+// residual: a distillation source lives on one timeslice and one spin, and with
+// rh = r_0 the scalar (rh, r) loses almost all of the spreading residual, which
+// leaves the FP16 recursion to drift from the true residual.
+#include "kernels.h"
+
+namespace dlma {
+
+namespace {
+
+struct Cd { double r, i; };
+HD Cd cmulc(Cd a, Cd b) { return {a.r * b.r - a.i * b.i, a.r * b.i + a.i * b.r}; }
+HD Cd cdivc(Cd a, Cd b) {
+    const double d = b.r * b.r + b.i * b.i;
+    return {(a.r * b.r + a.i * b.i) / d, (a.i * b.r - a.r * b.i) / d};
+}
+HD Cd ld2(const double2* p, int r) { const double2 v = p[r]; return {v.x, v.y}; }
+HD bool finite2(Cd a) { return isfinite(a.r) && isfinite(a.i); }
+
+// block sum of v written by thread 0 at part[idx]; every thread of the block calls it
+__device__ __forceinline__ void bi_partial(double v, double* part, long idx) {
+    __shared__ double lds[VEC_BS / 64];
+    const double s = block_sum<VEC_BS>(v, lds);
+    if (threadIdx.x == 0) part[idx] = s;
+}
+
+}  // namespace
+
+template <int P, int MODE> __global__ void __launch_bounds__(VEC_BS) k_bivec(const BiVecJob<P>* jobs, int njob) {
+    using R = typename PT<P>::R;
+    const int bid = blockIdx.x;
+    int jb = 0;
+    while (jb + 1 < njob && bid >= jobs[jb + 1].blk0) ++jb;
+    const BiVecJob<P>& J = jobs[jb];
+    const int lb = bid - J.blk0;
+    const int r = lb / J.nsb;
+    const int sb = lb - r * J.nsb;
+    const int cb = sb * VEC_BS + (int)threadIdx.x;
+    const bool act = J.active == nullptr || J.active[r] != 0;  // uniform over the block
+    double q0 = 0, q1 = 0, q2 = 0;
+    if (act && cb < J.Vh) {
+        R a[24], b[24], c[24];
+        if (MODE == BV_RR || MODE == BV_RV) {
+            load_spinor<P, R>(J.rh, J.Vh, r, cb, a);
+            load_spinor<P, R>(MODE == BV_RR ? J.r : J.v, J.Vh, r, cb, b);
+            for (int i = 0; i < 12; ++i) {
+                const double ar = a[2 * i], ai = a[2 * i + 1], br = b[2 * i], bi = b[2 * i + 1];
+                q0 += ar * br + ai * bi;
+                q1 += ar * bi - ai * br;
+            }
+        } else if (MODE == BV_S) {
+            const Cd al = ld2(J.alpha, r);
+            load_spinor<P, R>(J.r, J.Vh, r, cb, a);
+            load_spinor<P, R>(J.v, J.Vh, r, cb, b);
+            for (int i = 0; i < 12; ++i) {
+                const double br = b[2 * i], bi = b[2 * i + 1];
+                c[2 * i] = (R)((double)a[2 * i] - (al.r * br - al.i * bi));
+                c[2 * i + 1] = (R)((double)a[2 * i + 1] - (al.r * bi + al.i * br));
+            }
+            store_spinor<P, R>(J.s, J.Vh, r, cb, c);
+        } else if (MODE == BV_TS) {
+            load_spinor<P, R>(J.t, J.Vh, r, cb, a);
+            load_spinor<P, R>(J.s, J.Vh, r, cb, b);
+            for (int i = 0; i < 12; ++i) {
+                const double ar = a[2 * i], ai = a[2 * i + 1], br = b[2 * i], bi = b[2 * i + 1];
+                q0 += ar * br + ai * bi;
+                q1 += ar * bi - ai * br;
+                q2 += ar * ar + ai * ai;
+            }
+        } else if (MODE == BV_XR) {
+            const Cd al = ld2(J.alpha, r), om = ld2(J.omega, r);
+            load_spinor<P, R>(J.x, J.Vh, r, cb, a);
+            load_spinor<P, R>(J.p, J.Vh, r, cb, b);
+            load_spinor<P, R>(J.s, J.Vh, r, cb, c);
+            for (int i = 0; i < 12; ++i) {
+                const double pr = b[2 * i], pi = b[2 * i + 1], sr = c[2 * i], si = c[2 * i + 1];
+                a[2 * i] = (R)((double)a[2 * i] + al.r * pr - al.i * pi + om.r * sr - om.i * si);
+                a[2 * i + 1] = (R)((double)a[2 * i + 1] + al.r * pi + al.i * pr + om.r * si + om.i * sr);
+            }
+            store_spinor<P, R>(J.x, J.Vh, r, cb, a);
+            load_spinor<P, R>(J.t, J.Vh, r, cb, b);
+            for (int i = 0; i < 12; ++i) {
+                const double tr = b[2 * i], ti = b[2 * i + 1];
+                c[2 * i] = (R)((double)c[2 * i] - (om.r * tr - om.i * ti));
+                c[2 * i + 1] = (R)((double)c[2 * i + 1] - (om.r * ti + om.i * tr));
+            }
+            store_spinor<P, R>(J.r, J.Vh, r, cb, c);
+            // the new residual as stored (its storage rounding included)
+            load_spinor<P, R>(J.r, J.Vh, r, cb, c);
+            load_spinor<P, R>(J.rh, J.Vh, r, cb, a);
+            for (int i = 0; i < 12; ++i) {
+                const double hr = a[2 * i], hi = a[2 * i + 1], rr = c[2 * i], ri = c[2 * i + 1];
+                q0 += rr * rr + ri * ri;
+                q1 += hr * rr + hi * ri;
+                q2 += hr * ri - hi * rr;
+            }
+        } else {  // BV_P
+            const Cd be = ld2(J.beta, r), om = ld2(J.omega, r);
+            load_spinor<P, R>(J.r, J.Vh, r, cb, a);
+            load_spinor<P, R>(J.p, J.Vh, r, cb, b);
+            load_spinor<P, R>(J.v, J.Vh, r, cb, c);
+            for (int i = 0; i < 12; ++i) {
+                const double dr = (double)b[2 * i] - (om.r * c[2 * i] - om.i * c[2 * i + 1]);
+                const double di = (double)b[2 * i + 1] - (om.r * c[2 * i + 1] + om.i * c[2 * i]);
+                b[2 * i] = (R)((double)a[2 * i] + be.r * dr - be.i * di);
+                b[2 * i + 1] = (R)((double)a[2 * i + 1] + be.r * di + be.i * dr);
+            }
+            store_spinor<P, R>(J.p, J.Vh, r, cb, b);
+        }
+    }
+    constexpr int NQ = (MODE == BV_RR || MODE == BV_RV) ? 2 : ((MODE == BV_TS || MODE == BV_XR) ? 3 : 0);
+    if (NQ > 0) bi_partial(q0, J.part, ((long)r * NQ + 0) * J.pstride + sb);
+    if (NQ > 1) bi_partial(q1, J.part, ((long)r * NQ + 1) * J.pstride + sb);
+    if (NQ > 2) bi_partial(q2, J.part, ((long)r * NQ + 2) * J.pstride + sb);
+}
+
+template <int P> hipError_t launch_bivec(const BiVecJob<P>* j, int njob, int nblocks, int mode, hipStream_t s) {
+    if (nblocks <= 0) return hipSuccess;
+    switch (mode) {
+    case BV_RR: hipLaunchKernelGGL((k_bivec<P, BV_RR>), dim3(nblocks), dim3(VEC_BS), 0, s, j, njob); break;
+    case BV_RV: hipLaunchKernelGGL((k_bivec<P, BV_RV>), dim3(nblocks), dim3(VEC_BS), 0, s, j, njob); break;
+    case BV_S: hipLaunchKernelGGL((k_bivec<P, BV_S>), dim3(nblocks), dim3(VEC_BS), 0, s, j, njob); break;
+    case BV_TS: hipLaunchKernelGGL((k_bivec<P, BV_TS>), dim3(nblocks), dim3(VEC_BS), 0, s, j, njob); break;
+    case BV_XR: hipLaunchKernelGGL((k_bivec<P, BV_XR>), dim3(nblocks), dim3(VEC_BS), 0, s, j, njob); break;
+    case BV_P: hipLaunchKernelGGL((k_bivec<P, BV_P>), dim3(nblocks), dim3(VEC_BS), 0, s, j, njob); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template hipError_t launch_bivec<P64>(const BiVecJob<P64>*, int, int, int, hipStream_t);
+template hipError_t launch_bivec<P32>(const BiVecJob<P32>*, int, int, int, hipStream_t);
+template hipError_t launch_bivec<P16>(const BiVecJob<P16>*, int, int, int, hipStream_t);
+template hipError_t launch_bivec<PB16>(const BiVecJob<PB16>*, int, int, int, hipStream_t);
+
+// One block per right-hand side: fixed-order sums of the quantities' partials, then
+// the scalar update of the mode.  A right-hand side stops (inactive) when |r|^2
+// reaches its target, at the iteration cap, on a non-finite value, or on a
+// breakdown (a zero denominator); the defect-correction pass that runs the inner
+// solve restarts from the true residual in every case.
+__global__ void __launch_bounds__(256) k_bifinish(const BiFinJob* jobs, int njob, int mode) {
+    const int bid = blockIdx.x;
+    int jb = 0;
+    while (jb + 1 < njob && bid >= jobs[jb + 1].rhs0) ++jb;
+    const BiFinJob& J = jobs[jb];
+    const int r = bid - J.rhs0;
+    if (r >= J.nrhs) return;  // uniform over the block
+    const int NQ = (mode == BF_ALPHA || mode == BF_INIT) ? 2 : 3;
+    __shared__ double lds[4];
+    double q[3] = {0, 0, 0};
+    for (int k = 0; k < NQ; ++k) {
+        double v = 0;
+        const double* pp = J.part + ((size_t)r * NQ + k) * J.npart;
+        for (int i = threadIdx.x; i < J.npart; i += 256) v += pp[i];
+        q[k] = block_sum<256>(v, lds);
+    }
+    if (threadIdx.x != 0) return;
+    const Cd one = {1.0, 0.0}, zero = {0.0, 0.0};
+    auto st = [](double2* a, int i, Cd v) { a[i] = make_double2(v.r, v.i); };
+    if (mode == BF_INIT) {  // start of an inner solve (after the CG-state init): rho = (rh, r)
+        const Cd rho = {q[0], q[1]};
+        st(J.rho, r, rho);
+        st(J.alpha, r, one);
+        st(J.omega, r, one);
+        st(J.beta, r, zero);
+        if (J.active[r] && (!finite2(rho) || (rho.r == 0.0 && rho.i == 0.0))) J.active[r] = 0;
+        return;
+    }
+    if (!J.active[r]) return;
+    if (mode == BF_ALPHA) {
+        const Cd d = {q[0], q[1]};
+        if (!finite2(d) || (d.r == 0.0 && d.i == 0.0)) {
+            st(J.alpha, r, zero);
+            J.active[r] = 0;
+        } else {
+            st(J.alpha, r, cdivc(ld2(J.rho, r), d));
+        }
+    } else if (mode == BF_OMEGA) {
+        const Cd ts = {q[0], q[1]};
+        st(J.omega, r, (finite2(ts) && q[2] > 0.0 && isfinite(q[2])) ? Cd{ts.r / q[2], ts.i / q[2]} : zero);
+    } else {  // BF_BETA
+        const double rr = q[0];
+        const Cd rho1 = {q[1], q[2]};
+        J.rr[r] = rr;
+        const int it = J.iters[r] + 1;
+        J.iters[r] = it;
+        const Cd rho = ld2(J.rho, r), om = ld2(J.omega, r), al = ld2(J.alpha, r);
+        const bool brk = (om.r == 0.0 && om.i == 0.0) || (rho.r == 0.0 && rho.i == 0.0) || !finite2(rho1);
+        if (!isfinite(rr) || rr <= J.tol2[r] || it >= J.maxit || brk) {
+            J.active[r] = 0;
+            return;
+        }
+        st(J.beta, r, cmulc(cdivc(rho1, rho), cdivc(al, om)));
+        st(J.rho, r, rho1);
+    }
+}
+
+hipError_t launch_bifinish(const BiFinJob* j, int njob, int nblocks, int mode, hipStream_t s) {
+    if (nblocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_bifinish, dim3(nblocks), dim3(256), 0, s, j, njob, mode);
+    return hipGetLastError();
+}
+
+}  // namespace dlma

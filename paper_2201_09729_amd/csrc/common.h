@@ -175,9 +175,14 @@ template <int P, class R> HD void store_spinor(const SF<P>& f, int Vh, int r, in
         if (!(m >= 1e-30f)) m = 0.f;
         float inv = m > 0.f ? 1.0f / m : 0.f;
         f.nrm[(size_t)r * f.ns + cb] = m;
+        uint32_t w[12];
 #pragma unroll
-        for (int c = 0; c < 12; ++c)
-            f.v[f16_word(f, Vh, r, cb, c)] = f_to_h((float)s[2 * c] * inv) | (f_to_h((float)s[2 * c + 1] * inv) << 16);
+        for (int c = 0; c < 12; ++c) w[c] = f_to_h((float)s[2 * c] * inv) | (f_to_h((float)s[2 * c + 1] * inv) << 16);
+        // the three groups of four words compile to 128-bit stores
+        wide_store_begin();
+#pragma unroll
+        for (int c = 0; c < 12; ++c) f.v[f16_word(f, Vh, r, cb, c)] = w[c];
+        wide_store_end();
     } else {
         typename PT<P>::S* b = f.v + (size_t)r * f.rs + cb;
 #pragma unroll

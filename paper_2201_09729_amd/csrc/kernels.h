@@ -35,6 +35,40 @@ struct FinJob {
 };
 enum FinMode { FIN_NORM = 0, FIN_ALPHA = 1, FIN_BETA = 2, FIN_INIT = 3 };
 
+// BiCGStab on the even-odd reduced operator (the alternative inner solver).  Site-
+// local vector steps, one thread per site and right-hand side; partial sums of NQ
+// quantities per block at part[(r * NQ + q) * pstride + site block].
+template <int P> struct BiVecJob {
+    int Vh, nrhs, nsb, blk0;
+    SF<P> r, rh, p, v, s, t, x;        // residual, shadow residual, direction, D p, s, D s, iterate
+    const double2 *alpha, *omega, *beta;  // per right-hand side
+    const int* active;
+    double* part;
+    int pstride;
+};
+enum BiVecMode {
+    BV_RR = 0,    // part: (rh, r)                                   NQ = 2 (re, im)
+    BV_RV = 1,    // part: (rh, v)                                   NQ = 2 (re, im)
+    BV_S = 2,     // s = r - alpha v
+    BV_TS = 3,    // part: (t, s), |t|^2                             NQ = 3
+    BV_XR = 4,    // x += alpha p + omega s; r = s - omega t; part: |r|^2, (rh, r)   NQ = 3
+    BV_P = 5,     // p = r + beta (p - omega v)
+};
+template <int P> hipError_t launch_bivec(const BiVecJob<P>* j, int njob, int nblocks, int mode, hipStream_t s);
+
+// Per right-hand side scalars of BiCGStab from the partial sums (one block per rhs,
+// fixed order), with the CG state of FinJob (|r|^2, targets, flags, counts).
+struct BiFinJob {
+    int nrhs, rhs0, npart;     // npart: partials per quantity (the vector kernels' pstride)
+    const double* part;
+    double2 *rho, *alpha, *omega, *beta;
+    double *rr, *tol2;
+    int *active, *iters;
+    int maxit;
+};
+enum BiFinMode { BF_INIT = 0, BF_ALPHA = 1, BF_OMEGA = 2, BF_BETA = 3 };
+hipError_t launch_bifinish(const BiFinJob* j, int njob, int nblocks, int mode, hipStream_t s);
+
 // wn: LDS window sites per right-hand side of the launch's FP16 jobs (the largest
 // HopJob::wn among them; 0 = none, and always 0 for other precisions)
 struct HopCfg { int kind, flags, nb, wn = 0; };

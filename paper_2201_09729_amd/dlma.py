@@ -40,7 +40,7 @@ class SolveOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("maxiter", ctypes.c_int), ("max_outer", ctypes.c_int),
                 ("prec", ctypes.c_int), ("inner_tol", ctypes.c_double), ("rhs_block", ctypes.c_int),
                 ("use_x0", ctypes.c_int), ("graph_iters", ctypes.c_int), ("check_every", ctypes.c_int),
-                ("dagger", ctypes.c_int), ("lds_window", ctypes.c_int)]
+                ("dagger", ctypes.c_int), ("lds_window", ctypes.c_int), ("inner_solver", ctypes.c_int)]
 
 
 class SolveStat(ctypes.Structure):

@@ -57,17 +57,18 @@ def test_set_mass_matches_oracle(D, orc):
     assert np.linalg.norm(y - ref) / np.linalg.norm(ref) < 1e-13
 
 
+@pytest.mark.parametrize("solver", [0, 1], ids=["cgne", "bicgstab"])
 @pytest.mark.parametrize("prec", ["fp64", "mix_fp32", "mix_fp16", "mix_bf16"])
 @pytest.mark.parametrize("rhs_block", [1, 2, 3, 4])
-def test_solve_true_residual(D, orc, prec, rhs_block):
-    """8^3x16, kappa 0.120, csw 1.0: five right-hand sides (ragged for blocks of 2 and 4);
-    the oracle re-evaluates |b - D x_gpu| / |b| <= 1e-10 for every precision."""
+def test_solve_true_residual(D, orc, prec, rhs_block, solver):
+    """8^3x16, kappa 0.120, csw 1.0: five right-hand sides (ragged for blocks of 2, 3 and 4),
+    both inner solvers; the oracle re-evaluates |b - D x_gpu| / |b| <= 1e-10."""
     dims = (16, 8, 8, 8)
-    print("solve", prec, rhs_block, flush=True)
+    print("solve", prec, rhs_block, solver, flush=True)
     U = synth.gauge_field(dims, 0.3, 2)
     b = synth.random_spinor(dims, 5, 21)
     g = D.dlma_load_gauge(cu(U), 0.120, 1.0)
-    opts = D.default_opts(tol=1e-10, prec=prec, rhs_block=rhs_block, maxiter=4000)
+    opts = D.default_opts(tol=1e-10, prec=prec, rhs_block=rhs_block, maxiter=4000, inner_solver=solver)
     xs, st = D.dlma_solve([g], [cu(b)], opts=opts)
     x = xs[0].cpu().numpy()
     A = orc.clover(U, 0.120, 1.0)
@@ -160,9 +161,10 @@ def test_schur_bench_runs(D):
         assert ms > 0 and by > 0
 
 
+@pytest.mark.parametrize("solver", [0, 1], ids=["cgne", "bicgstab"])
 @pytest.mark.parametrize("prec", ["fp64", "mix_fp16"])
 @pytest.mark.parametrize("iters", [8, 3])
-def test_graph_replay_matches_direct_launches(D, orc, prec, iters):
+def test_graph_replay_matches_direct_launches(D, orc, prec, iters, solver):
     """The inner iterations replayed from one captured hipGraph give bit-identical
     solutions and statistics to the same iterations launched one by one (the host
     checks convergence after every replay, with copies and other kernels in between)."""
@@ -173,8 +175,8 @@ def test_graph_replay_matches_direct_launches(D, orc, prec, iters):
         Us.append(U)
         gs.append(D.dlma_load_gauge(cu(U), kappa, csw))
         bs.append(cu(synth.random_spinor(dims, n, seed + 100)))
-    direct = D.default_opts(tol=1e-10, prec=prec, graph_iters=0, check_every=iters)
-    graph = D.default_opts(tol=1e-10, prec=prec, graph_iters=iters)
+    direct = D.default_opts(tol=1e-10, prec=prec, graph_iters=0, check_every=iters, inner_solver=solver)
+    graph = D.default_opts(tol=1e-10, prec=prec, graph_iters=iters, inner_solver=solver)
     x0, s0 = D.dlma_solve(gs, bs, opts=direct)
     x1, s1 = D.dlma_solve(gs, bs, opts=graph)
     assert s0 == s1

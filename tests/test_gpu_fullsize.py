@@ -172,13 +172,15 @@ def test_headline_launch_configuration(D, orc):
     b = torch.cat([D.dist_sources(V[0], T, t0), eta, D.dlma_project(g, t0, V[0], eta, 1)])
     del eta
     # one defect-correction pass brings every right-hand side to the inner tolerance's
-    # level (2e-3): a corrupted store in the solution update of some RHS shows as a
-    # few times worse residuals there and extra passes
-    opts1 = D.default_opts(tol=TOL, prec="mix_fp16", rhs_block=2, max_outer=1)
-    _, st1 = D.dlma_solve([g], [b], opts=opts1, allow_notconv=True)
-    worst = max(s["relres"] for s in st1)
-    print("one pass: worst relres %.3e" % worst, flush=True)
-    assert worst <= 5e-3, worst
+    # level (2e-3): a corrupted store in the solution update of some RHS shows as
+    # several times worse residuals there and extra passes.  CGNE's passes are uniform
+    # (1.4e-3 .. 3.6e-3 measured); BiCGStab's spread more (up to 1.1e-2 measured).
+    for solver, bound in ((0, 5e-3), (1, 3e-2)):
+        opts1 = D.default_opts(tol=TOL, prec="mix_fp16", rhs_block=2, max_outer=1, inner_solver=solver)
+        _, st1 = D.dlma_solve([g], [b], opts=opts1, allow_notconv=True)
+        worst = max(s["relres"] for s in st1)
+        print("one pass, inner solver %d: worst relres %.3e" % (solver, worst), flush=True)
+        assert worst <= bound, (solver, worst)
     opts = D.default_opts(tol=TOL, prec="mix_fp16", rhs_block=2)
     (x,), st = D.dlma_solve([g], [b], opts=opts)
     assert len(st) == 192
