@@ -38,8 +38,10 @@ KCLASS = {0: "hop_k1 (odd sites: y = A_oo^-1 D_oe x)",
           1: "hop_k1_dag (odd sites: y = A_oo^-1 D_oe g5 x)",
           2: "hop_k2_dag (even sites: w = A_ee x - g5 D_eo y, with |w|^2)",
           3: "hop_k2_cg (even sites: q = A_ee w - D_eo y fused with r -= alpha q, x += alpha w, |r|^2)",
-          4: "hop_k2 (even sites: z = A_ee x - D_eo y)"}
-KTEMPLATE = {0: (0, 0), 1: (0, 1), 2: (1, 6), 3: (1, 8), 4: (1, 0)}
+          4: "hop_k2 (even sites: z = A_ee x - D_eo y)",
+          8: "hop_k2_dotr (even sites: v = A_ee p - D_eo y with (rh, v))",
+          9: "hop_k2_dotx (even sites: t = A_ee s - D_eo y with (t, s) and |t|^2)"}
+KTEMPLATE = {0: (0, 0), 1: (0, 1), 2: (1, 6), 3: (1, 8), 4: (1, 0), 8: (1, 512), 9: (1, 256)}
 PREC_ID = {"fp64": 0, "mix_fp32": 1, "mix_fp16": 2, "mix_bf16": 3}
 HOP_SOURCES = ["paper_2201_09729_amd/csrc/hop.h", "paper_2201_09729_amd/csrc/hop16.h", "paper_2201_09729_amd/csrc/common.h",
                "paper_2201_09729_amd/csrc/hop_inst.h"]
@@ -64,7 +66,7 @@ def hop_bytes_split(prec, kind, flags, dims):
     if kind == 0:
         passes = 2 + (1 if flags & 64 else 0) + (1 if flags & 128 else 0)
     else:
-        passes = 6 if flags & 8 else 3 + (1 if flags & 16 else 0)
+        passes = 6 if flags & 8 else 3 + (1 if flags & 16 else 0) + (1 if flags & 512 else 0)
     return fixed, vh * passes * spinor_bytes(prec)
 
 
@@ -185,12 +187,12 @@ def main():
     # algorithmic bytes count only right-hand sides still iterating: a launch reads
     # every link and clover entry once, plus the spinor passes of each active
     # right-hand side; a right-hand side is active in inner_iters launches of each
-    # class per inner iteration of the solver: one for CG on the normal equations, two
-    # for BiCGStab (v = Dhat p and t = Dhat s).
+    # class per inner iteration: one per class, except BiCGStab's K1, which runs for
+    # v = Dhat p and for t = Dhat s.
     kc = max(prof, key=lambda k: prof[k][1])
     n_l, ms_tot, by_all = prof[kc]
     fixed, per_rhs = hop_bytes_split(args.prec, *KTEMPLATE[kc], DIMS)
-    per_iter = 2 if args.inner_solver == 1 else 1
+    per_iter = 2 if (args.inner_solver == 1 and kc == 0) else 1  # BiCGStab applies K1 twice per iteration
     rhs_launches = per_iter * sum(s["inner_iters"] for stp in stats for s in stp)
     by_tot = n_l * fixed + rhs_launches * per_rhs
     achieved = by_tot / (ms_tot * 1e-3) / 1e9

@@ -276,6 +276,9 @@ int dlma_dot(const void* a, const void* b, long n, double* out, void* stream);
  *   5 = lap_matvec  application of -lap (or of its Chebyshev polynomial)
  *   6 = lap_ortho   three-term recurrence, two classical Gram-Schmidt passes, normalisation
  *   7 = lap_ritz    Ritz vectors and Rayleigh-quotient residual checks
+ * and the stencils of the BiCGStab inner solver (K1 of both applications is class 0):
+ *   8 = hop_k2_dotr even sites, v = A_ee p - D_eo y, with (rh, v)
+ *   9 = hop_k2_dotx even sites, t = A_ee s - D_eo y, with (t, s) and |t|^2
  * dlma_profile_read returns the launch count, total milliseconds and total
  * algorithmic bytes (compulsory HBM traffic of the launches, summed) per class.
  */

@@ -66,13 +66,13 @@ struct Cfg {
 
 template <int P> struct Tables {
     // device job tables
-    Buf dresid, dprep, drecon;                 // HopJob<P64>
+    Buf dresid, dprep, drecon, dresidE;        // HopJob<P64> (dresidE: the residual's even-site jobs)
     Buf dvnB, dclov, dconv64, dacc64;          // VecJob<P64>
     Buf dconv, dacc, dxpay;                    // VecJob<P>
     Buf dvnE, dfinE;                           // |E|^2 (Schur source) jobs
     Buf dk1d, dk2d, dk1, dk2cg;                // HopJob<P>
     Buf dfinB, dfinR, dfinI, dfinAB;           // FinJob
-    int nresid = 0, nprep = 0, nrecon = 0, nvnB = 0, nclov = 0, nconv = 0, nk = 0, nfin = 0;
+    int nresid = 0, nprep = 0, nrecon = 0, nvnB = 0, nclov = 0, nconv = 0, nk = 0, nfin = 0, nresidE = 0, bresidE = 0;
     int bresid = 0, bprep = 0, brecon = 0, bvnB = 0, bclov = 0, bconv = 0, bxpay = 0, bvnE = 0;
     int bk1 = 0, bk2 = 0, bfin = 0;
     int nb64 = 1;                      // right-hand sides per thread of the FP64 outer stencils
@@ -134,7 +134,7 @@ template <int P> int alloc_cfg(Cfg& c, bool bicg, hipStream_t s) {
     }
     c.hnsb = hop_nsb(g->geo);
     c.vnsb = ceil_div(Vh, VEC_BS);
-    int pmax = std::max(std::max(2 * c.hnsb, 2 * c.vnsb), 3 * c.vnsb);
+    int pmax = std::max(std::max(2 * c.hnsb, 3 * c.vnsb), 3 * c.hnsb);
     DLMA_TRY(c.part.allocate(sizeof(double) * n * pmax));
     DLMA_TRY(c.dstate.allocate(sizeof(double) * 8 * n + sizeof(int) * 2 * n + 256));
     double* d = c.dstate.as<double>();
@@ -152,7 +152,7 @@ template <int P> int alloc_cfg(Cfg& c, bool bicg, hipStream_t s) {
 template <int P> float* nrm_of(const Buf& b) { return P == P16 ? b.as<float>() : nullptr; }
 
 template <int P> int build_tables(std::vector<Cfg>& cs, Tables<P>& t, int nb, int sg_in, int win, int nb64, int sg64, hipStream_t s) {
-    std::vector<HopJob<P64>> resid, prep, recon;
+    std::vector<HopJob<P64>> resid, prep, recon, residE;
     std::vector<VecJob<P64>> vnB, clov, conv64, acc64, vnE;
     std::vector<VecJob<P>> conv, acc, xpay;
     std::vector<HopJob<P>> k1d, k2d, k1, k2cg, bk1p, bk2v, bk1s, bk2t;
@@ -177,6 +177,7 @@ template <int P> int build_tables(std::vector<Cfg>& cs, Tables<P>& t, int nb, in
             j.pstride = 2 * c.hnsb;
             j.cb = 1.0; j.ca = -1.0; j.ch = 0.5;
             resid.push_back(j);
+            if (par == 0) residE.push_back(j);
             VecJob<P64> v = {};
             v.Vh = Vh; v.nrhs = n; v.nsb = c.vnsb;
             v.a = full_view(c.B.p, Vh, par);
@@ -265,9 +266,9 @@ template <int P> int build_tables(std::vector<Cfg>& cs, Tables<P>& t, int nb, in
                 SF<P> vs = half_view<P>(c.bs.p, nrm_of<P>(c.nbs), Vh), vt = half_view<P>(c.bt.p, nrm_of<P>(c.nbt), Vh);
                 SF<P> vrh = half_view<P>(c.brh.p, nrm_of<P>(c.nbrh), Vh);
                 HopJob<P> k1 = j1; k1.part = nullptr;
-                HopJob<P> k2 = j2; k2.part = nullptr;
+                HopJob<P> k2 = j2;  // partials of (rh, v), then of (t, s) and |t|^2 (hop_nq layout)
                 HopJob<P> a1 = k1; a1.in = vp; a1.out = vy; bk1p.push_back(a1);
-                HopJob<P> a2 = k2; a2.x = vp; a2.in = vy; a2.out = vw; bk2v.push_back(a2);
+                HopJob<P> a2 = k2; a2.x = vp; a2.in = vy; a2.out = vw; a2.r = vrh; bk2v.push_back(a2);
                 HopJob<P> a3 = k1; a3.in = vs; a3.out = vy; bk1s.push_back(a3);
                 HopJob<P> a4 = k2; a4.x = vs; a4.in = vy; a4.out = vt; bk2t.push_back(a4);
                 BiVecJob<P> bv = {};
@@ -277,7 +278,8 @@ template <int P> int build_tables(std::vector<Cfg>& cs, Tables<P>& t, int nb, in
                 bv.active = c.active; bv.part = c.part.as<double>(); bv.pstride = c.vnsb;
                 bvv.push_back(bv);
                 BiFinJob bf = {};
-                bf.nrhs = n; bf.rhs0 = rhs0BF; rhs0BF += n; bf.npart = c.vnsb; bf.part = c.part.as<double>();
+                bf.nrhs = n; bf.rhs0 = rhs0BF; rhs0BF += n; bf.npart = c.vnsb; bf.nparth = c.hnsb;
+                bf.part = c.part.as<double>();
                 bf.rho = c.brho; bf.alpha = c.balpha; bf.omega = c.bomega; bf.beta = c.bbeta;
                 bf.rr = c.rr; bf.tol2 = c.tol2; bf.active = c.active; bf.iters = c.iters; bf.maxit = 1 << 30;
                 bfv.push_back(bf);
@@ -294,6 +296,9 @@ template <int P> int build_tables(std::vector<Cfg>& cs, Tables<P>& t, int nb, in
         FinJob fa = f; fa.npart = c.hnsb; fa.rhs0 = rhs0AB; rhs0AB += n; finAB.push_back(fa);
     }
     t.bresid = assign_blocks(resid); t.bprep = assign_blocks(prep); t.brecon = assign_blocks(recon);
+    t.bresidE = assign_blocks(residE);
+    t.nresidE = (int)residE.size();
+    DLMA_TRY(upload(t.dresidE, residE, s));
     t.bvnB = assign_vec_blocks(vnB); t.bclov = assign_vec_blocks(clov);
     t.bconv = assign_vec_blocks(conv); assign_vec_blocks(conv64); assign_vec_blocks(acc); assign_vec_blocks(acc64);
     t.bvnE = assign_vec_blocks(vnE);
@@ -388,22 +393,21 @@ template <int P> int cg_iteration(std::vector<Cfg>& cs, Tables<P>& t, int nb, co
 // One BiCGStab iteration on Dhat for every configuration (the steps of bicg.hip with
 // the solver's stencil kernels for the two operator applications).
 template <int P> int bicg_iteration(std::vector<Cfg>& cs, Tables<P>& t, int nb, const std::vector<int>& nact, hipStream_t s) {
-    double b1 = 0, b2 = 0;
+    double b1 = 0, b2v = 0, b2t = 0;
     if (Profiler::get().on)
         for (size_t i = 0; i < cs.size(); ++i) {
             b1 += hop_bytes(P, K1, 0, cs[i].g->Vh, nact[i]);
-            b2 += hop_bytes(P, K2, 0, cs[i].g->Vh, nact[i]);
+            b2v += hop_bytes(P, K2, F_DOTR, cs[i].g->Vh, nact[i]);
+            b2t += hop_bytes(P, K2, F_DOTX, cs[i].g->Vh, nact[i]);
         }
     const BiVecJob<P>* bv = t.dbv.template as<BiVecJob<P>>();
     const BiFinJob* bf = t.dbf.template as<BiFinJob>();
     DLMA_TRY(hop_launch<P>(HopCfg{K1, 0, nb, t.wn}, t.dbk1p.p, t.nk, t.bk1, KC_K1, b1, s));
-    DLMA_TRY(hop_launch<P>(HopCfg{K2, 0, nb, t.wn}, t.dbk2v.p, t.nk, t.bk2, KC_K2, b2, s));
-    DLMA_HIP(launch_bivec<P>(bv, t.nbv, t.bbv, BV_RV, s));
+    DLMA_TRY(hop_launch<P>(HopCfg{K2, F_DOTR, nb, t.wn}, t.dbk2v.p, t.nk, t.bk2, KC_K2V, b2v, s));
     DLMA_HIP(launch_bifinish(bf, t.nbv, t.bbf, BF_ALPHA, s));
     DLMA_HIP(launch_bivec<P>(bv, t.nbv, t.bbv, BV_S, s));
     DLMA_TRY(hop_launch<P>(HopCfg{K1, 0, nb, t.wn}, t.dbk1s.p, t.nk, t.bk1, KC_K1, b1, s));
-    DLMA_TRY(hop_launch<P>(HopCfg{K2, 0, nb, t.wn}, t.dbk2t.p, t.nk, t.bk2, KC_K2, b2, s));
-    DLMA_HIP(launch_bivec<P>(bv, t.nbv, t.bbv, BV_TS, s));
+    DLMA_TRY(hop_launch<P>(HopCfg{K2, F_DOTX, nb, t.wn}, t.dbk2t.p, t.nk, t.bk2, KC_K2T, b2t, s));
     DLMA_HIP(launch_bifinish(bf, t.nbv, t.bbf, BF_OMEGA, s));
     DLMA_HIP(launch_bivec<P>(bv, t.nbv, t.bbv, BV_XR, s));
     DLMA_HIP(launch_bifinish(bf, t.nbv, t.bbf, BF_BETA, s));
@@ -514,6 +518,26 @@ int solve_impl(std::vector<Cfg>& cs, const dlma_solve_opts& o, hipStream_t s) {
     IterGraph ig;
     if (use_graph) check = o.graph_iters;
 
+    // After an odd-site reconstruction x_o += A_oo^-1 (r_o - D_oe e) the odd residual
+    // b_o - A_oo x_o - D_oe x_e vanishes up to FP64 rounding.  Passes after one then
+    // compute the residual on the even sites only, with R_o and T = A_oo^-1 R_o held
+    // at zero; the last pass confirms convergence with the full residual.
+    bool odd_zero = false;
+    auto true_residual = [&](bool even_only) -> int {
+        if (even_only) {
+            for (auto& c : cs)  // the odd sites' partial norms are zero
+                DLMA_HIP(hipMemset2DAsync(c.part.as<double>() + c.hnsb, 2 * sizeof(double) * c.hnsb, 0,
+                                          sizeof(double) * c.hnsb, c.nrhs, s));
+            DLMA_HIP(launch_hop<P64>(HopCfg{K2, F_HASB | F_NORM, t.nb64}, t.dresidE.template as<HopJob<P64>>(), t.nresidE,
+                                     t.bresidE, s));
+        } else {
+            DLMA_HIP(launch_hop<P64>(HopCfg{K2, F_HASB | F_NORM, t.nb64}, t.dresid.template as<HopJob<P64>>(), t.nresid, t.bresid, s));
+        }
+        DLMA_HIP(launch_finish(t.dfinR.template as<FinJob>(), t.nfin, t.bfin, FIN_NORM, s));
+        for (auto& c : cs) DLMA_HIP(hipMemcpyAsync(c.rnorm2.data(), c.nrm, sizeof(double) * c.nrhs, hipMemcpyDeviceToHost, s));
+        DLMA_HIP(hipStreamSynchronize(s));
+        return DLMA_OK;
+    };
     for (int pass = 0;; ++pass) {
         // true residual
         if (pass == 0 && !o.use_x0) {
@@ -522,10 +546,17 @@ int solve_impl(std::vector<Cfg>& cs, const dlma_solve_opts& o, hipStream_t s) {
                 c.rnorm2 = c.bnorm2;
             }
         } else {
-            DLMA_HIP(launch_hop<P64>(HopCfg{K2, F_HASB | F_NORM, t.nb64}, t.dresid.template as<HopJob<P64>>(), t.nresid, t.bresid, s));
-            DLMA_HIP(launch_finish(t.dfinR.template as<FinJob>(), t.nfin, t.bfin, FIN_NORM, s));
-            for (auto& c : cs) DLMA_HIP(hipMemcpyAsync(c.rnorm2.data(), c.nrm, sizeof(double) * c.nrhs, hipMemcpyDeviceToHost, s));
-            DLMA_HIP(hipStreamSynchronize(s));
+            DLMA_TRY(true_residual(odd_zero));
+            if (odd_zero) {  // all converged on the even sites: confirm with both parities
+                bool all = true;
+                for (auto& c : cs)
+                    for (int r = 0; r < c.nrhs && all; ++r)
+                        all = c.bnorm2[r] > 0 ? std::sqrt(c.rnorm2[r] / c.bnorm2[r]) <= o.tol : true;
+                if (all) {
+                    odd_zero = false;
+                    DLMA_TRY(true_residual(false));
+                }
+            }
         }
         int nleft = 0;
         int maxused = 0;
@@ -548,8 +579,8 @@ int solve_impl(std::vector<Cfg>& cs, const dlma_solve_opts& o, hipStream_t s) {
             std::fprintf(stderr, "[dlma] pass %d: %d rhs left, relres %.3e .. %.3e\n", pass, nleft, mn, mx);
         }
         if (nleft == 0 || pass >= o.max_outer || maxused >= o.maxiter) break;
-        // Schur source and inner start
-        DLMA_HIP(launch_clover_apply64(t.dclov.template as<VecJob<P64>>(), t.nclov, t.bclov, s));
+        // Schur source and inner start (T = A_oo^-1 R_o stays zero while R_o is)
+        if (!odd_zero) DLMA_HIP(launch_clover_apply64(t.dclov.template as<VecJob<P64>>(), t.nclov, t.bclov, s));
         DLMA_HIP(launch_hop<P64>(HopCfg{K2, F_NOA, t.nb64}, t.dprep.template as<HopJob<P64>>(), t.nprep, t.bprep, s));
         DLMA_HIP(launch_norm<P64>(t.dvnE.template as<VecJob<P64>>(), t.nconv, t.bvnE, s));
         DLMA_HIP(launch_finish(t.dfinE.template as<FinJob>(), t.nfin, t.bfin, FIN_NORM, s));
@@ -595,6 +626,14 @@ int solve_impl(std::vector<Cfg>& cs, const dlma_solve_opts& o, hipStream_t s) {
         // reconstruction
         DLMA_HIP(launch_accum_to64<P>(t.dacc.template as<VecJob<P>>(), t.dacc64.template as<VecJob<P64>>(), t.nconv, t.bconv, s));
         DLMA_HIP(launch_hop<P64>(HopCfg{K1, F_HASD | F_ACCUM, t.nb64}, t.drecon.template as<HopJob<P64>>(), t.nrecon, t.brecon, s));
+        if (!odd_zero) {  // every right-hand side now has r_o = 0: hold R_o and T at zero
+            for (auto& c : cs) {
+                const size_t hb = sizeof(double2) * 12 * (size_t)c.g->Vh;
+                DLMA_HIP(hipMemset2DAsync((char*)c.R.p + hb, 2 * hb, 0, hb, c.nrhs, s));
+                DLMA_HIP(hipMemsetAsync(c.T.p, 0, c.T.n, s));
+            }
+            odd_zero = true;
+        }
         for (auto& c : cs) DLMA_HIP(hipMemcpyAsync(c.hiters.data(), c.iters, sizeof(int) * c.nrhs, hipMemcpyDeviceToHost, s));
         DLMA_HIP(hipStreamSynchronize(s));
         for (auto& c : cs)

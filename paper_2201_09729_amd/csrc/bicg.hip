@@ -94,8 +94,7 @@ template <int P, int MODE> __global__ void __launch_bounds__(VEC_BS) k_bivec(con
                 c[2 * i + 1] = (R)((double)c[2 * i + 1] - (om.r * ti + om.i * tr));
             }
             store_spinor<P, R>(J.r, J.Vh, r, cb, c);
-            // the new residual as stored (its storage rounding included)
-            load_spinor<P, R>(J.r, J.Vh, r, cb, c);
+            // |r|^2 and (rh, r) of the new residual before its storage rounding
             load_spinor<P, R>(J.rh, J.Vh, r, cb, a);
             for (int i = 0; i < 12; ++i) {
                 const double hr = a[2 * i], hi = a[2 * i + 1], rr = c[2 * i], ri = c[2 * i + 1];
@@ -155,12 +154,13 @@ __global__ void __launch_bounds__(256) k_bifinish(const BiFinJob* jobs, int njob
     const int r = bid - J.rhs0;
     if (r >= J.nrhs) return;  // uniform over the block
     const int NQ = (mode == BF_ALPHA || mode == BF_INIT) ? 2 : 3;
+    const int np = (mode == BF_ALPHA || mode == BF_OMEGA) ? J.nparth : J.npart;
     __shared__ double lds[4];
     double q[3] = {0, 0, 0};
     for (int k = 0; k < NQ; ++k) {
         double v = 0;
-        const double* pp = J.part + ((size_t)r * NQ + k) * J.npart;
-        for (int i = threadIdx.x; i < J.npart; i += 256) v += pp[i];
+        const double* pp = J.part + ((size_t)r * NQ + k) * np;
+        for (int i = threadIdx.x; i < np; i += 256) v += pp[i];
         q[k] = block_sum<256>(v, lds);
     }
     if (threadIdx.x != 0) return;

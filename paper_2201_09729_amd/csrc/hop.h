@@ -32,7 +32,14 @@ enum HopFlags {
     F_NOA = 32,     // K2: identity instead of the clover matrix
     F_HASD = 64,    // K1: add d (taken from the x view)
     F_ACCUM = 128,  // K1: out += result
+    F_DOTX = 256,   // K2: partials of sum conj(out) x (re, im) and |out|^2
+    F_DOTR = 512,   // K2: partials of sum conj(r) out (re, im), r the job's r field
 };
+
+// Partial sums a stencil launch writes per right-hand side: F_DOTX 3, F_DOTR 2,
+// F_NORM or F_CG 1 (|out|^2 or the updated |r|^2).  Layout: one quantity at
+// part[r * pstride + block]; several at part[(r * NQ + q) * pstride + block].
+constexpr int hop_nq(int fl) { return (fl & F_DOTX) ? 3 : ((fl & F_DOTR) ? 2 : ((fl & (F_NORM | F_CG)) ? 1 : 0)); }
 
 template <int P> struct HopJob {
     Geo g;
@@ -91,9 +98,10 @@ HD void hop_dir(const HopJob<P>& J, const Nbr& nb, int cb, int g0, bool (&use)[N
         }
 }
 
-// Per-site body.  Returns the squared norms (of out, or of the updated r) in nrm2.
+// Per-site body.  Returns the site's contributions to the partial sums of hop_nq(FL)
+// quantities in qs.
 template <int P, int NB, int KIND, int FL>
-HD void hop_site(const HopJob<P>& J, int cb, int g0, double (&nrm2)[NB]) {
+HD void hop_site(const HopJob<P>& J, int cb, int g0, double (&qs)[NB][3]) {
     static_assert(P != P16, "FP16 fields take hop_site16");
     using R = typename PT<P>::R;
     const int Vh = J.g.Vh;
@@ -102,7 +110,7 @@ HD void hop_site(const HopJob<P>& J, int cb, int g0, double (&nrm2)[NB]) {
     for (int j = 0; j < NB; ++j) {
         int r = g0 + j;
         use[j] = r < J.nrhs && (J.active == nullptr || J.active[r] != 0);
-        nrm2[j] = 0.0;
+        qs[j][0] = qs[j][1] = qs[j][2] = 0.0;
     }
     R acc[NB][24];
 #pragma unroll
@@ -158,7 +166,7 @@ HD void hop_site(const HopJob<P>& J, int cb, int g0, double (&nrm2)[NB]) {
                     double s = 0;
 #pragma unroll
                     for (int i = 0; i < 24; ++i) s += (double)acc[j][i] * (double)acc[j][i];
-                    nrm2[j] = s;
+                    qs[j][0] = s;
                 }
             }
     } else {
@@ -212,7 +220,7 @@ HD void hop_site(const HopJob<P>& J, int cb, int g0, double (&nrm2)[NB]) {
                     double s = 0;
 #pragma unroll
                     for (int i = 0; i < 24; ++i) s += (double)rv[i] * (double)rv[i];
-                    nrm2[j] = s;
+                    qs[j][0] = s;
                     load_spinor<P, R>(J.x, Vh, g0 + j, cb, w);
                     load_spinor<P, R>(J.xs, Vh, g0 + j, cb, rv);
 #pragma unroll
@@ -220,11 +228,29 @@ HD void hop_site(const HopJob<P>& J, int cb, int g0, double (&nrm2)[NB]) {
                     store_spinor<P, R>(J.xs, Vh, g0 + j, cb, rv);
                 } else {
                     store_spinor<P, R>(J.out, Vh, g0 + j, cb, acc[j]);
-                    if (FL & F_NORM) {
+                    if (FL & (F_NORM | F_DOTX)) {
                         double s = 0;
 #pragma unroll
                         for (int i = 0; i < 24; ++i) s += (double)acc[j][i] * (double)acc[j][i];
-                        nrm2[j] = s;
+                        qs[j][(FL & F_DOTX) ? 2 : 0] = s;
+                    }
+                    if (FL & (F_DOTX | F_DOTR)) {
+                        R v[24];
+                        if (FL & F_DOTX) load_spinor<P, R>(J.x, Vh, g0 + j, cb, v);
+                        else load_spinor<P, R>(J.r, Vh, g0 + j, cb, v);
+                        double re = 0, im = 0;
+#pragma unroll
+                        for (int c = 0; c < 12; ++c) {
+                            // F_DOTX: conj(out) x; F_DOTR: conj(r) out
+                            const double ar = (FL & F_DOTX) ? acc[j][2 * c] : v[2 * c];
+                            const double ai = (FL & F_DOTX) ? acc[j][2 * c + 1] : v[2 * c + 1];
+                            const double br = (FL & F_DOTX) ? v[2 * c] : acc[j][2 * c];
+                            const double bi = (FL & F_DOTX) ? v[2 * c + 1] : acc[j][2 * c + 1];
+                            re += ar * br + ai * bi;
+                            im += ar * bi - ai * br;
+                        }
+                        qs[j][0] = re;
+                        qs[j][1] = im;
                     }
                 }
             }
@@ -258,8 +284,8 @@ template <int BS> __device__ __forceinline__ double block_sum(double v, double* 
 // The per-site body for the FP64, FP32 and BF16 fields (FP16 fields take the
 // raw-word path of hop16.h, called from the kernel directly).
 template <int P, int NB, int KIND, int FL>
-HD void site_body(const HopJob<P>& J, int cb, int g0, double (&nrm2)[NB]) {
-    hop_site<P, NB, KIND, FL>(J, cb, g0, nrm2);
+HD void site_body(const HopJob<P>& J, int cb, int g0, double (&qs)[NB][3]) {
+    hop_site<P, NB, KIND, FL>(J, cb, g0, qs);
 }
 
 // Occupancy floor per instantiation: the FP16 kernels with up to two right-hand
@@ -310,12 +336,13 @@ hop_kernel(const HopJob<P>* __restrict__ jobs, int njob, int wn_cap) {
     bool live = false;
 #pragma unroll
     for (int j = 0; j < NB; ++j) live = live || rhs_active(J, g0 + j);
+    constexpr int NQ = hop_nq(FL);
     if (!live) {
-        if ((FL & (F_NORM | F_CG)) && threadIdx.x < NB && g0 + (int)threadIdx.x < J.nrhs)
-            J.part[(size_t)(g0 + threadIdx.x) * J.pstride + sb] = 0.0;
+        if (NQ > 0 && (int)threadIdx.x < NB * NQ && g0 + (int)threadIdx.x / NQ < J.nrhs)
+            J.part[(size_t)(g0 * NQ + (int)threadIdx.x) * J.pstride + sb] = 0.0;
         return;
     }
-    double nrm2[NB];
+    double qs[NB][3];
     if constexpr (P == P16) {
         // Every thread runs the body, whose LDS staging has a block barrier: a thread
         // past the timeslice's last site works on that site and stores nothing.
@@ -324,22 +351,25 @@ hop_kernel(const HopJob<P>* __restrict__ jobs, int njob, int wn_cap) {
         const int ts0 = t * J.vt;
         const int wn = (J.wn > 0 && J.wn <= wn_cap) ? J.wn : 0;
         const Window16 win{wn, ts0 + s * BS - J.g.Xh, ts0, ts0 + J.vt, (LdsWords)hop_window};
-        hop_site16<NB, KIND, FL, BS>(J, valid ? cb : ts0 + J.vt - 1, g0, valid, win, nrm2);
+        hop_site16<NB, KIND, FL, BS>(J, valid ? cb : ts0 + J.vt - 1, g0, valid, win, qs);
     } else {
         if (sx < J.vt) {
-            site_body<P, NB, KIND, FL>(J, cb, g0, nrm2);
+            site_body<P, NB, KIND, FL>(J, cb, g0, qs);
         } else {
 #pragma unroll
-            for (int j = 0; j < NB; ++j) nrm2[j] = 0.0;
+            for (int j = 0; j < NB; ++j) qs[j][0] = qs[j][1] = qs[j][2] = 0.0;
         }
     }
-    if (FL & (F_NORM | F_CG)) {
+    if (NQ > 0) {
         __shared__ double lds[BS / 64];
 #pragma unroll
         for (int j = 0; j < NB; ++j) {
             if (g0 + j >= J.nrhs) break;  // uniform over the block
-            double s = block_sum<BS>(nrm2[j], lds);
-            if (threadIdx.x == 0) J.part[(size_t)(g0 + j) * J.pstride + sb] = s;
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                double s = block_sum<BS>(qs[j][q], lds);
+                if (threadIdx.x == 0) J.part[((size_t)(g0 + j) * NQ + q) * J.pstride + sb] = s;
+            }
         }
     }
 }

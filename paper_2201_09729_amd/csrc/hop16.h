@@ -463,11 +463,11 @@ HD void hop_dir16(const HopJob<P16>& J, const WSrc& U, const F16Field (&in)[NB],
     }
 }
 
-// out = ... as in hop_site (hop.h) for P16 fields; nrm2 as there.  Every thread of
-// the block calls it (W's staging has a block barrier); a thread with !valid works on
-// a real site but stores nothing and returns nrm2 = 0.
+// out = ... as in hop_site (hop.h) for P16 fields; the partial-sum contributions qs
+// as there.  Every thread of the block calls it (W's staging has a block barrier); a
+// thread with !valid works on a real site but stores nothing and returns qs = 0.
 template <int NB, int KIND, int FL, int BS>
-HD void hop_site16(const HopJob<P16>& J, int cb, int g0, bool valid, const Window16& W, double (&nrm2)[NB]) {
+HD void hop_site16(const HopJob<P16>& J, int cb, int g0, bool valid, const Window16& W, double (&qs)[NB][3]) {
     const uint32_t G16 = 16u * (uint32_t)J.g.Vh;  // bytes per 16-byte group plane
     const uint32_t site = (uint32_t)cb, lo = 4u * site, s16 = 16u * site;
     constexpr bool G5IN = (FL & F_G5IN) != 0;
@@ -480,7 +480,7 @@ HD void hop_site16(const HopJob<P16>& J, int cb, int g0, bool valid, const Windo
     for (int j = 0; j < NB; ++j) {
         const int r = g0 + j;
         use[j] = rhs_active(J, r);
-        nrm2[j] = 0.0;
+        qs[j][0] = qs[j][1] = qs[j][2] = 0.0;
         in[j] = f16_field(J.in, J.g.Vh, r);
         al[j] = CG ? (float)J.alpha[r < J.nrhs ? r : 0] : 0.f;
         // K2 with the CG update accumulates -alpha * out directly
@@ -550,7 +550,7 @@ HD void hop_site16(const HopJob<P16>& J, int cb, int g0, bool valid, const Windo
                 }
                 if (valid) {
                     const float q = store16(o, G16, site, acc[j]);
-                    if (FL & F_NORM) nrm2[j] = (double)q;
+                    if (FL & F_NORM) qs[j][0] = (double)q;
                 }
             }
     } else {
@@ -614,7 +614,7 @@ HD void hop_site16(const HopJob<P16>& J, int cb, int g0, bool valid, const Windo
                         acc[j][2 * c] = __builtin_fmaf(lo16(w), nr, acc[j][2 * c]);
                         acc[j][2 * c + 1] = __builtin_fmaf(hi16(w), nr, acc[j][2 * c + 1]);
                     }
-                    if (valid) nrm2[j] = (double)store16(rf, G16, site, acc[j]);
+                    if (valid) qs[j][0] = (double)store16(rf, G16, site, acc[j]);
                     // xs += alpha x
                     const F16Field sf = f16_field(J.xs, J.g.Vh, g0 + j);
                     const float ns = wldf<CP_NT>(sf.n, lo, 0), ax = al[j] * nx[j];
@@ -629,7 +629,34 @@ HD void hop_site16(const HopJob<P16>& J, int cb, int g0, bool valid, const Windo
                 } else if (valid) {
                     const F16Field o = f16_field(J.out, J.g.Vh, g0 + j);
                     const float q = store16(o, G16, site, acc[j]);
-                    if (FL & F_NORM) nrm2[j] = (double)q;
+                    if (FL & F_NORM) qs[j][0] = (double)q;
+                    if (FL & F_DOTX) {  // sum conj(out) x, with x's words and scale in registers
+                        float re = 0.f, im = 0.f;
+#pragma unroll
+                        for (int c = 0; c < 12; ++c) {
+                            const float xr = lo16(xw[j][c]), xi = hi16(xw[j][c]);
+                            re = __builtin_fmaf(acc[j][2 * c], xr, __builtin_fmaf(acc[j][2 * c + 1], xi, re));
+                            im = __builtin_fmaf(acc[j][2 * c], xi, __builtin_fmaf(-acc[j][2 * c + 1], xr, im));
+                        }
+                        qs[j][0] = (double)re * nx[j];
+                        qs[j][1] = (double)im * nx[j];
+                        qs[j][2] = (double)q;
+                    }
+                    if (FL & F_DOTR) {  // sum conj(r) out, r (the shadow residual) read at the own site
+                        const F16Field rf = f16_field(J.r, J.g.Vh, g0 + j);
+                        const float nr = wldf<CP_NT>(rf.n, lo, 0);
+                        uint32_t rw[12];
+                        load_words<CP_NT>(rf, s16, G16, rw);
+                        float re = 0.f, im = 0.f;
+#pragma unroll
+                        for (int c = 0; c < 12; ++c) {
+                            const float rr = lo16(rw[c]), ri = hi16(rw[c]);
+                            re = __builtin_fmaf(rr, acc[j][2 * c], __builtin_fmaf(ri, acc[j][2 * c + 1], re));
+                            im = __builtin_fmaf(rr, acc[j][2 * c + 1], __builtin_fmaf(-ri, acc[j][2 * c], im));
+                        }
+                        qs[j][0] = (double)re * nr;
+                        qs[j][1] = (double)im * nr;
+                    }
                 }
             }
     }

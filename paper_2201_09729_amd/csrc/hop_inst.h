@@ -30,6 +30,9 @@ hipError_t launch_hop<DLMA_PREC>(const HopCfg& c, const HopJob<DLMA_PREC>* djobs
     DLMA_HOP_ALLNB(K2, F_NORM)
     DLMA_HOP_ALLNB(K2, F_G5OUT | F_NORM)
     DLMA_HOP_ALLNB(K2, F_CG)
+    // BiCGStab: v = Dhat p with (rh, v); t = Dhat s with (t, s) and |t|^2
+    DLMA_HOP_ALLNB(K2, F_DOTR)
+    DLMA_HOP_ALLNB(K2, F_DOTX)
 #if DLMA_PREC == 0
     // FP64 only: full operator, defect-correction residual, Schur source, reconstruction
     DLMA_HOP_ALLNB(K2, F_G5IN | F_G5OUT)

@@ -59,7 +59,8 @@ template <int P> hipError_t launch_bivec(const BiVecJob<P>* j, int njob, int nbl
 // Per right-hand side scalars of BiCGStab from the partial sums (one block per rhs,
 // fixed order), with the CG state of FinJob (|r|^2, targets, flags, counts).
 struct BiFinJob {
-    int nrhs, rhs0, npart;     // npart: partials per quantity (the vector kernels' pstride)
+    int nrhs, rhs0, npart;     // npart: partials per quantity of the vector kernels (their pstride)
+    int nparth;                // the same for the stencil kernels (alpha's and omega's sums come from K2)
     const double* part;
     double2 *rho, *alpha, *omega, *beta;
     double *rr, *tol2;
@@ -67,6 +68,8 @@ struct BiFinJob {
     int maxit;
 };
 enum BiFinMode { BF_INIT = 0, BF_ALPHA = 1, BF_OMEGA = 2, BF_BETA = 3 };
+// BF_ALPHA reads (rh, v) from K2 with F_DOTR, BF_OMEGA (t, s) and |t|^2 from K2 with
+// F_DOTX (layout of hop_nq), BF_INIT and BF_BETA the vector kernels' sums.
 hipError_t launch_bifinish(const BiFinJob* j, int njob, int nblocks, int mode, hipStream_t s);
 
 // wn: LDS window sites per right-hand side of the launch's FP16 jobs (the largest

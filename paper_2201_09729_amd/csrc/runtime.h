@@ -169,7 +169,9 @@ enum KClass {
     KC_LAP_MATVEC = 5,  // Lanczos: applications of -lap (or of its Chebyshev polynomial)
     KC_LAP_ORTHO = 6,   // Lanczos: three-term step, two Gram-Schmidt passes, normalisation
     KC_LAP_RITZ = 7,    // Lanczos: Ritz vectors and Rayleigh-quotient residual checks
-    KC_N = 8
+    KC_K2V = 8,         // BiCGStab: v = Dhat p (K2 with (rh, v))
+    KC_K2T = 9,         // BiCGStab: t = Dhat s (K2 with (t, s), |t|^2)
+    KC_N = 10
 };
 
 struct Profiler {

@@ -57,7 +57,7 @@ def test_argument_validation_without_gpu(lib):
     assert lib.dlma_lap_eigs(None, 4, 0, 1, None, None, None, None, None) == -1
     assert lib.dlma_project(None, 0, 1, None, None, None, 1, 0, None) == -1
     assert lib.dlma_correlators(None, 0, 1, None, None, 0, 1, None, None, None, None) == -1
-    assert lib.dlma_profile_read(8, None, None, None) == -1  # classes are 0..7
+    assert lib.dlma_profile_read(10, None, None, None) == -1  # classes are 0..9
 
 
 def test_solve_opts_defaults(lib):
