@@ -67,12 +67,14 @@ struct Cfg {
 template <int P> struct Tables {
     // device job tables
     Buf dresid, dprep, drecon, dresidE;        // HopJob<P64> (dresidE: the residual's even-site jobs)
-    Buf dvnB, dclov, dconv64, dacc64;          // VecJob<P64>
+    Buf dresidO, dprep0, drecon0;              // HopJob<P64>: odd-site residual; pass-0 jobs reading B as R
+    Buf dvnB, dclov, dconv64, dacc64, dclov0;  // VecJob<P64>
     Buf dconv, dacc, dxpay;                    // VecJob<P>
     Buf dvnE, dfinE;                           // |E|^2 (Schur source) jobs
     Buf dk1d, dk2d, dk1, dk2cg;                // HopJob<P>
     Buf dfinB, dfinR, dfinI, dfinAB;           // FinJob
     int nresid = 0, nprep = 0, nrecon = 0, nvnB = 0, nclov = 0, nconv = 0, nk = 0, nfin = 0, nresidE = 0, bresidE = 0;
+    int nresidO = 0, bresidO = 0;
     int bresid = 0, bprep = 0, brecon = 0, bvnB = 0, bclov = 0, bconv = 0, bxpay = 0, bvnE = 0;
     int bk1 = 0, bk2 = 0, bfin = 0;
     int nb64 = 1;                      // right-hand sides per thread of the FP64 outer stencils
@@ -152,8 +154,8 @@ template <int P> int alloc_cfg(Cfg& c, bool bicg, hipStream_t s) {
 template <int P> float* nrm_of(const Buf& b) { return P == P16 ? b.as<float>() : nullptr; }
 
 template <int P> int build_tables(std::vector<Cfg>& cs, Tables<P>& t, int nb, int sg_in, int win, int nb64, int sg64, hipStream_t s) {
-    std::vector<HopJob<P64>> resid, prep, recon, residE;
-    std::vector<VecJob<P64>> vnB, clov, conv64, acc64, vnE;
+    std::vector<HopJob<P64>> resid, prep, recon, residE, residO, prep0, recon0;
+    std::vector<VecJob<P64>> vnB, clov, conv64, acc64, vnE, clov0;
     std::vector<VecJob<P>> conv, acc, xpay;
     std::vector<HopJob<P>> k1d, k2d, k1, k2cg, bk1p, bk2v, bk1s, bk2t;
     std::vector<FinJob> finB, finR, finI, finAB, finE;
@@ -177,7 +179,13 @@ template <int P> int build_tables(std::vector<Cfg>& cs, Tables<P>& t, int nb, in
             j.pstride = 2 * c.hnsb;
             j.cb = 1.0; j.ca = -1.0; j.ch = 0.5;
             resid.push_back(j);
-            if (par == 0) residE.push_back(j);
+            if (par == 0) {  // with R_o = 0 the even residual is the Schur source E itself
+                HopJob<P64> je = j;
+                je.out = half_view<P64>(c.E.p, nullptr, Vh);
+                residE.push_back(je);
+            } else {
+                residO.push_back(j);
+            }
             VecJob<P64> v = {};
             v.Vh = Vh; v.nrhs = n; v.nsb = c.vnsb;
             v.a = full_view(c.B.p, Vh, par);
@@ -192,6 +200,8 @@ template <int P> int build_tables(std::vector<Cfg>& cs, Tables<P>& t, int nb, in
             v.c = half_view<P64>(c.T.p, nullptr, Vh);
             v.C = g->Ci64.as<double2>();
             clov.push_back(v);
+            v.a = full_view(c.B.p, Vh, 1);  // first pass from x = 0: R = B
+            clov0.push_back(v);
         }
         {   // E = R_e + 1/2 H T
             HopJob<P64> j = hop_job<P64>(g, 0, n, nb64);
@@ -202,6 +212,8 @@ template <int P> int build_tables(std::vector<Cfg>& cs, Tables<P>& t, int nb, in
             j.out = half_view<P64>(c.E.p, nullptr, Vh);
             j.ca = 1.0; j.ch = 0.5;
             prep.push_back(j);
+            j.x = full_view(c.B.p, Vh, 0);
+            prep0.push_back(j);
         }
         {   // r = p = P(E), xs = 0 ; and accumulate E = xs, X_e += E
             VecJob<P> v = {};
@@ -244,6 +256,8 @@ template <int P> int build_tables(std::vector<Cfg>& cs, Tables<P>& t, int nb, in
             j.out = full_view(c.X.p, Vh, 1);
             j.ch = 0.5;
             recon.push_back(j);
+            j.x = full_view(c.B.p, Vh, 1);
+            recon0.push_back(j);
         }
         {   // inner CG stencils
             const typename PT<P>::S* U = (const typename PT<P>::S*)gauge_links(g, P);
@@ -299,6 +313,11 @@ template <int P> int build_tables(std::vector<Cfg>& cs, Tables<P>& t, int nb, in
     t.bresidE = assign_blocks(residE);
     t.nresidE = (int)residE.size();
     DLMA_TRY(upload(t.dresidE, residE, s));
+    t.bresidO = assign_blocks(residO);
+    t.nresidO = (int)residO.size();
+    DLMA_TRY(upload(t.dresidO, residO, s));
+    assign_blocks(prep0); assign_blocks(recon0); assign_vec_blocks(clov0);
+    DLMA_TRY(upload(t.dprep0, prep0, s)); DLMA_TRY(upload(t.drecon0, recon0, s)); DLMA_TRY(upload(t.dclov0, clov0, s));
     t.bvnB = assign_vec_blocks(vnB); t.bclov = assign_vec_blocks(clov);
     t.bconv = assign_vec_blocks(conv); assign_vec_blocks(conv64); assign_vec_blocks(acc); assign_vec_blocks(acc64);
     t.bvnE = assign_vec_blocks(vnE);
@@ -520,16 +539,21 @@ int solve_impl(std::vector<Cfg>& cs, const dlma_solve_opts& o, hipStream_t s) {
 
     // After an odd-site reconstruction x_o += A_oo^-1 (r_o - D_oe e) the odd residual
     // b_o - A_oo x_o - D_oe x_e vanishes up to FP64 rounding.  Passes after one then
-    // compute the residual on the even sites only, with R_o and T = A_oo^-1 R_o held
-    // at zero; the last pass confirms convergence with the full residual.
+    // compute the residual on the even sites only, straight into the Schur source E
+    // (with R_o = 0, T = A_oo^-1 R_o = 0 and E = R_e), and reconstruct without R_o.
+    // When every right-hand side has converged on the even sites, the odd-site
+    // residual of the same x completes the full norm that confirms it.
     bool odd_zero = false;
-    auto true_residual = [&](bool even_only) -> int {
-        if (even_only) {
+    auto true_residual = [&](int sites) -> int {  // 0 both parities, 1 even (odd partials 0), 2 odd (even kept)
+        if (sites == 1) {
             for (auto& c : cs)  // the odd sites' partial norms are zero
                 DLMA_HIP(hipMemset2DAsync(c.part.as<double>() + c.hnsb, 2 * sizeof(double) * c.hnsb, 0,
                                           sizeof(double) * c.hnsb, c.nrhs, s));
             DLMA_HIP(launch_hop<P64>(HopCfg{K2, F_HASB | F_NORM, t.nb64}, t.dresidE.template as<HopJob<P64>>(), t.nresidE,
                                      t.bresidE, s));
+        } else if (sites == 2) {
+            DLMA_HIP(launch_hop<P64>(HopCfg{K2, F_HASB | F_NORM, t.nb64}, t.dresidO.template as<HopJob<P64>>(), t.nresidO,
+                                     t.bresidO, s));
         } else {
             DLMA_HIP(launch_hop<P64>(HopCfg{K2, F_HASB | F_NORM, t.nb64}, t.dresid.template as<HopJob<P64>>(), t.nresid, t.bresid, s));
         }
@@ -539,22 +563,27 @@ int solve_impl(std::vector<Cfg>& cs, const dlma_solve_opts& o, hipStream_t s) {
         return DLMA_OK;
     };
     for (int pass = 0;; ++pass) {
-        // true residual
-        if (pass == 0 && !o.use_x0) {
-            for (auto& c : cs) {
-                DLMA_HIP(hipMemcpyAsync(c.R.p, c.B.p, c.B.n, hipMemcpyDeviceToDevice, s));
-                c.rnorm2 = c.bnorm2;
-            }
+        // true residual; from x = 0 it is b, and the first pass's jobs read B in place of R
+        const bool from_b = pass == 0 && !o.use_x0;
+        if (from_b) {
+            for (auto& c : cs) c.rnorm2 = c.bnorm2;
         } else {
-            DLMA_TRY(true_residual(odd_zero));
-            if (odd_zero) {  // all converged on the even sites: confirm with both parities
+            DLMA_TRY(true_residual(odd_zero ? 1 : 0));
+            if (odd_zero) {  // all converged on the even sites: add the odd sites of the same x
                 bool all = true;
                 for (auto& c : cs)
                     for (int r = 0; r < c.nrhs && all; ++r)
                         all = c.bnorm2[r] > 0 ? std::sqrt(c.rnorm2[r] / c.bnorm2[r]) <= o.tol : true;
                 if (all) {
-                    odd_zero = false;
-                    DLMA_TRY(true_residual(false));
+                    DLMA_TRY(true_residual(2));
+                    bool still = true;
+                    for (auto& c : cs)
+                        for (int r = 0; r < c.nrhs && still; ++r)
+                            still = c.bnorm2[r] > 0 ? std::sqrt(c.rnorm2[r] / c.bnorm2[r]) <= o.tol : true;
+                    if (!still) {  // rounding left an odd residual: start over from the full one
+                        odd_zero = false;
+                        DLMA_TRY(true_residual(0));
+                    }
                 }
             }
         }
@@ -579,11 +608,17 @@ int solve_impl(std::vector<Cfg>& cs, const dlma_solve_opts& o, hipStream_t s) {
             std::fprintf(stderr, "[dlma] pass %d: %d rhs left, relres %.3e .. %.3e\n", pass, nleft, mn, mx);
         }
         if (nleft == 0 || pass >= o.max_outer || maxused >= o.maxiter) break;
-        // Schur source and inner start (T = A_oo^-1 R_o stays zero while R_o is)
-        if (!odd_zero) DLMA_HIP(launch_clover_apply64(t.dclov.template as<VecJob<P64>>(), t.nclov, t.bclov, s));
-        DLMA_HIP(launch_hop<P64>(HopCfg{K2, F_NOA, t.nb64}, t.dprep.template as<HopJob<P64>>(), t.nprep, t.bprep, s));
-        DLMA_HIP(launch_norm<P64>(t.dvnE.template as<VecJob<P64>>(), t.nconv, t.bvnE, s));
-        DLMA_HIP(launch_finish(t.dfinE.template as<FinJob>(), t.nfin, t.bfin, FIN_NORM, s));
+        // Schur source E = R_e + 1/2 H_eo A_oo^-1 R_o and |E|^2; with R_o = 0 the
+        // even-site residual already wrote E, and its norm is the residual's
+        if (odd_zero) {
+            for (auto& c : cs) DLMA_HIP(hipMemcpyAsync(c.enrm, c.nrm, sizeof(double) * c.nrhs, hipMemcpyDeviceToDevice, s));
+        } else {
+            DLMA_HIP(launch_clover_apply64((from_b ? t.dclov0 : t.dclov).template as<VecJob<P64>>(), t.nclov, t.bclov, s));
+            DLMA_HIP(launch_hop<P64>(HopCfg{K2, F_NOA, t.nb64}, (from_b ? t.dprep0 : t.dprep).template as<HopJob<P64>>(),
+                                     t.nprep, t.bprep, s));
+            DLMA_HIP(launch_norm<P64>(t.dvnE.template as<VecJob<P64>>(), t.nconv, t.bvnE, s));
+            DLMA_HIP(launch_finish(t.dfinE.template as<FinJob>(), t.nfin, t.bfin, FIN_NORM, s));
+        }
         DLMA_HIP(launch_conv_from64<P>(t.dconv.template as<VecJob<P>>(), t.nconv, t.bconv, t.dconv64.template as<VecJob<P64>>(), s));
         for (auto& c : cs) DLMA_HIP(hipMemcpyAsync(c.active, c.hact.data(), sizeof(int) * c.nrhs, hipMemcpyHostToDevice, s));
         for (auto& f : t.hfinI) { f.rel2 = rel * rel; f.maxit = std::max(1, o.maxiter - maxused); }
@@ -625,15 +660,12 @@ int solve_impl(std::vector<Cfg>& cs, const dlma_solve_opts& o, hipStream_t s) {
         }
         // reconstruction
         DLMA_HIP(launch_accum_to64<P>(t.dacc.template as<VecJob<P>>(), t.dacc64.template as<VecJob<P64>>(), t.nconv, t.bconv, s));
-        DLMA_HIP(launch_hop<P64>(HopCfg{K1, F_HASD | F_ACCUM, t.nb64}, t.drecon.template as<HopJob<P64>>(), t.nrecon, t.brecon, s));
-        if (!odd_zero) {  // every right-hand side now has r_o = 0: hold R_o and T at zero
-            for (auto& c : cs) {
-                const size_t hb = sizeof(double2) * 12 * (size_t)c.g->Vh;
-                DLMA_HIP(hipMemset2DAsync((char*)c.R.p + hb, 2 * hb, 0, hb, c.nrhs, s));
-                DLMA_HIP(hipMemsetAsync(c.T.p, 0, c.T.n, s));
-            }
-            odd_zero = true;
-        }
+        if (odd_zero)
+            DLMA_HIP(launch_hop<P64>(HopCfg{K1, F_ACCUM, t.nb64}, t.drecon.template as<HopJob<P64>>(), t.nrecon, t.brecon, s));
+        else
+            DLMA_HIP(launch_hop<P64>(HopCfg{K1, F_HASD | F_ACCUM, t.nb64}, (from_b ? t.drecon0 : t.drecon).template as<HopJob<P64>>(),
+                                     t.nrecon, t.brecon, s));
+        odd_zero = true;  // every right-hand side now has r_o = 0 up to rounding
         for (auto& c : cs) DLMA_HIP(hipMemcpyAsync(c.hiters.data(), c.iters, sizeof(int) * c.nrhs, hipMemcpyDeviceToHost, s));
         DLMA_HIP(hipStreamSynchronize(s));
         for (auto& c : cs)

@@ -39,6 +39,7 @@ hipError_t launch_hop<DLMA_PREC>(const HopCfg& c, const HopJob<DLMA_PREC>* djobs
     DLMA_HOP_ALLNB(K2, F_HASB | F_NORM)
     DLMA_HOP_ALLNB(K2, F_NOA)
     DLMA_HOP_ALLNB(K1, F_HASD | F_ACCUM)
+    DLMA_HOP_ALLNB(K1, F_ACCUM)
 #endif
     return hipErrorInvalidValue;
 }
