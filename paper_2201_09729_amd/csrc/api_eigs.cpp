@@ -210,10 +210,13 @@ extern "C" int dlma_lap_eigs(dlma_gauge_t h, int nev, int t0, int nt, const void
     if (deg < 0) deg = 0;
     hipStream_t s = S(stream);
     const long isq = n, tsq = (long)(maxm + 1) * n;
-    Buf Q, R[3], Hc, AB, AY, LR, RZ;
+    Buf Q, R[3], Hc, AB, AY, LR, RZ, PA, PN;
     DLMA_TRY(Q.allocate(sizeof(double2) * tsq * nt));
     for (auto& b : R) DLMA_TRY(b.allocate(sizeof(double2) * n * nt));
-    DLMA_TRY(Hc.allocate(sizeof(double2) * (size_t)(maxm + 1) * nt));
+    DLMA_TRY(Hc.allocate(sizeof(double2) * (size_t)(maxm + 1) * nt * GS_NCH));
+    // block partials of alpha (from the stencil) and of |w|^2 (from the last Gram-Schmidt pass)
+    DLMA_TRY(PA.allocate(sizeof(double) * (size_t)lap_site_blocks(g->geo) * nt));
+    DLMA_TRY(PN.allocate(sizeof(double) * (size_t)gs_sub_blocks(n) * nt));
     DLMA_TRY(AB.allocate(sizeof(double) * 2 * (size_t)maxm * nt + 64));
     DLMA_TRY(AY.allocate(sizeof(double2) * (size_t)nt * nev * n));
     DLMA_TRY(LR.allocate(sizeof(double) * 2 * (size_t)nt * nev));
@@ -245,23 +248,32 @@ extern "C" int dlma_lap_eigs(dlma_gauge_t h, int nev, int t0, int nt, const void
     };
     const double vec_b = 16.0 * n * nt, link_b = 3.0 * 2.0 * 9.0 * 16.0 * L3 * nt;
 
-    // w = B q_j with B = -lap (cur_deg = 0) or T_deg((c - (-lap))/e)
+    // w = B q_j with B = -lap (cur_deg = 0) or T_deg((c - (-lap))/e); the last stencil
+    // also writes the block partials of Re <q_j, w> (alpha_j) to PA.  The recurrence
+    // reads q_j in place (stride tsq) and rotates through R[0..2].
+    double* apart = PA.as<double>();
+    const int nap = lap_site_blocks(g->geo);
     auto apply_op = [&](const double2* qj, double2*& w) -> int {
         if (cur_deg == 0) {
-            DLMA_HIP(launch_neg_lap(U64, g->geo, t0, qj, R[0].as<double2>(), tsq, n, nt, s));
+            DLMA_HIP(launch_neg_lap(U64, g->geo, t0, qj, R[0].as<double2>(), tsq, n, nt, s, 1, 0, 0, qj, apart));
             w = R[0].as<double2>();
             return DLMA_OK;
         }
-        double2 *a = R[0].as<double2>(), *b = R[1].as<double2>(), *c = R[2].as<double2>();
-        DLMA_HIP(hipMemcpy2DAsync(a, n * sizeof(double2), qj, tsq * sizeof(double2), n * sizeof(double2), nt,
-                                  hipMemcpyDeviceToDevice, s));
-        DLMA_HIP(launch_cheb_step(U64, g->geo, t0, a, nullptr, b, n, nt, cc, 1.0 / ee, s));
+        const double2* a = qj;
+        long tsa = tsq;
+        double2 *b = R[1].as<double2>(), *c = R[2].as<double2>(), *spare = R[0].as<double2>();
+        const bool last1 = cur_deg == 1;
+        DLMA_HIP(launch_cheb_step(U64, g->geo, t0, a, tsa, nullptr, 0, b, n, nt, cc, 1.0 / ee, s, last1 ? qj : nullptr, tsq,
+                                  last1 ? apart : nullptr));
         for (int k = 2; k <= cur_deg; ++k) {
-            DLMA_HIP(launch_cheb_step(U64, g->geo, t0, b, a, c, n, nt, cc, 2.0 / ee, s));
-            double2* t = a;
+            const bool last = k == cur_deg;
+            DLMA_HIP(launch_cheb_step(U64, g->geo, t0, b, n, a, tsa, c, n, nt, cc, 2.0 / ee, s, last ? qj : nullptr, tsq,
+                                      last ? apart : nullptr));
+            double2* freed = (a == qj) ? spare : const_cast<double2*>(a);  // never write q_j
             a = b;
+            tsa = n;
             b = c;
-            c = t;
+            c = freed;
         }
         w = b;
         return DLMA_OK;
@@ -350,12 +362,13 @@ extern "C" int dlma_lap_eigs(dlma_gauge_t h, int nev, int t0, int nt, const void
             DLMA_TRY(apply_op(q + (long)j * isq, w));
             t_end(ev, KC_LAP_MATVEC, (cur_deg > 0 ? cur_deg : 1) * (link_b + 2.0 * vec_b));
             t_begin(ev);
-            DLMA_HIP(launch_lanczos_three(q, tsq, isq, w, n, n, alpha, beta, maxm, j, nt, s, j > karrow));
+            DLMA_HIP(launch_lanczos_three_p(q, tsq, isq, w, n, n, apart, nap, alpha, beta, maxm, j, nt, s, j > karrow));
             for (int pass = 0; pass < 2; ++pass) {  // classical Gram-Schmidt against all q_i, twice
-                DLMA_HIP(launch_dots(q, tsq, isq, w, n, n, Hc.as<double2>(), maxm + 1, j + 1, nt, s));
-                DLMA_HIP(launch_sub_combo(q, tsq, isq, Hc.as<double2>(), maxm + 1, j + 1, w, n, n, nt, s));
+                DLMA_HIP(launch_gs_dots(q, tsq, isq, w, n, n, Hc.as<double2>(), maxm + 1, j + 1, nt, s));
+                DLMA_HIP(launch_gs_sub(q, tsq, isq, Hc.as<double2>(), maxm + 1, j + 1, w, n, n, nt,
+                                       pass == 1 ? PN.as<double>() : nullptr, s));
             }
-            DLMA_HIP(launch_normalize_into(w, n, q + (long)(j + 1) * isq, tsq, n, beta, maxm, j, nt, s));
+            DLMA_HIP(launch_scale_p(w, n, q + (long)(j + 1) * isq, tsq, n, PN.as<double>(), beta, maxm, j, nt, s));
             t_end(ev, KC_LAP_ORTHO, (4.0 * (j + 1) + 8.0) * vec_b);
             m = ++j;
             const bool last_step = step + 1 == msteps;

@@ -55,12 +55,13 @@ struct Cfg {
     Buf bs, bt, brh, nbs, nbt, nbrh;    // BiCGStab: s, t, shadow residual (precision P) and FP16 scales
     Buf bstate;                      // BiCGStab: rho alpha omega beta (complex, per rhs)
     double2 *brho = nullptr, *balpha = nullptr, *bomega = nullptr, *bbeta = nullptr;
-    Buf dstate;                      // rr rr0 alpha beta tol2 abs2 nrm (double) | active iters (int)
+    Buf dstate;                      // rr rr0 alpha beta tol2 abs2 nrm enrm (double) | active iters oact (int)
     int hnsb, vnsb;                  // site blocks of stencil and vector kernels
     double *rr, *rr0, *alpha, *beta, *tol2, *abs2, *nrm, *enrm;
     int *active, *iters;
+    int* oact;  // right-hand sides iterated in the last pass: the FP64 outer stencils skip the others
     std::vector<double> bnorm2, rnorm2, relres;
-    std::vector<int> used, conv, hact, hiters;
+    std::vector<int> used, conv, hact, hiters, hoact;
     int outer = 0;
 };
 
@@ -138,16 +139,17 @@ template <int P> int alloc_cfg(Cfg& c, bool bicg, hipStream_t s) {
     c.vnsb = ceil_div(Vh, VEC_BS);
     int pmax = std::max(std::max(2 * c.hnsb, 3 * c.vnsb), 3 * c.hnsb);
     DLMA_TRY(c.part.allocate(sizeof(double) * n * pmax));
-    DLMA_TRY(c.dstate.allocate(sizeof(double) * 8 * n + sizeof(int) * 2 * n + 256));
+    DLMA_TRY(c.dstate.allocate(sizeof(double) * 8 * n + sizeof(int) * 3 * n + 256));
     double* d = c.dstate.as<double>();
     c.rr = d; c.rr0 = d + n; c.alpha = d + 2 * n; c.beta = d + 3 * n; c.tol2 = d + 4 * n; c.abs2 = d + 5 * n;
     c.nrm = d + 6 * n;
     c.enrm = d + 7 * n;
     c.active = (int*)(d + 8 * n);
     c.iters = c.active + n;
-    DLMA_HIP(hipMemsetAsync(c.dstate.p, 0, sizeof(double) * 8 * n + sizeof(int) * 2 * n, s));
+    c.oact = c.iters + n;
+    DLMA_HIP(hipMemsetAsync(c.dstate.p, 0, sizeof(double) * 8 * n + sizeof(int) * 3 * n, s));
     c.bnorm2.assign(n, 0); c.rnorm2.assign(n, 0); c.relres.assign(n, 0);
-    c.used.assign(n, 0); c.conv.assign(n, 0); c.hact.assign(n, 0); c.hiters.assign(n, 0);
+    c.used.assign(n, 0); c.conv.assign(n, 0); c.hact.assign(n, 0); c.hiters.assign(n, 0); c.hoact.assign(n, 1);
     return DLMA_OK;
 }
 
@@ -178,13 +180,13 @@ template <int P> int build_tables(std::vector<Cfg>& cs, Tables<P>& t, int nb, in
             j.part = c.part.as<double>() + (size_t)par * c.hnsb;
             j.pstride = 2 * c.hnsb;
             j.cb = 1.0; j.ca = -1.0; j.ch = 0.5;
+            if (par == 1) residO.push_back(j);  // the final check covers every right-hand side
+            j.active = c.oact;  // converged right-hand sides keep their last residual
             resid.push_back(j);
             if (par == 0) {  // with R_o = 0 the even residual is the Schur source E itself
                 HopJob<P64> je = j;
                 je.out = half_view<P64>(c.E.p, nullptr, Vh);
                 residE.push_back(je);
-            } else {
-                residO.push_back(j);
             }
             VecJob<P64> v = {};
             v.Vh = Vh; v.nrhs = n; v.nsb = c.vnsb;
@@ -255,6 +257,7 @@ template <int P> int build_tables(std::vector<Cfg>& cs, Tables<P>& t, int nb, in
             j.x = full_view(c.R.p, Vh, 1);
             j.out = full_view(c.X.p, Vh, 1);
             j.ch = 0.5;
+            j.active = c.oact;  // E = 0 for the others
             recon.push_back(j);
             j.x = full_view(c.B.p, Vh, 1);
             recon0.push_back(j);
@@ -544,7 +547,15 @@ int solve_impl(std::vector<Cfg>& cs, const dlma_solve_opts& o, hipStream_t s) {
     // When every right-hand side has converged on the even sites, the odd-site
     // residual of the same x completes the full norm that confirms it.
     bool odd_zero = false;
-    auto true_residual = [&](int sites) -> int {  // 0 both parities, 1 even (odd partials 0), 2 odd (even kept)
+    // sites: 0 both parities, 1 even (odd partials 0), both for the right-hand sides of
+    // the last pass (the others keep their norms); 2 odd sites of every right-hand
+    // side, added to the norms held on the host
+    auto true_residual = [&](int sites) -> int {
+        if (sites == 2) {
+            for (auto& c : cs)
+                DLMA_HIP(hipMemset2DAsync(c.part.as<double>(), 2 * sizeof(double) * c.hnsb, 0, sizeof(double) * c.hnsb,
+                                          c.nrhs, s));
+        }
         if (sites == 1) {
             for (auto& c : cs)  // the odd sites' partial norms are zero
                 DLMA_HIP(hipMemset2DAsync(c.part.as<double>() + c.hnsb, 2 * sizeof(double) * c.hnsb, 0,
@@ -558,10 +569,27 @@ int solve_impl(std::vector<Cfg>& cs, const dlma_solve_opts& o, hipStream_t s) {
             DLMA_HIP(launch_hop<P64>(HopCfg{K2, F_HASB | F_NORM, t.nb64}, t.dresid.template as<HopJob<P64>>(), t.nresid, t.bresid, s));
         }
         DLMA_HIP(launch_finish(t.dfinR.template as<FinJob>(), t.nfin, t.bfin, FIN_NORM, s));
-        for (auto& c : cs) DLMA_HIP(hipMemcpyAsync(c.rnorm2.data(), c.nrm, sizeof(double) * c.nrhs, hipMemcpyDeviceToHost, s));
+        std::vector<std::vector<double>> got(cs.size());
+        for (size_t i = 0; i < cs.size(); ++i) {
+            got[i].resize(cs[i].nrhs);
+            DLMA_HIP(hipMemcpyAsync(got[i].data(), cs[i].nrm, sizeof(double) * cs[i].nrhs, hipMemcpyDeviceToHost, s));
+        }
         DLMA_HIP(hipStreamSynchronize(s));
+        for (size_t i = 0; i < cs.size(); ++i)
+            for (int r = 0; r < cs[i].nrhs; ++r) {
+                if (sites == 2) cs[i].rnorm2[r] += got[i][r];
+                else if (cs[i].hoact[r]) cs[i].rnorm2[r] = got[i][r];
+            }
         return DLMA_OK;
     };
+    auto upload_oact = [&](bool all) -> int {
+        for (auto& c : cs) {
+            if (all) std::fill(c.hoact.begin(), c.hoact.end(), 1);
+            DLMA_HIP(hipMemcpyAsync(c.oact, c.hoact.data(), sizeof(int) * c.nrhs, hipMemcpyHostToDevice, s));
+        }
+        return DLMA_OK;
+    };
+    DLMA_TRY(upload_oact(true));
     for (int pass = 0;; ++pass) {
         // true residual; from x = 0 it is b, and the first pass's jobs read B in place of R
         const bool from_b = pass == 0 && !o.use_x0;
@@ -582,6 +610,7 @@ int solve_impl(std::vector<Cfg>& cs, const dlma_solve_opts& o, hipStream_t s) {
                             still = c.bnorm2[r] > 0 ? std::sqrt(c.rnorm2[r] / c.bnorm2[r]) <= o.tol : true;
                     if (!still) {  // rounding left an odd residual: start over from the full one
                         odd_zero = false;
+                        DLMA_TRY(upload_oact(true));
                         DLMA_TRY(true_residual(0));
                     }
                 }
@@ -620,7 +649,11 @@ int solve_impl(std::vector<Cfg>& cs, const dlma_solve_opts& o, hipStream_t s) {
             DLMA_HIP(launch_finish(t.dfinE.template as<FinJob>(), t.nfin, t.bfin, FIN_NORM, s));
         }
         DLMA_HIP(launch_conv_from64<P>(t.dconv.template as<VecJob<P>>(), t.nconv, t.bconv, t.dconv64.template as<VecJob<P64>>(), s));
-        for (auto& c : cs) DLMA_HIP(hipMemcpyAsync(c.active, c.hact.data(), sizeof(int) * c.nrhs, hipMemcpyHostToDevice, s));
+        for (auto& c : cs) {
+            DLMA_HIP(hipMemcpyAsync(c.active, c.hact.data(), sizeof(int) * c.nrhs, hipMemcpyHostToDevice, s));
+            c.hoact = c.hact;
+        }
+        DLMA_TRY(upload_oact(false));
         for (auto& f : t.hfinI) { f.rel2 = rel * rel; f.maxit = std::max(1, o.maxiter - maxused); }
         for (auto& f : t.hfinAB) f.maxit = std::max(1, o.maxiter - maxused);
         DLMA_HIP(hipMemcpyAsync(t.dfinI.p, t.hfinI.data(), sizeof(FinJob) * t.hfinI.size(), hipMemcpyHostToDevice, s));

@@ -4,10 +4,16 @@
 
 namespace dlma {
 
+// qd (one vector per timeslice, nv = 1): also write the block partials of Re <qd, out>
+// to part[t * lap_site_blocks(g) + block]
+int lap_site_blocks(const Geo& g);
 hipError_t launch_neg_lap(const double2* U64, const Geo& g, int t0, const double2* in, double2* out, long tsi, long tso,
-                          int nt, hipStream_t s, int nv = 1, long vsi = 0, long vso = 0);
-hipError_t launch_cheb_step(const double2* U64, const Geo& g, int t0, const double2* in, const double2* prev, double2* out,
-                            long ts, int nt, double c1, double c2, hipStream_t s);
+                          int nt, hipStream_t s, int nv = 1, long vsi = 0, long vso = 0, const double2* qd = nullptr,
+                          double* part = nullptr);
+// ts*: timeslice strides of in, prev, out and qd
+hipError_t launch_cheb_step(const double2* U64, const Geo& g, int t0, const double2* in, long tsi, const double2* prev, long tsp,
+                            double2* out, long tso, int nt, double c1, double c2, hipStream_t s, const double2* qd = nullptr,
+                            long tsqd = 0, double* part = nullptr);
 hipError_t launch_rayleigh(const double2* y, const double2* ay, long n, int nvec, double* lam, double* res, hipStream_t s);
 hipError_t launch_dots(const double2* a, long tsa, long isa, const double2* b, long tsb, long n, double2* out, int ostride,
                        int ni, int nt, hipStream_t s);
@@ -17,6 +23,19 @@ hipError_t launch_sub_combo(const double2* q, long tsq, long isq, const double2*
 // whose couplings to the kept Ritz vectors the Gram-Schmidt passes remove)
 hipError_t launch_lanczos_three(const double2* q, long tsq, long isq, double2* w, long tsw, long n, double* alpha, double* beta,
                                 int astride, int j, int nt, hipStream_t s, bool prev = true);
+// Lanczos step with split reductions: alpha from the stencil's partials (nap per
+// timeslice), Gram-Schmidt dots in GS_NCH element chunks, |w|^2 partials from the last
+// subtraction (gs_sub_blocks(n) per timeslice) consumed by the normalisation
+constexpr int GS_NCH = 8;
+int gs_sub_blocks(long n);
+hipError_t launch_lanczos_three_p(const double2* q, long tsq, long isq, double2* w, long tsw, long n, const double* apart, int nap,
+                                  double* alpha, double* beta, int astride, int j, int nt, hipStream_t s, bool prev);
+hipError_t launch_gs_dots(const double2* a, long tsa, long isa, const double2* b, long tsb, long n, double2* hp, int hstride, int ni,
+                          int nt, hipStream_t s);
+hipError_t launch_gs_sub(const double2* q, long tsq, long isq, const double2* hp, int hstride, int ni, double2* w, long tsw, long n,
+                         int nt, double* npart, hipStream_t s);
+hipError_t launch_scale_p(const double2* w, long tsw, double2* q, long tsq, long n, const double* npart, double* nrm, int ostride,
+                          int j, int nt, hipStream_t s);
 hipError_t launch_normalize_into(const double2* w, long tsw, double2* q, long tsq, long n, double* nrm, int ostride, int j, int nt,
                                  hipStream_t s);
 hipError_t launch_ritz(const double2* q, long tsq, long isq, const double* S, int m, int nev, double2* y, long tsy, long n, int nt,

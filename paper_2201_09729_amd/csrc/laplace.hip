@@ -17,82 +17,99 @@ __device__ __forceinline__ double2 cconjmul(double2 a, double2 b) {  // conj(a) 
 struct LapMode {
     int cheb;            // 0: out = -lap in;  1: out = c2 (c1 in + lap in) - prev
     double c1, c2;
-    const double2* prev; // same addressing as in; nullptr = 0
+    const double2* prev; // timeslice stride tsp, vector stride as in; nullptr = 0
+    long tsp;
+    const double2* qd;   // one vector per timeslice (stride tsqd): block partials of Re <qd, out>; nullptr = none
+    long tsqd;
+    double* part;        // [nt][gridDim.x] partials for qd
 };
 
 // out = -lap(t) in = 6 in - sum_j [U_j(m,t) in(m+j) + U_j(m-j,t)^dag in(m-j)],  j = x, y, z,
 // for nv vectors on each of nt timeslices: vector (tl, kv) at base + tl*tstride + kv*vstride.
-__global__ void k_neg_lap(const double2* __restrict__ U64, Geo g, int t0, const double2* __restrict__ in,
-                          double2* __restrict__ out, long tstride_in, long tstride_out, int nt, int nv, long vstride_in,
-                          long vstride_out, LapMode md) {
+// Grid: (site blocks of one timeslice, nv, nt).
+__global__ void __launch_bounds__(256) k_neg_lap(const double2* __restrict__ U64, Geo g, int t0, const double2* __restrict__ in,
+                                                 double2* __restrict__ out, long tstride_in, long tstride_out, long vstride_in,
+                                                 long vstride_out, LapMode md) {
     const int L3 = g.Z * g.Y * g.X;
-    long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    int kv = blockIdx.y;
-    if (i >= (long)nt * L3 || kv >= nv) return;
-    int tl = (int)(i / L3);
-    int m = (int)(i - (long)tl * L3);
-    int t = t0 + tl;
-    int x = m % g.X, y = (m / g.X) % g.Y, z = m / (g.X * g.Y);
-    const double2* v = in + tl * tstride_in + kv * vstride_in;
-    double2 acc[3];
-    for (int a = 0; a < 3; ++a) {
-        double2 q = v[(long)m * 3 + a];
-        acc[a] = make_double2(6.0 * q.x, 6.0 * q.y);
-    }
-    for (int j = 1; j <= 3; ++j) {
-        int xf = x, yf = y, zf = z, xb = x, yb = y, zb = z;
-        if (j == 1) { xf = x + 1 == g.X ? 0 : x + 1; xb = x == 0 ? g.X - 1 : x - 1; }
-        if (j == 2) { yf = y + 1 == g.Y ? 0 : y + 1; yb = y == 0 ? g.Y - 1 : y - 1; }
-        if (j == 3) { zf = z + 1 == g.Z ? 0 : z + 1; zb = z == 0 ? g.Z - 1 : z - 1; }
-        int mf = (zf * g.Y + yf) * g.X + xf, mb = (zb * g.Y + yb) * g.X + xb;
-        // link U_j at (t, m) and at the backward neighbour (t, m - j)
-        int par = (t + z + y + x) & 1, parb = (t + zb + yb + xb) & 1;
-        long cb = (((long)t * g.Z + z) * g.Y + y) * g.Xh + (x >> 1);
-        long cbb = (((long)t * g.Z + zb) * g.Y + yb) * g.Xh + (xb >> 1);
-        const double2* uf = U64 + ((size_t)(par * 4 + j) * 9) * g.Vh + cb;
-        const double2* ub = U64 + ((size_t)(parb * 4 + j) * 9) * g.Vh + cbb;
-        double2 vf[3], vb[3];
-        for (int b = 0; b < 3; ++b) { vf[b] = v[(long)mf * 3 + b]; vb[b] = v[(long)mb * 3 + b]; }
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    const int kv = blockIdx.y, tl = blockIdx.z;
+    double dq = 0.0;
+    if (m < L3) {
+        const int t = t0 + tl;
+        int x = m % g.X, y = (m / g.X) % g.Y, z = m / (g.X * g.Y);
+        const double2* v = in + tl * tstride_in + kv * vstride_in;
+        double2 acc[3];
         for (int a = 0; a < 3; ++a) {
-            double2 s = make_double2(0, 0);
-            for (int b = 0; b < 3; ++b) {
-                double2 u = uf[(size_t)(a * 3 + b) * g.Vh];
-                double2 p = cmul2(u, vf[b]);
-                double2 w = ub[(size_t)(b * 3 + a) * g.Vh];  // (U^dag)_{ab} = conj(U_{ba})
-                double2 q = cconjmul(w, vb[b]);
-                s.x += p.x + q.x;
-                s.y += p.y + q.y;
+            double2 q = v[(long)m * 3 + a];
+            acc[a] = make_double2(6.0 * q.x, 6.0 * q.y);
+        }
+        for (int j = 1; j <= 3; ++j) {
+            int xf = x, yf = y, zf = z, xb = x, yb = y, zb = z;
+            if (j == 1) { xf = x + 1 == g.X ? 0 : x + 1; xb = x == 0 ? g.X - 1 : x - 1; }
+            if (j == 2) { yf = y + 1 == g.Y ? 0 : y + 1; yb = y == 0 ? g.Y - 1 : y - 1; }
+            if (j == 3) { zf = z + 1 == g.Z ? 0 : z + 1; zb = z == 0 ? g.Z - 1 : z - 1; }
+            int mf = (zf * g.Y + yf) * g.X + xf, mb = (zb * g.Y + yb) * g.X + xb;
+            // link U_j at (t, m) and at the backward neighbour (t, m - j)
+            int par = (t + z + y + x) & 1, parb = (t + zb + yb + xb) & 1;
+            long cb = (((long)t * g.Z + z) * g.Y + y) * g.Xh + (x >> 1);
+            long cbb = (((long)t * g.Z + zb) * g.Y + yb) * g.Xh + (xb >> 1);
+            const double2* uf = U64 + ((size_t)(par * 4 + j) * 9) * g.Vh + cb;
+            const double2* ub = U64 + ((size_t)(parb * 4 + j) * 9) * g.Vh + cbb;
+            double2 vf[3], vb[3];
+            for (int b = 0; b < 3; ++b) { vf[b] = v[(long)mf * 3 + b]; vb[b] = v[(long)mb * 3 + b]; }
+            for (int a = 0; a < 3; ++a) {
+                double2 s = make_double2(0, 0);
+                for (int b = 0; b < 3; ++b) {
+                    double2 u = uf[(size_t)(a * 3 + b) * g.Vh];
+                    double2 p = cmul2(u, vf[b]);
+                    double2 w = ub[(size_t)(b * 3 + a) * g.Vh];  // (U^dag)_{ab} = conj(U_{ba})
+                    double2 q = cconjmul(w, vb[b]);
+                    s.x += p.x + q.x;
+                    s.y += p.y + q.y;
+                }
+                acc[a].x -= s.x;
+                acc[a].y -= s.y;
             }
-            acc[a].x -= s.x;
-            acc[a].y -= s.y;
+        }
+        double2* o = out + tl * tstride_out + kv * vstride_out;
+        if (md.cheb) {
+            const double2* pv = md.prev ? md.prev + tl * md.tsp + kv * vstride_in : nullptr;
+            for (int a = 0; a < 3; ++a) {
+                double2 q = v[(long)m * 3 + a], pr = pv ? pv[(long)m * 3 + a] : make_double2(0.0, 0.0);
+                acc[a] = make_double2(md.c2 * (md.c1 * q.x - acc[a].x) - pr.x, md.c2 * (md.c1 * q.y - acc[a].y) - pr.y);
+            }
+        }
+        for (int a = 0; a < 3; ++a) o[(long)m * 3 + a] = acc[a];
+        if (md.qd) {
+            const double2* pq = md.qd + tl * md.tsqd + (long)m * 3;
+            for (int a = 0; a < 3; ++a) dq += pq[a].x * acc[a].x + pq[a].y * acc[a].y;
         }
     }
-    double2* o = out + tl * tstride_out + kv * vstride_out;
-    if (md.cheb) {
-        const double2* pv = md.prev ? md.prev + tl * tstride_in + kv * vstride_in : nullptr;
-        for (int a = 0; a < 3; ++a) {
-            double2 q = v[(long)m * 3 + a], pr = pv ? pv[(long)m * 3 + a] : make_double2(0.0, 0.0);
-            acc[a] = make_double2(md.c2 * (md.c1 * q.x - acc[a].x) - pr.x, md.c2 * (md.c1 * q.y - acc[a].y) - pr.y);
-        }
+    if (md.qd) {  // uniform over the grid
+        __shared__ double lds[4];
+        dq = block_sum<256>(dq, lds);
+        if (threadIdx.x == 0) md.part[(long)tl * gridDim.x + blockIdx.x] = dq;
     }
-    for (int a = 0; a < 3; ++a) o[(long)m * 3 + a] = acc[a];
 }
 
+int lap_site_blocks(const Geo& g) { return (g.Z * g.Y * g.X + 255) / 256; }
+
 hipError_t launch_neg_lap(const double2* U64, const Geo& g, int t0, const double2* in, double2* out, long tsi, long tso,
-                          int nt, hipStream_t s, int nv, long vsi, long vso) {
-    long n = (long)nt * g.Z * g.Y * g.X;
-    LapMode md = {0, 0.0, 0.0, nullptr};
-    hipLaunchKernelGGL(k_neg_lap, dim3((unsigned)((n + 255) / 256), nv), dim3(256), 0, s, U64, g, t0, in, out, tsi, tso, nt, nv,
+                          int nt, hipStream_t s, int nv, long vsi, long vso, const double2* qd, double* part) {
+    if (nt <= 0 || nv <= 0) return hipSuccess;
+    LapMode md = {0, 0.0, 0.0, nullptr, 0L, qd, tsi, part};
+    hipLaunchKernelGGL(k_neg_lap, dim3((unsigned)lap_site_blocks(g), nv, nt), dim3(256), 0, s, U64, g, t0, in, out, tsi, tso,
                        vsi, vso, md);
     return hipGetLastError();
 }
 
 // out = c2 * (c1 * in - (-lap) in) - prev  (one step of the Chebyshev three-term recurrence)
-hipError_t launch_cheb_step(const double2* U64, const Geo& g, int t0, const double2* in, const double2* prev, double2* out,
-                            long ts, int nt, double c1, double c2, hipStream_t s) {
-    long n = (long)nt * g.Z * g.Y * g.X;
-    LapMode md = {1, c1, c2, prev};
-    hipLaunchKernelGGL(k_neg_lap, dim3((unsigned)((n + 255) / 256), 1), dim3(256), 0, s, U64, g, t0, in, out, ts, ts, nt, 1, 0L,
+hipError_t launch_cheb_step(const double2* U64, const Geo& g, int t0, const double2* in, long tsi, const double2* prev, long tsp,
+                            double2* out, long tso, int nt, double c1, double c2, hipStream_t s, const double2* qd, long tsqd,
+                            double* part) {
+    if (nt <= 0) return hipSuccess;
+    LapMode md = {1, c1, c2, prev, tsp, qd, tsqd, part};
+    hipLaunchKernelGGL(k_neg_lap, dim3((unsigned)lap_site_blocks(g), 1, nt), dim3(256), 0, s, U64, g, t0, in, out, tsi, tso, 0L,
                        0L, md);
     return hipGetLastError();
 }
@@ -260,6 +277,152 @@ hipError_t launch_normalize_into(const double2* w, long tsw, double2* q, long ts
                                  hipStream_t s) {
     hipLaunchKernelGGL(k_norm_t, dim3(nt), dim3(256), 0, s, w, tsw, n, nrm, ostride, j);
     hipLaunchKernelGGL(k_scale_into, dim3((unsigned)((n + 255) / 256), nt), dim3(256), 0, s, w, tsw, q, tsq, n, nrm, ostride, j);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- Lanczos step, split reductions
+//
+// A Lanczos step on one timeslice reduces over 3 L^3 elements several times; one
+// block per reduction leaves most of the chip idle and waits on a long serial loop.
+// Here every reduction is split over blocks that write partial sums, and the
+// kernel that consumes the result adds the partials in a fixed order (the same on
+// every thread, so the result is deterministic).
+
+// alpha_t = sum of the block partials of Re <q_j, w> written by the stencil that
+// produced w; w -= alpha_t q_j + beta_{j-1} q_{j-1}
+__global__ void k_lanczos_three_p(const double2* __restrict__ qj, const double2* __restrict__ qjm, long tsq,
+                                  double2* __restrict__ w, long tsw, long n, const double* __restrict__ apart, int nap,
+                                  double* __restrict__ alpha, const double* __restrict__ beta, int astride, int j, int prev) {
+    long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    int t = blockIdx.y;
+    double a = 0.0;
+    for (int b = 0; b < nap; ++b) a += apart[(long)t * nap + b];
+    if (blockIdx.x == 0 && threadIdx.x == 0) alpha[(long)t * astride + j] = a;
+    if (e >= n) return;
+    double2 v = w[t * tsw + e];
+    double2 c = qj[t * tsq + e];
+    v.x -= a * c.x;
+    v.y -= a * c.y;
+    if (prev) {
+        double b = beta[(long)t * astride + j - 1];
+        double2 d = qjm[t * tsq + e];
+        v.x -= b * d.x;
+        v.y -= b * d.y;
+    }
+    w[t * tsw + e] = v;
+}
+
+hipError_t launch_lanczos_three_p(const double2* q, long tsq, long isq, double2* w, long tsw, long n, const double* apart, int nap,
+                                  double* alpha, double* beta, int astride, int j, int nt, hipStream_t s, bool prev) {
+    const double2* qjm = j > 0 ? q + (long)(j - 1) * isq : q;
+    hipLaunchKernelGGL(k_lanczos_three_p, dim3((unsigned)((n + 255) / 256), nt), dim3(256), 0, s, q + (long)j * isq, qjm, tsq, w,
+                       tsw, n, apart, nap, alpha, beta, astride, j, (prev && j > 0) ? 1 : 0);
+    return hipGetLastError();
+}
+
+// Partial dots hp[(t * GS_NCH + ch) * hstride + i] = <a_{t,i}, b_t> over chunk ch of the elements
+__global__ void __launch_bounds__(256) k_gs_dots(const double2* __restrict__ a, long tsa, long isa, const double2* __restrict__ b,
+                                                 long tsb, long n, double2* __restrict__ hp, int hstride) {
+    __shared__ double lds[4];
+    const int i = blockIdx.x, ch = blockIdx.y, t = blockIdx.z;
+    const long clen = (n + GS_NCH - 1) / GS_NCH;
+    const long e0 = ch * clen, e1 = e0 + clen < n ? e0 + clen : n;
+    const double2* pa = a + t * tsa + i * isa;
+    const double2* pb = b + t * tsb;
+    double2 s = make_double2(0, 0);
+    for (long e = e0 + threadIdx.x; e < e1; e += 256) {
+        double2 p = cconjmul(pa[e], pb[e]);
+        s.x += p.x;
+        s.y += p.y;
+    }
+    s = block_sum2<256>(s, lds);
+    if (threadIdx.x == 0) hp[((long)t * GS_NCH + ch) * hstride + i] = s;
+}
+
+hipError_t launch_gs_dots(const double2* a, long tsa, long isa, const double2* b, long tsb, long n, double2* hp, int hstride, int ni,
+                          int nt, hipStream_t s) {
+    if (ni <= 0 || nt <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gs_dots, dim3(ni, GS_NCH, nt), dim3(256), 0, s, a, tsa, isa, b, tsb, n, hp, hstride);
+    return hipGetLastError();
+}
+
+// w_t -= sum_{i < ni} q_{t,i} h_{t,i} with h the sum of the GS_NCH partials (added into LDS
+// tile by tile); with npart, also the block partials of |w_t|^2 after the update
+__global__ void __launch_bounds__(256) k_gs_sub(const double2* __restrict__ q, long tsq, long isq, const double2* __restrict__ hp,
+                                                int hstride, int ni, double2* __restrict__ w, long tsw, long n,
+                                                double* __restrict__ npart) {
+    constexpr int TILE = 1024;
+    __shared__ double2 h[TILE];
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int t = blockIdx.y;
+    const double2* pq = q + t * tsq + e;
+    double2 s = make_double2(0, 0);
+    for (int i0 = 0; i0 < ni; i0 += TILE) {
+        const int nk = ni - i0 < TILE ? ni - i0 : TILE;
+        __syncthreads();
+        for (int k = threadIdx.x; k < nk; k += 256) {
+            double2 v = make_double2(0, 0);
+            for (int ch = 0; ch < GS_NCH; ++ch) {
+                double2 p = hp[((long)t * GS_NCH + ch) * hstride + i0 + k];
+                v.x += p.x;
+                v.y += p.y;
+            }
+            h[k] = v;
+        }
+        __syncthreads();
+        if (e < n)
+            for (int k = 0; k < nk; ++k) {
+                double2 c = cmul2(pq[(long)(i0 + k) * isq], h[k]);
+                s.x += c.x;
+                s.y += c.y;
+            }
+    }
+    double nn = 0.0;
+    if (e < n) {
+        double2* pw = w + t * tsw + e;
+        double2 v = *pw;
+        v.x -= s.x;
+        v.y -= s.y;
+        *pw = v;
+        nn = v.x * v.x + v.y * v.y;
+    }
+    if (npart) {  // uniform over the grid
+        __shared__ double lds[4];
+        nn = block_sum<256>(nn, lds);
+        if (threadIdx.x == 0) npart[(long)t * gridDim.x + blockIdx.x] = nn;
+    }
+}
+
+int gs_sub_blocks(long n) { return (int)((n + 255) / 256); }
+
+hipError_t launch_gs_sub(const double2* q, long tsq, long isq, const double2* hp, int hstride, int ni, double2* w, long tsw, long n,
+                         int nt, double* npart, hipStream_t s) {
+    if (nt <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gs_sub, dim3((unsigned)gs_sub_blocks(n), nt), dim3(256), 0, s, q, tsq, isq, hp, hstride, ni, w, tsw, n,
+                       npart);
+    return hipGetLastError();
+}
+
+// beta_t = sqrt(sum of the nnp block partials of |w_t|^2); q_{j+1} = w / beta
+// (beta below 1e-300 leaves q_{j+1} = 0)
+__global__ void k_scale_p(const double2* __restrict__ w, long tsw, double2* __restrict__ q, long tsq, long n,
+                          const double* __restrict__ npart, int nnp, double* __restrict__ nrm, int ostride, int j) {
+    long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    int t = blockIdx.y;
+    double s = 0.0;
+    for (int b = 0; b < nnp; ++b) s += npart[(long)t * nnp + b];
+    const double bt = sqrt(s);
+    if (blockIdx.x == 0 && threadIdx.x == 0) nrm[(long)t * ostride + j] = bt;
+    if (e >= n) return;
+    double inv = bt > 1e-300 ? 1.0 / bt : 0.0;
+    double2 v = w[t * tsw + e];
+    q[t * tsq + e] = make_double2(v.x * inv, v.y * inv);
+}
+
+hipError_t launch_scale_p(const double2* w, long tsw, double2* q, long tsq, long n, const double* npart, double* nrm, int ostride,
+                          int j, int nt, hipStream_t s) {
+    hipLaunchKernelGGL(k_scale_p, dim3((unsigned)gs_sub_blocks(n), nt), dim3(256), 0, s, w, tsw, q, tsq, n, npart,
+                       gs_sub_blocks(n), nrm, ostride, j);
     return hipGetLastError();
 }
 
