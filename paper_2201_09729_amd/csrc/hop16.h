@@ -441,7 +441,8 @@ template <int NB, int MU, bool G5IN, bool G5OUT, bool WIN>
 HD void hop_dir16(const HopJob<P16>& J, const WSrc& U, const F16Field (&in)[NB], const Nbr& nb, uint32_t site,
                   const bool (&use)[NB], const float (&sc)[NB], const Window16& W, float (&acc)[NB][24]) {
     const uint32_t Vh = (uint32_t)J.g.Vh;
-    uint32_t u[9], w[12];
+    uint32_t u[9], w[NB][12];
+    float n[NB];
 #pragma unroll
     for (int d = 0; d < 2; ++d) {
         const uint32_t ns = (uint32_t)nb.n[2 * MU + d];
@@ -450,15 +451,18 @@ HD void hop_dir16(const HopJob<P16>& J, const WSrc& U, const F16Field (&in)[NB],
 #pragma unroll
         for (int j = 0; j < NB; ++j)
             if (use[j]) {
-                float n;
                 if (WIN) {
-                    n = window_words<NB>(W, in[j], j, ns, 16u * Vh, w);
+                    n[j] = window_words<NB>(W, in[j], j, ns, 16u * Vh, w[j]);
                 } else {
-                    load_words(in[j], 16u * ns, 16u * Vh, w);
-                    n = wldf(in[j].n, 4u * ns, 0);
+                    load_words(in[j], 16u * ns, 16u * Vh, w[j]);
+                    n[j] = wldf(in[j].n, 4u * ns, 0);
                 }
-                if (d == 0) hop_term16<MU, true, G5IN, G5OUT>(u, w, n * sc[j], acc[j]);
-                else hop_term16<MU, false, G5IN, G5OUT>(u, w, n * sc[j], acc[j]);
+            }
+#pragma unroll
+        for (int j = 0; j < NB; ++j)
+            if (use[j]) {
+                if (d == 0) hop_term16<MU, true, G5IN, G5OUT>(u, w[j], n[j] * sc[j], acc[j]);
+                else hop_term16<MU, false, G5IN, G5OUT>(u, w[j], n[j] * sc[j], acc[j]);
             }
     }
 }
