@@ -226,6 +226,7 @@ template <int P> int build_tables(std::vector<Cfg>& cs, Tables<P>& t, int nb, in
             v.part = c.part.as<double>();
             v.pstride = c.vnsb;
             v.s = c.enrm;
+            v.active = c.oact;  // the others keep r, p, xs (xs is not added to x for them)
             conv.push_back(v);
             VecJob<P64> v64 = {};
             v64.Vh = Vh; v64.nrhs = n; v64.nsb = c.vnsb;
@@ -637,6 +638,13 @@ int solve_impl(std::vector<Cfg>& cs, const dlma_solve_opts& o, hipStream_t s) {
             std::fprintf(stderr, "[dlma] pass %d: %d rhs left, relres %.3e .. %.3e\n", pass, nleft, mn, mx);
         }
         if (nleft == 0 || pass >= o.max_outer || maxused >= o.maxiter) break;
+        // right-hand sides iterated in this pass: the inner solver's flags and the mask
+        // of the FP64 kernels (conversion, accumulation, reconstruction, next residual)
+        for (auto& c : cs) {
+            DLMA_HIP(hipMemcpyAsync(c.active, c.hact.data(), sizeof(int) * c.nrhs, hipMemcpyHostToDevice, s));
+            c.hoact = c.hact;
+        }
+        DLMA_TRY(upload_oact(false));
         // Schur source E = R_e + 1/2 H_eo A_oo^-1 R_o and |E|^2; with R_o = 0 the
         // even-site residual already wrote E, and its norm is the residual's
         if (odd_zero) {
@@ -649,11 +657,6 @@ int solve_impl(std::vector<Cfg>& cs, const dlma_solve_opts& o, hipStream_t s) {
             DLMA_HIP(launch_finish(t.dfinE.template as<FinJob>(), t.nfin, t.bfin, FIN_NORM, s));
         }
         DLMA_HIP(launch_conv_from64<P>(t.dconv.template as<VecJob<P>>(), t.nconv, t.bconv, t.dconv64.template as<VecJob<P64>>(), s));
-        for (auto& c : cs) {
-            DLMA_HIP(hipMemcpyAsync(c.active, c.hact.data(), sizeof(int) * c.nrhs, hipMemcpyHostToDevice, s));
-            c.hoact = c.hact;
-        }
-        DLMA_TRY(upload_oact(false));
         for (auto& f : t.hfinI) { f.rel2 = rel * rel; f.maxit = std::max(1, o.maxiter - maxused); }
         for (auto& f : t.hfinAB) f.maxit = std::max(1, o.maxiter - maxused);
         DLMA_HIP(hipMemcpyAsync(t.dfinI.p, t.hfinI.data(), sizeof(FinJob) * t.hfinI.size(), hipMemcpyHostToDevice, s));

@@ -459,6 +459,10 @@ template <int P> __global__ void __launch_bounds__(VEC_BS) k_conv_from64(const V
     vec_locate(jobs, njob, J, r, cb, sb);
     const VecJob<P64>* S = &j64[J - jobs];
     double nrm = 0;
+    if (J->active && !J->active[r]) {  // right-hand side not iterated this pass (uniform per block)
+        if (threadIdx.x == 0) J->part[(long)r * J->pstride + sb] = 0.0;
+        return;
+    }
     if (cb < J->Vh) {
         double x[24];
         load_spinor<P64, double>(S->a, J->Vh, r, cb, x);
@@ -478,12 +482,19 @@ template <int P> hipError_t launch_conv_from64(const VecJob<P>* j, int njob, int
     return hipGetLastError();
 }
 
-// e64 = |bhat| e (back to the scale of the Schur source, FP64), x64 += e64
+// e64 = |bhat| e (back to the scale of the Schur source, FP64), x64 += e64; a right-hand
+// side not iterated this pass gets e64 = 0 and keeps x64
 template <int P> __global__ void __launch_bounds__(VEC_BS) k_accum_to64(const VecJob<P>* jobs, const VecJob<P64>* j64, int njob) {
     const VecJob<P>* J; int r, cb, sb;
     vec_locate(jobs, njob, J, r, cb, sb);
     if (cb >= J->Vh) return;
     const VecJob<P64>* S = &j64[J - jobs];
+    if (J->active && !J->active[r]) {
+        double z[24];
+        for (int i = 0; i < 24; ++i) z[i] = 0.0;
+        store_spinor<P64, double>(S->a, J->Vh, r, cb, z);
+        return;
+    }
     typename PT<P>::R e[24];
     load_spinor<P, typename PT<P>::R>(J->a, J->Vh, r, cb, e);
     double sc = sqrt(J->s[r]);
