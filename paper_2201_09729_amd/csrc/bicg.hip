@@ -35,6 +35,99 @@ __device__ __forceinline__ void bi_partial(double v, double* part, long idx) {
 
 }  // namespace
 
+// FP16 fields: the steps of one iteration in FP32 arithmetic on the raw words (128-bit
+// loads and stores of the grouped layout, scales folded into the arithmetic).  FP32
+// carries the 11-bit storage values and the FP64 scalars with margin; the partial
+// sums are added in FP64.  Returns the NQ partial-sum contributions of the site.
+HD void bv16_cplx(const uint32_t w[12], float n, float v[24]) {
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+        v[2 * c] = lo16(w[c]) * n;
+        v[2 * c + 1] = hi16(w[c]) * n;
+    }
+}
+
+template <int MODE> HD void bivec16(const BiVecJob<P16>& J, int r, uint32_t site, double& q0, double& q1, double& q2) {
+    const uint32_t Vh = (uint32_t)J.Vh, G16 = 16u * Vh, s16 = 16u * site, lo = 4u * site;
+    uint32_t wa[12], wb[12], wc[12];
+    float a[24], b[24], c[24];
+    if (MODE == BV_S) {  // s = r - alpha v
+        const F16Field R = f16_field(J.r, J.Vh, r), V = f16_field(J.v, J.Vh, r), S = f16_field(J.s, J.Vh, r);
+        const float ar = (float)J.alpha[r].x, ai = (float)J.alpha[r].y;
+        load_words<CP_NT>(R, s16, G16, wa);
+        load_words<CP_NT>(V, s16, G16, wb);
+        const float nr = wldf<CP_NT>(R.n, lo, 0), nv = wldf<CP_NT>(V.n, lo, 0);
+        bv16_cplx(wa, nr, a);
+        bv16_cplx(wb, nv, b);
+#pragma unroll
+        for (int i = 0; i < 12; ++i) {
+            c[2 * i] = a[2 * i] - (ar * b[2 * i] - ai * b[2 * i + 1]);
+            c[2 * i + 1] = a[2 * i + 1] - (ar * b[2 * i + 1] + ai * b[2 * i]);
+        }
+        (void)store16(S, G16, site, c);
+    } else if (MODE == BV_XR) {  // x += alpha p + omega s; r = s - omega t; |r|^2, (rh, r)
+        const F16Field X = f16_field(J.x, J.Vh, r), Pp = f16_field(J.p, J.Vh, r), S = f16_field(J.s, J.Vh, r);
+        const F16Field T = f16_field(J.t, J.Vh, r), R = f16_field(J.r, J.Vh, r), RH = f16_field(J.rh, J.Vh, r);
+        const float alr = (float)J.alpha[r].x, ali = (float)J.alpha[r].y;
+        const float omr = (float)J.omega[r].x, omi = (float)J.omega[r].y;
+        load_words<CP_NT>(X, s16, G16, wa);
+        load_words<CP_NT>(Pp, s16, G16, wb);
+        load_words<CP_NT>(S, s16, G16, wc);
+        const float nx = wldf<CP_NT>(X.n, lo, 0), np = wldf<CP_NT>(Pp.n, lo, 0), ns = wldf<CP_NT>(S.n, lo, 0);
+        bv16_cplx(wa, nx, a);
+        bv16_cplx(wb, np, b);
+        bv16_cplx(wc, ns, c);
+#pragma unroll
+        for (int i = 0; i < 12; ++i) {
+            const float pr = b[2 * i], pi = b[2 * i + 1], sr = c[2 * i], si = c[2 * i + 1];
+            a[2 * i] += alr * pr - ali * pi + omr * sr - omi * si;
+            a[2 * i + 1] += alr * pi + ali * pr + omr * si + omi * sr;
+        }
+        (void)store16(X, G16, site, a);
+        load_words<CP_NT>(T, s16, G16, wb);
+        const float nt = wldf<CP_NT>(T.n, lo, 0);
+        bv16_cplx(wb, nt, b);
+#pragma unroll
+        for (int i = 0; i < 12; ++i) {
+            const float tr = b[2 * i], ti = b[2 * i + 1];
+            c[2 * i] -= omr * tr - omi * ti;
+            c[2 * i + 1] -= omr * ti + omi * tr;
+        }
+        // |r|^2 and (rh, r) of the new residual before its storage rounding
+        q0 = (double)store16(R, G16, site, c);
+        load_words<CP_NT>(RH, s16, G16, wa);
+        const float nh = wldf<CP_NT>(RH.n, lo, 0);
+        float re = 0.f, im = 0.f;
+#pragma unroll
+        for (int i = 0; i < 12; ++i) {
+            const float hr = lo16(wa[i]), hi = hi16(wa[i]), rr = c[2 * i], ri = c[2 * i + 1];
+            re = __builtin_fmaf(hr, rr, __builtin_fmaf(hi, ri, re));
+            im = __builtin_fmaf(hr, ri, __builtin_fmaf(-hi, rr, im));
+        }
+        q1 = (double)re * nh;
+        q2 = (double)im * nh;
+    } else {  // BV_P: p = r + beta (p - omega v)
+        const F16Field R = f16_field(J.r, J.Vh, r), Pp = f16_field(J.p, J.Vh, r), V = f16_field(J.v, J.Vh, r);
+        const float ber = (float)J.beta[r].x, bei = (float)J.beta[r].y;
+        const float omr = (float)J.omega[r].x, omi = (float)J.omega[r].y;
+        load_words<CP_NT>(R, s16, G16, wa);
+        load_words<CP_NT>(Pp, s16, G16, wb);
+        load_words<CP_NT>(V, s16, G16, wc);
+        const float nr = wldf<CP_NT>(R.n, lo, 0), np = wldf<CP_NT>(Pp.n, lo, 0), nv = wldf<CP_NT>(V.n, lo, 0);
+        bv16_cplx(wa, nr, a);
+        bv16_cplx(wb, np, b);
+        bv16_cplx(wc, nv, c);
+#pragma unroll
+        for (int i = 0; i < 12; ++i) {
+            const float dr = b[2 * i] - (omr * c[2 * i] - omi * c[2 * i + 1]);
+            const float di = b[2 * i + 1] - (omr * c[2 * i + 1] + omi * c[2 * i]);
+            b[2 * i] = a[2 * i] + ber * dr - bei * di;
+            b[2 * i + 1] = a[2 * i + 1] + ber * di + bei * dr;
+        }
+        (void)store16(Pp, G16, site, b);
+    }
+}
+
 template <int P, int MODE> __global__ void __launch_bounds__(VEC_BS) k_bivec(const BiVecJob<P>* jobs, int njob) {
     using R = typename PT<P>::R;
     const int bid = blockIdx.x;
@@ -45,9 +138,11 @@ template <int P, int MODE> __global__ void __launch_bounds__(VEC_BS) k_bivec(con
     const int r = lb / J.nsb;
     const int sb = lb - r * J.nsb;
     const int cb = sb * VEC_BS + (int)threadIdx.x;
-    const bool act = J.active == nullptr || J.active[r] != 0;  // uniform over the block
+    const bool act = rhs_active(J, r);  // uniform over the block
     double q0 = 0, q1 = 0, q2 = 0;
-    if (act && cb < J.Vh) {
+    if constexpr (P == P16 && (MODE == BV_S || MODE == BV_XR || MODE == BV_P)) {
+        if (act && cb < J.Vh) bivec16<MODE>(J, r, (uint32_t)cb, q0, q1, q2);
+    } else if (act && cb < J.Vh) {
         R a[24], b[24], c[24];
         if (MODE == BV_RR || MODE == BV_RV) {
             load_spinor<P, R>(J.rh, J.Vh, r, cb, a);

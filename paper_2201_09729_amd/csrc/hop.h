@@ -63,6 +63,25 @@ template <int P> struct HopJob {
     double ca, cb, ch;
 };
 
+// A value the caller knows to be the same on every lane, marked as such so that
+// branches on it and values merged after them stay in scalar registers.
+HD int wave_uniform(int v) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_readfirstlane(v);
+#else
+    return v;
+#endif
+}
+
+// Whether right-hand side r of job J is still iterating.  Every branch here is on
+// a wave-uniform value (the flag is read once and marked uniform), so the values
+// that meet after it (field addresses, buffer resources) stay in scalar registers.
+template <class Job> HD bool rhs_active(const Job& J, int r) {
+    if (r >= J.nrhs) return false;
+    if (J.active == nullptr) return true;
+    return wave_uniform(J.active[r]) != 0;
+}
+
 template <int P, class R> HD void load_half_spinor(const SF<P>& f, int Vh, int r, int cb, int blk, R s[12]) {
     static_assert(P != P16, "FP16 fields use the grouped layout of hop16.h");
     const typename PT<P>::S* b = f.v + (size_t)r * f.rs + (size_t)blk * 6 * Vh + cb;
@@ -109,7 +128,7 @@ HD void hop_site(const HopJob<P>& J, int cb, int g0, double (&qs)[NB][3]) {
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
         int r = g0 + j;
-        use[j] = r < J.nrhs && (J.active == nullptr || J.active[r] != 0);
+        use[j] = rhs_active(J, r);
         qs[j][0] = qs[j][1] = qs[j][2] = 0.0;
     }
     R acc[NB][24];

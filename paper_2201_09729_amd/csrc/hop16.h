@@ -105,25 +105,6 @@ HD void wst4(const WSrc& s, uint32_t v, uint32_t u, u32x4 w) {
 #endif
 }
 
-// A value the caller knows to be the same on every lane, marked as such so that
-// branches on it and values merged after them stay in scalar registers.
-HD int wave_uniform(int v) {
-#if defined(__HIP_DEVICE_COMPILE__)
-    return __builtin_amdgcn_readfirstlane(v);
-#else
-    return v;
-#endif
-}
-
-// Whether right-hand side r of job J is still iterating.  Every branch here is on
-// a wave-uniform value (the flag is read once and marked uniform), so the values
-// that meet after it (field addresses, buffer resources) stay in scalar registers.
-template <class Job> HD bool rhs_active(const Job& J, int r) {
-    if (r >= J.nrhs) return false;
-    if (J.active == nullptr) return true;
-    return wave_uniform(J.active[r]) != 0;
-}
-
 // binary16 halves of a word, widened where they are consumed
 HD float lo16(uint32_t w) { return (float)__builtin_bit_cast(_Float16, (uint16_t)(w & 0xffffu)); }
 HD float hi16(uint32_t w) { return (float)__builtin_bit_cast(_Float16, (uint16_t)(w >> 16)); }
