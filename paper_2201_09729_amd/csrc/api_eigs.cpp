@@ -343,12 +343,12 @@ extern "C" int dlma_lap_eigs(dlma_gauge_t h, int nev, int t0, int nt, const void
     // thick restart the basis never exceeds maxm vectors: when it is full, the keep
     // Ritz vectors of the wanted end replace it, the last Lanczos vector follows them,
     // and the run continues from there (convergence is tested once per cycle).
-    auto lanczos = [&](long msteps, bool largest, bool checks, int& m, bool& conv) -> int {
+    auto lanczos = [&](long msteps, bool largest, bool checks, int& m, bool& conv, const double2* start) -> int {
         conv = false;
         m = 0;
         karrow = 0;
         int next_check = check, restarts = 0;
-        DLMA_HIP(launch_normalize_into((const double2*)v0, n, q, tsq, n, beta, maxm, 0, nt, s));
+        DLMA_HIP(launch_normalize_into(start, n, q, tsq, n, beta, maxm, 0, nt, s));
         DLMA_HIP(hipMemcpyAsync(hb.data(), beta, sizeof(double) * maxm * nt, hipMemcpyDeviceToHost, s));
         DLMA_HIP(hipStreamSynchronize(s));
         for (int t = 0; t < nt; ++t)
@@ -455,7 +455,7 @@ extern "C" int dlma_lap_eigs(dlma_gauge_t h, int nev, int t0, int nt, const void
         // short unfiltered run: Ritz values are upper bounds of the lowest eigenvalues,
         // so the (nev + nev/4 + 4)-th one lies above every wanted eigenvalue
         int m0 = (int)std::min<long>(std::min(maxm, std::max(2 * nev + 20, 40)), n);
-        DLMA_TRY(lanczos(m0, false, false, m, conv));
+        DLMA_TRY(lanczos(m0, false, false, m, conv, (const double2*)v0));
         DLMA_HIP(hipMemcpyAsync(ha.data(), alpha, sizeof(double) * maxm * nt, hipMemcpyDeviceToHost, s));
         DLMA_HIP(hipMemcpyAsync(hb.data(), beta, sizeof(double) * maxm * nt, hipMemcpyDeviceToHost, s));
         DLMA_HIP(hipStreamSynchronize(s));
@@ -474,7 +474,48 @@ extern "C" int dlma_lap_eigs(dlma_gauge_t h, int nev, int t0, int nt, const void
             ee = 0.5 * (12.0 - cut);
         }
     }
-    DLMA_TRY(lanczos(restart ? (long)(max_restarts + 1) * maxm : (long)maxm, cur_deg > 0, true, m, conv));
+    // Second estimate of the cut (not with thick restart, whose cycles keep one filter):
+    // the unfiltered run's Ritz values lie far above the eigenvalues beyond the wanted
+    // ones, so the first cut damps too little of the spectrum.  A short filtered run
+    // resolves the top of the filtered spectrum; its (nev + nev/4)-th largest Ritz value
+    // theta maps back through the filter to lambda(theta) = c - e cosh(acosh(theta)/deg),
+    // an upper bound of that eigenvalue of -lap.  The final run uses the new cut and
+    // starts from the sum of the short run's wanted Ritz vectors.
+    const double2* start = (const double2*)v0;
+    const int mB = (int)std::min<long>(std::min(maxm - 1, nev + std::max(20, nev / 2)), n - 1);
+    if (cur_deg > 0 && !restart && mB > nev + nev / 4) {
+        DLMA_TRY(lanczos(mB, true, false, m, conv, start));
+        DLMA_HIP(hipMemcpyAsync(ha.data(), alpha, sizeof(double) * maxm * nt, hipMemcpyDeviceToHost, s));
+        DLMA_HIP(hipMemcpyAsync(hb.data(), beta, sizeof(double) * maxm * nt, hipMemcpyDeviceToHost, s));
+        DLMA_HIP(hipStreamSynchronize(s));
+        double cut2 = 0;
+        std::vector<double> Ssum((size_t)nt * m, 0.0);
+        bool ok = true;
+        for (int t = 0; t < nt && ok; ++t) {
+            std::vector<double> d, Z;
+            if (!proj_eig(t, m, d, &Z, nullptr)) { ok = false; break; }
+            std::vector<int> idx = argsort(d);
+            std::reverse(idx.begin(), idx.end());
+            const double th = d[idx[nev + nev / 4]];
+            const double lam = th > 1.0 ? cc - ee * std::cosh(std::acosh(th) / cur_deg) : 12.0;
+            cut2 = std::max(cut2, lam);
+            for (int k = 0; k < nev; ++k)
+                for (int i = 0; i < m; ++i) Ssum[(size_t)t * m + i] += Z[(size_t)i * m + idx[k]];
+        }
+        if (!ok) return fail(DLMA_EHIP, "tridiagonal eigensolver did not converge");
+        if (cut2 < cc - ee) {  // a lower cut than the first (cc - ee is the current cut)
+            cc = 0.5 * (cut2 + 12.0);
+            ee = 0.5 * (12.0 - cut2);
+        }
+        // start vector: q times the summed coefficients (one Ritz combination per timeslice)
+        Buf Sd;
+        DLMA_TRY(Sd.allocate(sizeof(double) * Ssum.size()));
+        DLMA_HIP(hipMemcpyAsync(Sd.p, Ssum.data(), sizeof(double) * Ssum.size(), hipMemcpyHostToDevice, s));
+        DLMA_HIP(launch_ritz(q, tsq, isq, Sd.as<double>(), m, 1, AY.as<double2>(), n, n, nt, s));
+        DLMA_HIP(hipStreamSynchronize(s));  // Sd's device copy lives in this scope
+        start = AY.as<double2>();
+    }
+    DLMA_TRY(lanczos(restart ? (long)(max_restarts + 1) * maxm : (long)maxm, cur_deg > 0, true, m, conv, start));
     if (!conv) {  // basis cap reached: report the last Ritz pairs
         bool ok = false;
         DLMA_TRY(ritz_check(m, cur_deg > 0, ok));
