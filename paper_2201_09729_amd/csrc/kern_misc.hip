@@ -354,39 +354,59 @@ hipError_t launch_regroup16(const double2* src, void* dst, int M, int K, int G, 
 
 // ---------------------------------------------------------------- canonical <-> even-odd
 
-__global__ void k_canon_to_eo(const double2* __restrict__ can, double2* __restrict__ eo, Geo g, int nrhs, int g5) {
-    long V = 2L * g.Vh;
-    long s = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    int r = blockIdx.y;
-    if (s >= V) return;
-    Coord c = coord_of(g, s);
-    int par = (c.c[0] + c.c[1] + c.c[2] + c.c[3]) & 1;
-    long cb = s >> 1;
-    const double2* src = can + ((size_t)r * V + s) * 12;
-    double2* dst = eo + ((size_t)r * 2 + par) * 12 * g.Vh + cb;
-#pragma unroll
-    for (int k = 0; k < 12; ++k) {
-        double2 v = src[k];
-        if (g5 && k >= 6) v = make_double2(-v.x, -v.y);  // g5 = diag(1,1,-1,-1) in spin
-        dst[(size_t)k * g.Vh] = v;
-    }
-}
+// Layout conversion between the canonical order (per right-hand side: sites in
+// lexicographic order, 12 complex components each) and the even-odd solver order
+// (per right-hand side and parity: 12 component planes of Vh sites).  A block moves
+// 256 consecutive canonical sites of one right-hand side through LDS, so that both
+// sides are read and written in long contiguous runs: the canonical side as one
+// 48 KB span, the even-odd side as runs of consecutive checkerboard indices within
+// a component plane (the sites s and s+1 of a pair share s/2 and have opposite
+// parities; X is even).
+constexpr int LAYOUT_BS = 256;
 
-__global__ void k_eo_to_canon(const double2* __restrict__ eo, double2* __restrict__ can, Geo g, int nrhs, int g5) {
-    long V = 2L * g.Vh;
-    long s = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    int r = blockIdx.y;
-    if (s >= V) return;
-    Coord c = coord_of(g, s);
-    int par = (c.c[0] + c.c[1] + c.c[2] + c.c[3]) & 1;
-    long cb = s >> 1;
-    const double2* src = eo + ((size_t)r * 2 + par) * 12 * g.Vh + cb;
-    double2* dst = can + ((size_t)r * V + s) * 12;
+template <bool TO_EO>
+__global__ void __launch_bounds__(LAYOUT_BS) k_layout(const double2* __restrict__ src, double2* __restrict__ dst, Geo g, int g5) {
+    __shared__ double2 buf[LAYOUT_BS * 12];
+    const long V = 2L * g.Vh;
+    const int r = blockIdx.y;
+    const long s0 = (long)blockIdx.x * LAYOUT_BS;
+    const int ns = (int)(V - s0 < LAYOUT_BS ? V - s0 : LAYOUT_BS);  // sites in this block (even)
+    const size_t eo0 = (size_t)r * 2 * 12 * g.Vh;
+    // pair q = site pair (s0 + 2q, s0 + 2q + 1), half h selects one of them
+    const int q = (int)threadIdx.x & (LAYOUT_BS / 2 - 1), h = (int)threadIdx.x / (LAYOUT_BS / 2);
+    const long sp = s0 + 2 * q + h;
+    int par = 0;
+    if (2 * q + h < ns) {
+        const Coord c = coord_of(g, sp);
+        par = (c.c[0] + c.c[1] + c.c[2] + c.c[3]) & 1;
+    }
+    const long cb = sp >> 1;
+    if (TO_EO) {
+        const double2* can = src + ((size_t)r * V + s0) * 12;
+        for (int e = threadIdx.x; e < ns * 12; e += LAYOUT_BS) buf[e] = can[e];
+        __syncthreads();
+        if (2 * q + h < ns) {
+            double2* o = dst + eo0 + (size_t)par * 12 * g.Vh + cb;
 #pragma unroll
-    for (int k = 0; k < 12; ++k) {
-        double2 v = src[(size_t)k * g.Vh];
-        if (g5 && k >= 6) v = make_double2(-v.x, -v.y);
-        dst[k] = v;
+            for (int k = 0; k < 12; ++k) {
+                double2 v = buf[(2 * q + h) * 12 + k];
+                if (g5 && k >= 6) v = make_double2(-v.x, -v.y);  // g5 = diag(1,1,-1,-1) in spin
+                o[(size_t)k * g.Vh] = v;
+            }
+        }
+    } else {
+        if (2 * q + h < ns) {
+            const double2* in = src + eo0 + (size_t)par * 12 * g.Vh + cb;
+#pragma unroll
+            for (int k = 0; k < 12; ++k) {
+                double2 v = in[(size_t)k * g.Vh];
+                if (g5 && k >= 6) v = make_double2(-v.x, -v.y);
+                buf[(2 * q + h) * 12 + k] = v;
+            }
+        }
+        __syncthreads();
+        double2* o = dst + ((size_t)r * V + s0) * 12;
+        for (int e = threadIdx.x; e < ns * 12; e += LAYOUT_BS) o[e] = buf[e];
     }
 }
 
@@ -395,8 +415,8 @@ hipError_t launch_canon_to_eo(const double2* can, double2* eo, const Geo& g, int
     long V = 2L * g.Vh;
     for (int r0 = 0; r0 < nrhs; r0 += 65535) {
         int n = nrhs - r0 < 65535 ? nrhs - r0 : 65535;
-        hipLaunchKernelGGL(k_canon_to_eo, dim3((unsigned)((V + 255) / 256), n), dim3(256), 0, s,
-                           can + (size_t)r0 * V * 12, eo + (size_t)r0 * V * 12, g, n, g5);
+        hipLaunchKernelGGL(k_layout<true>, dim3((unsigned)((V + LAYOUT_BS - 1) / LAYOUT_BS), n), dim3(LAYOUT_BS), 0, s,
+                           can + (size_t)r0 * V * 12, eo + (size_t)r0 * V * 12, g, g5);
     }
     return hipGetLastError();
 }
@@ -406,8 +426,8 @@ hipError_t launch_eo_to_canon(const double2* eo, double2* can, const Geo& g, int
     long V = 2L * g.Vh;
     for (int r0 = 0; r0 < nrhs; r0 += 65535) {
         int n = nrhs - r0 < 65535 ? nrhs - r0 : 65535;
-        hipLaunchKernelGGL(k_eo_to_canon, dim3((unsigned)((V + 255) / 256), n), dim3(256), 0, s,
-                           eo + (size_t)r0 * V * 12, can + (size_t)r0 * V * 12, g, n, g5);
+        hipLaunchKernelGGL(k_layout<false>, dim3((unsigned)((V + LAYOUT_BS - 1) / LAYOUT_BS), n), dim3(LAYOUT_BS), 0, s,
+                           eo + (size_t)r0 * V * 12, can + (size_t)r0 * V * 12, g, g5);
     }
     return hipGetLastError();
 }
