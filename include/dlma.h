@@ -192,6 +192,9 @@ typedef struct {
                           and continues (0 = no restarts: the basis grows to max_basis) */
     int restart_keep;  /* Ritz vectors kept per restart, nev < keep < restart_basis (0 = nev + half the rest) */
     int max_restarts;  /* cap on restarts (0 = 200) */
+    int block_size;    /* > 0: block variant instead of Lanczos, a Chebyshev-filtered subspace iteration on
+                          block_size vectors per timeslice, nev < block_size <= min(64, 3 L^3) */
+    int block_iters;   /* cap on block iterations (0 = 200) */
 } dlma_eig_opts;
 
 /*

@@ -154,6 +154,112 @@ bool sym_eig(std::vector<double> A, int n, std::vector<double>& d, std::vector<d
     return tridiag_ql(d, e, &Z, nullptr, true);
 }
 
+// Eigenpairs of a complex Hermitian n x n matrix A (row-major): Householder
+// reflections I - 2 v v^H reduce A to Hermitian tridiagonal form (column k below the
+// diagonal mapped onto a multiple of e_{k+1}); a diagonal of unit phases makes the
+// off-diagonals real and non-negative; tridiag_ql diagonalises the real tridiagonal
+// matrix; the eigenvectors are Q D Y.  d: eigenvalues (unsorted), Z: eigenvectors
+// as columns (row-major).
+bool herm_eig(std::vector<cplx> A, int n, std::vector<double>& d, std::vector<cplx>& Z) {
+    std::vector<cplx> Q((size_t)n * n, 0.0), v(n), p(n), q(n);
+    for (int i = 0; i < n; ++i) Q[(size_t)i * n + i] = 1.0;
+    auto a = [&](int r, int c) -> cplx& { return A[(size_t)r * n + c]; };
+    for (int k = 0; k + 2 < n; ++k) {
+        double xn2 = 0;
+        for (int i = k + 1; i < n; ++i) xn2 += std::norm(a(i, k));
+        const double xn = std::sqrt(xn2);
+        if (xn == 0.0) continue;
+        const cplx x0 = a(k + 1, k);
+        const cplx ph = std::abs(x0) > 0 ? x0 / std::abs(x0) : cplx(1.0, 0.0);
+        const cplx alpha = -ph * xn;
+        double vn2 = 0;
+        for (int i = k + 1; i < n; ++i) v[i] = a(i, k);
+        v[k + 1] -= alpha;
+        for (int i = k + 1; i < n; ++i) vn2 += std::norm(v[i]);
+        if (vn2 == 0.0) continue;
+        const double vn = std::sqrt(vn2);
+        for (int i = k + 1; i < n; ++i) v[i] /= vn;
+        // trailing block: A' = A - 2 v q^H - 2 q v^H with p = A v, q = p - (v^H p) v
+        cplx vp = 0;
+        for (int r = k + 1; r < n; ++r) {
+            cplx acc = 0;
+            for (int c = k + 1; c < n; ++c) acc += a(r, c) * v[c];
+            p[r] = acc;
+            vp += std::conj(v[r]) * acc;
+        }
+        for (int r = k + 1; r < n; ++r) q[r] = p[r] - vp * v[r];
+        for (int r = k + 1; r < n; ++r)
+            for (int c = k + 1; c < n; ++c) a(r, c) -= 2.0 * (v[r] * std::conj(q[c]) + q[r] * std::conj(v[c]));
+        a(k + 1, k) = alpha;
+        a(k, k + 1) = std::conj(alpha);
+        for (int i = k + 2; i < n; ++i) a(i, k) = a(k, i) = 0.0;
+        // Q = Q H
+        for (int r = 0; r < n; ++r) {
+            cplx acc = 0;
+            for (int c = k + 1; c < n; ++c) acc += Q[(size_t)r * n + c] * v[c];
+            for (int c = k + 1; c < n; ++c) Q[(size_t)r * n + c] -= 2.0 * acc * std::conj(v[c]);
+        }
+    }
+    d.resize(n);
+    std::vector<double> e(n > 1 ? n - 1 : 0);
+    std::vector<cplx> delta(n, 1.0);
+    for (int i = 0; i < n; ++i) d[i] = a(i, i).real();
+    for (int i = 0; i + 1 < n; ++i) {
+        const cplx ei = a(i + 1, i);
+        const double ae = std::abs(ei);
+        e[i] = ae;
+        delta[i + 1] = ae > 0 ? delta[i] * ei / ae : delta[i];
+    }
+    std::vector<double> Y;
+    if (!tridiag_ql(d, e, &Y, nullptr)) return false;
+    Z.assign((size_t)n * n, 0.0);
+    for (int r = 0; r < n; ++r)
+        for (int i = 0; i < n; ++i) {
+            const cplx qd = Q[(size_t)r * n + i] * delta[i];
+            if (qd == cplx(0.0, 0.0)) continue;
+            for (int j = 0; j < n; ++j) Z[(size_t)r * n + j] += qd * Y[(size_t)i * n + j];
+        }
+    return true;
+}
+
+// Z = D R^-1 for the Cholesky factor R (upper, G' = R^H R) of G' = D G D, D =
+// diag(G_ii^-1/2): X Z has orthonormal columns when G = X^H X.  False if G' is not
+// numerically positive definite.
+bool chol_orth_factor(const std::vector<cplx>& G, int n, std::vector<cplx>& Z) {
+    std::vector<double> dg(n);
+    for (int i = 0; i < n; ++i) {
+        const double gii = G[(size_t)i * n + i].real();
+        if (!(gii > 0)) return false;
+        dg[i] = 1.0 / std::sqrt(gii);
+    }
+    std::vector<cplx> R((size_t)n * n, 0.0);
+    for (int j = 0; j < n; ++j) {
+        double s = G[(size_t)j * n + j].real() * dg[j] * dg[j];
+        for (int k = 0; k < j; ++k) s -= std::norm(R[(size_t)k * n + j]);
+        if (!(s > 0)) return false;
+        const double rjj = std::sqrt(s);
+        R[(size_t)j * n + j] = rjj;
+        for (int i = j + 1; i < n; ++i) {
+            cplx t = G[(size_t)j * n + i] * dg[j] * dg[i];
+            for (int k = 0; k < j; ++k) t -= std::conj(R[(size_t)k * n + j]) * R[(size_t)k * n + i];
+            R[(size_t)j * n + i] = t / rjj;
+        }
+    }
+    // R^-1 by back substitution, column by column; then the row scaling by D
+    Z.assign((size_t)n * n, 0.0);
+    for (int c = 0; c < n; ++c) {
+        Z[(size_t)c * n + c] = 1.0 / R[(size_t)c * n + c];
+        for (int i = c - 1; i >= 0; --i) {
+            cplx acc = 0;
+            for (int k = i + 1; k <= c; ++k) acc += R[(size_t)i * n + k] * Z[(size_t)k * n + c];
+            Z[(size_t)i * n + c] = -acc / R[(size_t)i * n + i];
+        }
+    }
+    for (int i = 0; i < n; ++i)
+        for (int c = 0; c < n; ++c) Z[(size_t)i * n + c] *= dg[i];
+    return true;
+}
+
 std::vector<int> argsort(const std::vector<double>& v) {
     std::vector<int> idx(v.size());
     std::iota(idx.begin(), idx.end(), 0);
@@ -180,6 +286,160 @@ template <class F> bool parallel_for(int n, F f) {
 
 }  // namespace
 
+// Block variant: Chebyshev-filtered subspace iteration on a block of kb > nev vectors
+// per timeslice.  Each iteration filters the block with T_deg((c - (-lap))/e), which
+// damps [cut, 12] (cut = the block's largest Ritz value), orthonormalises it (Cholesky
+// QR, twice, after scaling the columns to unit length), and takes the Rayleigh-Ritz
+// vectors of the block.  The degree is the largest (at most 60) with
+// T_deg at the lowest Ritz value below 1e8, so the filtered columns keep a dynamic
+// range the Cholesky QR resolves.  Stops when the nev lowest Ritz pairs have
+// |lap v - lambda v| <= tol * 12.  All timeslices advance together; the block
+// operations (filter, Gram matrices, basis updates) are batched over the block.
+static int block_eigs(Gauge* g, int nev, int t0, int nt, const double2* v0, double2* Vo, double* evals, double tol,
+                      const dlma_eig_opts* opts, hipStream_t s) {
+    const long L3 = (long)g->dims[1] * g->dims[2] * g->dims[3];
+    const long n = 3 * L3;
+    const int kb = opts->block_size;
+    if (kb <= nev || kb > 64 || kb > n) return fail(DLMA_EINVAL, "block_size must satisfy nev < block_size <= min(64, 3 L^3)");
+    const int maxit = opts->block_iters > 0 ? opts->block_iters : 200;
+    const size_t bsz = (size_t)nt * kb * n;
+    Buf pool[4], Part, Gd, Zd, LR;
+    for (auto& b : pool) DLMA_TRY(b.allocate(sizeof(double2) * bsz));
+    const int nc = block_gram_chunks(n, nt);
+    DLMA_TRY(Part.allocate(sizeof(double2) * (size_t)nt * nc * kb * kb));
+    DLMA_TRY(Gd.allocate(sizeof(double2) * (size_t)nt * kb * kb));
+    DLMA_TRY(Zd.allocate(sizeof(double2) * (size_t)nt * kb * kb));
+    DLMA_TRY(LR.allocate(sizeof(double) * 2 * (size_t)nt * kb));
+    double2* buf[4] = {pool[0].as<double2>(), pool[1].as<double2>(), pool[2].as<double2>(), pool[3].as<double2>()};
+    int iX = 0, iW = 1;  // current block and -lap of it; the other two are free
+    auto free_pair = [&](int& a, int& b) {
+        int f[2], k = 0;
+        for (int i = 0; i < 4 && k < 2; ++i)
+            if (i != iX && i != iW) f[k++] = i;
+        a = f[0];
+        b = f[1];
+    };
+    const double2* U64 = g->U64.as<double2>();
+    Profiler& prof = Profiler::get();
+    const double vec_b = 16.0 * n * nt * kb, link_b = 3.0 * 2.0 * 9.0 * 16.0 * L3 * nt;
+    std::vector<cplx> hG((size_t)nt * kb * kb), hZ((size_t)nt * kb * kb);
+    std::vector<double> lam((size_t)nt * kb), res((size_t)nt * kb);
+    auto gram = [&](const double2* A, const double2* B) -> int {
+        DLMA_HIP(launch_block_gram(A, B, n, kb, nt, Part.as<double2>(), Gd.as<double2>(), s));
+        DLMA_HIP(hipMemcpyAsync(hG.data(), Gd.p, sizeof(double2) * hG.size(), hipMemcpyDeviceToHost, s));
+        DLMA_HIP(hipStreamSynchronize(s));
+        return DLMA_OK;
+    };
+    auto orth = [&]() -> int {  // Cholesky QR twice on the current block
+        hipEvent_t ev = nullptr;
+        if (prof.on) prof.begin(0, 0.0, s, ev);
+        for (int pass = 0; pass < 2; ++pass) {
+            DLMA_TRY(gram(buf[iX], buf[iX]));
+            for (int t = 0; t < nt; ++t) {
+                std::vector<cplx> Gt(hG.begin() + (size_t)t * kb * kb, hG.begin() + (size_t)(t + 1) * kb * kb), Zt;
+                if (!chol_orth_factor(Gt, kb, Zt)) return fail(DLMA_ENOTCONV, "block eigensolver: the filtered block lost rank");
+                std::copy(Zt.begin(), Zt.end(), hZ.begin() + (size_t)t * kb * kb);
+            }
+            int f0, f1;
+            free_pair(f0, f1);
+            DLMA_HIP(hipMemcpyAsync(Zd.p, hZ.data(), sizeof(double2) * hZ.size(), hipMemcpyHostToDevice, s));
+            DLMA_HIP(launch_block_update(buf[iX], Zd.as<double2>(), n, kb, kb, nt, buf[f0], (long)kb * n, s));
+            iX = f0;
+        }
+        DLMA_HIP(hipStreamSynchronize(s));  // hZ is rewritten next
+        if (prof.on) prof.end(ev, KC_LAP_ORTHO, 2.0 * (2.0 * vec_b + 2.0 * vec_b), s);
+        return DLMA_OK;
+    };
+    auto rayleigh_ritz = [&]() -> int {  // Ritz vectors of the (orthonormal) block, ascending
+        hipEvent_t ev = nullptr;
+        if (prof.on) prof.begin(0, 0.0, s, ev);
+        DLMA_HIP(launch_neg_lap(U64, g->geo, t0, buf[iX], buf[iW], (long)kb * n, (long)kb * n, nt, s, kb, n, n));
+        DLMA_TRY(gram(buf[iX], buf[iW]));
+        for (int t = 0; t < nt; ++t) {
+            std::vector<cplx> Ht(hG.begin() + (size_t)t * kb * kb, hG.begin() + (size_t)(t + 1) * kb * kb), Zc;
+            for (int i = 0; i < kb; ++i)  // symmetrise the rounding
+                for (int j = 0; j < i; ++j) {
+                    const cplx a = 0.5 * (Ht[(size_t)i * kb + j] + std::conj(Ht[(size_t)j * kb + i]));
+                    Ht[(size_t)i * kb + j] = a;
+                    Ht[(size_t)j * kb + i] = std::conj(a);
+                }
+            for (int i = 0; i < kb; ++i) Ht[(size_t)i * kb + i] = Ht[(size_t)i * kb + i].real();
+            std::vector<double> d;
+            if (!herm_eig(Ht, kb, d, Zc)) return fail(DLMA_EHIP, "block eigensolver: projected eigenproblem did not converge");
+            std::vector<int> idx = argsort(d);
+            for (int j = 0; j < kb; ++j)
+                for (int i = 0; i < kb; ++i) hZ[(size_t)t * kb * kb + (size_t)i * kb + j] = Zc[(size_t)i * kb + idx[j]];
+        }
+        int f0, f1;
+        free_pair(f0, f1);
+        DLMA_HIP(hipMemcpyAsync(Zd.p, hZ.data(), sizeof(double2) * hZ.size(), hipMemcpyHostToDevice, s));
+        DLMA_HIP(launch_block_update(buf[iX], Zd.as<double2>(), n, kb, kb, nt, buf[f0], (long)kb * n, s));
+        DLMA_HIP(launch_block_update(buf[iW], Zd.as<double2>(), n, kb, kb, nt, buf[f1], (long)kb * n, s));
+        iX = f0;
+        iW = f1;
+        double* dl = LR.as<double>();
+        DLMA_HIP(launch_rayleigh(buf[iX], buf[iW], n, nt * kb, dl, dl + (size_t)nt * kb, s));
+        DLMA_HIP(hipMemcpyAsync(lam.data(), dl, sizeof(double) * lam.size(), hipMemcpyDeviceToHost, s));
+        DLMA_HIP(hipMemcpyAsync(res.data(), dl + (size_t)nt * kb, sizeof(double) * res.size(), hipMemcpyDeviceToHost, s));
+        DLMA_HIP(hipStreamSynchronize(s));
+        if (prof.on) prof.end(ev, KC_LAP_RITZ, link_b + 8.0 * vec_b, s);
+        return DLMA_OK;
+    };
+    // start: seeded random block whose first column is the caller's start vector
+    DLMA_HIP(launch_block_random(buf[iX], (long)bsz, 0x5eedu + (unsigned)t0, s));
+    DLMA_HIP(hipMemcpy2DAsync(buf[iX], sizeof(double2) * kb * n, v0, sizeof(double2) * n, sizeof(double2) * n, nt,
+                              hipMemcpyDeviceToDevice, s));
+    DLMA_TRY(orth());
+    DLMA_TRY(rayleigh_ritz());
+    bool conv = false;
+    for (int it = 0;; ++it) {
+        conv = true;
+        for (int t = 0; t < nt && conv; ++t)
+            for (int k = 0; k < nev; ++k)
+                if (!(res[(size_t)t * kb + k] <= tol * 12.0)) { conv = false; break; }
+        if (conv || it >= maxit) break;
+        double cut = 0, lo = 12.0;
+        for (int t = 0; t < nt; ++t) {
+            cut = std::max(cut, lam[(size_t)t * kb + kb - 1]);
+            lo = std::min(lo, lam[(size_t)t * kb]);
+        }
+        cut = std::min(cut, 11.5);
+        const double cc = 0.5 * (cut + 12.0), ee = 0.5 * (12.0 - cut);
+        const double x1 = std::max((cc - lo) / ee, 1.0 + 1e-12);
+        int deg = 4;
+        while (deg < 60 && std::cosh((deg + 1) * std::acosh(x1)) < 1e8) ++deg;
+        hipEvent_t ev = nullptr;
+        if (prof.on) prof.begin(0, 0.0, s, ev);
+        int f0, f1;
+        free_pair(f0, f1);
+        int ia = iX, ib = f0, ic = f1;  // the recurrence rotates through X, the free pair and W
+        DLMA_HIP(launch_cheb_block(U64, g->geo, t0, buf[ia], nullptr, buf[ib], nt, kb, cc, 1.0 / ee, s));
+        for (int k = 2; k <= deg; ++k) {
+            DLMA_HIP(launch_cheb_block(U64, g->geo, t0, buf[ib], buf[ia], buf[ic], nt, kb, cc, 2.0 / ee, s));
+            const int t = ia;
+            ia = ib;
+            ib = ic;
+            ic = (k == 2) ? iW : t;  // W is free until the next Rayleigh-Ritz step
+        }
+        if (prof.on) prof.end(ev, KC_LAP_MATVEC, deg * (link_b + 3.0 * vec_b), s);
+        // the filtered block is in ib; W takes any buffer other than it
+        iX = ib;
+        iW = (ia != iX) ? ia : ic;
+        DLMA_TRY(orth());
+        DLMA_TRY(rayleigh_ritz());
+    }
+    // the nev lowest Ritz pairs, ascending in -lap (descending in lap)
+    DLMA_HIP(hipMemcpy2DAsync(Vo, sizeof(double2) * nev * n, buf[iX], sizeof(double2) * kb * n, sizeof(double2) * nev * n, nt,
+                              hipMemcpyDeviceToDevice, s));
+    for (int t = 0; t < nt; ++t)
+        for (int k = 0; k < nev; ++k) evals[(size_t)t * nev + k] = -lam[(size_t)t * kb + k];
+    DLMA_HIP(launch_phase_fix(Vo, n, nev * nt, s));
+    DLMA_HIP(hipStreamSynchronize(s));
+    if (prof.on) prof.collect();
+    if (!conv) return fail(DLMA_ENOTCONV, "block eigensolver did not reach the tolerance within block_iters iterations");
+    return DLMA_OK;
+}
+
 extern "C" int dlma_lap_eigs(dlma_gauge_t h, int nev, int t0, int nt, const void* v0, void* V_out, double* evals,
                              const dlma_eig_opts* opts, void* stream) {
     Gauge* g = (Gauge*)h;
@@ -191,6 +451,7 @@ extern "C" int dlma_lap_eigs(dlma_gauge_t h, int nev, int t0, int nt, const void
     if (nt < 1 || t0 < 0 || t0 + nt > T) return fail(DLMA_EINVAL, "timeslices t0..t0+nt-1 must lie in [0, T)");
     if (nev < 1 || nev > n) return fail(DLMA_EINVAL, "nev must be in [1, 3 L^3]");
     const double tol = (opts && opts->tol > 0) ? opts->tol : 1e-10;
+    if (opts && opts->block_size > 0) return block_eigs(g, nev, t0, nt, (const double2*)v0, (double2*)V_out, evals, tol, opts, S(stream));
     // thick restart: the basis holds at most restart_basis vectors; at that size the
     // run keeps `keep` Ritz vectors of the wanted end and the last Lanczos vector
     const bool restart = opts && opts->restart_basis > 0;

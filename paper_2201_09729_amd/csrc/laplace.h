@@ -40,6 +40,15 @@ hipError_t launch_normalize_into(const double2* w, long tsw, double2* q, long ts
                                  hipStream_t s);
 hipError_t launch_ritz(const double2* q, long tsq, long isq, const double* S, int m, int nev, double2* y, long tsy, long n, int nt,
                        hipStream_t s);
+// block eigensolver (vectors [t][k][n]; kb <= 64)
+hipError_t launch_cheb_block(const double2* U64, const Geo& g, int t0, const double2* in, const double2* prev, double2* out,
+                             int nt, int kb, double c1, double c2, hipStream_t s);
+int block_gram_chunks(long n, int nt);
+hipError_t launch_block_gram(const double2* A, const double2* B, long n, int kb, int nt, double2* part, double2* G,
+                             hipStream_t s);
+hipError_t launch_block_update(const double2* X, const double2* Z, long n, int kb, int kout, int nt, double2* Y, long ytstride,
+                               hipStream_t s);
+hipError_t launch_block_random(double2* V, long count, unsigned seed, hipStream_t s);
 hipError_t launch_phase_fix(double2* y, long n, int nvec, hipStream_t s);
 hipError_t launch_project(const double2* Vt, const double2* in, double2* out, const Geo& g, int t, int nev, int nrhs, int mode,
                           double2* coef, hipStream_t s);

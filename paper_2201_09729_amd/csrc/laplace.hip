@@ -497,6 +497,168 @@ hipError_t launch_phase_fix(double2* y, long n, int nvec, hipStream_t s) {
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- block eigensolver
+//
+// Chebyshev-filtered subspace iteration keeps a block of kb vectors per timeslice,
+// stored [t][k][n] (vector k of timeslice t at base + (t*kb + k)*n).
+
+// One Chebyshev step on every vector of the block: out = c2 (c1 in - (-lap) in) - prev
+hipError_t launch_cheb_block(const double2* U64, const Geo& g, int t0, const double2* in, const double2* prev, double2* out,
+                             int nt, int kb, double c1, double c2, hipStream_t s) {
+    if (nt <= 0 || kb <= 0) return hipSuccess;
+    const long n = 3L * g.Z * g.Y * g.X;
+    LapMode md = {1, c1, c2, prev, (long)kb * n, nullptr, 0L, nullptr};
+    hipLaunchKernelGGL(k_neg_lap, dim3((unsigned)lap_site_blocks(g), kb, nt), dim3(256), 0, s, U64, g, t0, in, out,
+                       (long)kb * n, (long)kb * n, n, n, md);
+    return hipGetLastError();
+}
+
+// Gram partials: part[t][c][i][j] = sum over rows of chunk c of conj(A_i[e]) B_j[e], i, j < kb.
+// Rows are staged through LDS in tiles; each thread owns the (i, j) pairs
+// i = ty + 16a, j = tx + 16b (a, b < 4), so kb <= 64.
+constexpr int GRAM_ROWS = 16;
+__global__ void __launch_bounds__(256) k_block_gram(const double2* __restrict__ A, const double2* __restrict__ B, long n, int kb,
+                                                    long chunk, double2* __restrict__ part) {
+    __shared__ double2 ta[GRAM_ROWS][64], tb[GRAM_ROWS][64];
+    const int c = blockIdx.x, t = blockIdx.y, nc = gridDim.x;
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    const double2* At = A + (size_t)t * kb * n;
+    const double2* Bt = B + (size_t)t * kb * n;
+    const long e0 = (long)c * chunk, e1 = e0 + chunk < n ? e0 + chunk : n;
+    double2 acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = make_double2(0, 0);
+    for (long r0 = e0; r0 < e1; r0 += GRAM_ROWS) {
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < GRAM_ROWS * 64; idx += 256) {
+            const int rr = idx / 64, k = idx % 64;
+            const long e = r0 + rr;
+            const bool ok = e < e1 && k < kb;
+            ta[rr][k] = ok ? At[(size_t)k * n + e] : make_double2(0, 0);
+            tb[rr][k] = ok ? Bt[(size_t)k * n + e] : make_double2(0, 0);
+        }
+        __syncthreads();
+        for (int rr = 0; rr < GRAM_ROWS; ++rr) {
+            double2 av[4], bv[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) av[a] = ta[rr][ty + 16 * a];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) bv[b] = tb[rr][tx + 16 * b];
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const double2 p = cconjmul(av[a], bv[b]);
+                    acc[a][b].x += p.x;
+                    acc[a][b].y += p.y;
+                }
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int i = ty + 16 * a, j = tx + 16 * b;
+            if (i < kb && j < kb) part[(((size_t)t * nc + c) * kb + i) * kb + j] = acc[a][b];
+        }
+}
+
+// G[t][i][j] = sum of the chunk partials in chunk order
+__global__ void k_block_gram_sum(const double2* __restrict__ part, int nc, int kb, int nt, double2* __restrict__ G) {
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (long)nt * kb * kb) return;
+    const int t = (int)(idx / ((long)kb * kb));
+    const int ij = (int)(idx - (long)t * kb * kb);
+    double2 s = make_double2(0, 0);
+    for (int c = 0; c < nc; ++c) {
+        const double2 p = part[((size_t)t * nc + c) * kb * kb + ij];
+        s.x += p.x;
+        s.y += p.y;
+    }
+    G[idx] = s;
+}
+
+int block_gram_chunks(long n, int nt) {
+    long want = (512 + nt - 1) / nt;  // enough blocks to fill the chip
+    long maxc = (n + GRAM_ROWS - 1) / GRAM_ROWS;
+    return (int)std::max(1L, std::min(want, maxc));
+}
+
+hipError_t launch_block_gram(const double2* A, const double2* B, long n, int kb, int nt, double2* part, double2* G,
+                             hipStream_t s) {
+    if (kb > 64) return hipErrorInvalidValue;
+    const int nc = block_gram_chunks(n, nt);
+    long chunk = (n + nc - 1) / nc;
+    chunk = (chunk + GRAM_ROWS - 1) / GRAM_ROWS * GRAM_ROWS;
+    hipLaunchKernelGGL(k_block_gram, dim3(nc, nt), dim3(256), 0, s, A, B, n, kb, chunk, part);
+    const long tot = (long)nt * kb * kb;
+    hipLaunchKernelGGL(k_block_gram_sum, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, part, nc, kb, nt, G);
+    return hipGetLastError();
+}
+
+// Y_j = sum_i X_i Z[t][i][j] for j < kout (Z complex, row-major kb x kout per timeslice);
+// grid (row blocks, nt, output groups of 8)
+__global__ void __launch_bounds__(256) k_block_update(const double2* __restrict__ X, const double2* __restrict__ Z, long n, int kb,
+                                                      int kout, double2* __restrict__ Y, long ytstride) {
+    __shared__ double2 zs[64 * 8];
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int t = blockIdx.y, j0 = blockIdx.z * 8;
+    const double2* Zt = Z + (size_t)t * kb * kout;
+    for (int idx = threadIdx.x; idx < kb * 8; idx += 256) {
+        const int i = idx / 8, jj = idx % 8;
+        zs[idx] = j0 + jj < kout ? Zt[(size_t)i * kout + j0 + jj] : make_double2(0, 0);
+    }
+    __syncthreads();
+    if (e >= n) return;
+    double2 acc[8];
+#pragma unroll
+    for (int jj = 0; jj < 8; ++jj) acc[jj] = make_double2(0, 0);
+    const double2* Xt = X + (size_t)t * kb * n + e;
+    for (int i = 0; i < kb; ++i) {
+        const double2 x = Xt[(size_t)i * n];
+#pragma unroll
+        for (int jj = 0; jj < 8; ++jj) {
+            const double2 p = cmul2(x, zs[i * 8 + jj]);
+            acc[jj].x += p.x;
+            acc[jj].y += p.y;
+        }
+    }
+    double2* Yt = Y + (size_t)t * ytstride + e;
+#pragma unroll
+    for (int jj = 0; jj < 8; ++jj)
+        if (j0 + jj < kout) Yt[(size_t)(j0 + jj) * n] = acc[jj];
+}
+
+hipError_t launch_block_update(const double2* X, const double2* Z, long n, int kb, int kout, int nt, double2* Y, long ytstride,
+                               hipStream_t s) {
+    if (kb > 64) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_block_update, dim3((unsigned)((n + 255) / 256), nt, (kout + 7) / 8), dim3(256), 0, s, X, Z, n, kb, kout,
+                       Y, ytstride);
+    return hipGetLastError();
+}
+
+// Seeded complex uniform entries in (-1/2, 1/2): splitmix64 of the element index
+__global__ void k_block_random(double2* __restrict__ V, long count, unsigned seed) {
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    double v[2];
+    for (int k = 0; k < 2; ++k) {
+        uint64_t z = (uint64_t)seed * 0x9E3779B97F4A7C15ull + (uint64_t)(2 * i + k) + 1;
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        z ^= z >> 31;
+        v[k] = (double)(z >> 11) * (1.0 / 9007199254740992.0) - 0.5;
+    }
+    V[i] = make_double2(v[0], v[1]);
+}
+
+hipError_t launch_block_random(double2* V, long count, unsigned seed, hipStream_t s) {
+    hipLaunchKernelGGL(k_block_random, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, V, count, seed);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- projector
 
 // c[r][k][s] = sum_{m,col} conj(V[k][m][col]) in_r(t, m, s, col); one block per (k, r)

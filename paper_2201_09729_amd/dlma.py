@@ -55,7 +55,7 @@ class RhsSet(ctypes.Structure):
 class EigOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_basis", ctypes.c_int), ("check_every", ctypes.c_int),
                 ("cheb_degree", ctypes.c_int), ("restart_basis", ctypes.c_int), ("restart_keep", ctypes.c_int),
-                ("max_restarts", ctypes.c_int)]
+                ("max_restarts", ctypes.c_int), ("block_size", ctypes.c_int), ("block_iters", ctypes.c_int)]
 
 
 _lib = None
@@ -225,7 +225,7 @@ def dlma_solve(gauges, bs, xs=None, opts: SolveOpts | None = None, allow_notconv
 
 def dlma_lap_eigs(g: Gauge, nev: int, t0: int, nt: int, v0: torch.Tensor, tol: float = 1e-10,
                   max_basis: int = 0, check_every: int = 0, cheb_degree: int = 0, restart_basis: int = 0,
-                  restart_keep: int = 0, max_restarts: int = 0):
+                  restart_keep: int = 0, max_restarts: int = 0, block_size: int = 0, block_iters: int = 0):
     """Lowest nev modes of -lap(t), t = t0..t0+nt-1; v0: [nt][Z][Y][X][3] start vectors.
 
     Returns (V [nt][nev][Z][Y][X][3] complex128 on the GPU, evals numpy [nt][nev])."""
@@ -234,7 +234,8 @@ def dlma_lap_eigs(g: Gauge, nev: int, t0: int, nt: int, v0: torch.Tensor, tol: f
     T, Z, Y, X = g.dims
     V = torch.empty((nt, nev, Z, Y, X, 3), dtype=torch.complex128, device=v0.device)
     ev = np.zeros((nt, nev), dtype=np.float64)
-    o = EigOpts(tol, max_basis, check_every, cheb_degree, restart_basis, restart_keep, max_restarts)
+    o = EigOpts(tol, max_basis, check_every, cheb_degree, restart_basis, restart_keep, max_restarts, block_size,
+                block_iters)
     _check(load_library().dlma_lap_eigs(g.h, int(nev), int(t0), int(nt), ctypes.c_void_p(v0.data_ptr()),
                                         ctypes.c_void_p(V.data_ptr()), ev.ctypes.data_as(ctypes.c_void_p),
                                         ctypes.byref(o), _stream()))

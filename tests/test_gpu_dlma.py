@@ -23,22 +23,26 @@ def cu(a):
     return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
 
 
-@pytest.mark.parametrize("dims,nev,seed,ts,cheb,rb", [((4, 4, 4, 4), 4, 1, (0, 4), 0, 0),
-                                                      ((16, 8, 8, 8), 16, 2, (3, 3), -1, 0),
-                                                      ((16, 8, 8, 8), 16, 2, (3, 3), 12, 0),
-                                                      ((16, 8, 8, 8), 16, 2, (3, 3), -1, 40),
-                                                      ((16, 8, 8, 8), 16, 2, (3, 3), 12, 34),
-                                                      ((8, 6, 6, 6), 24, 3, (0, 8), 0, 60)])
-def test_lap_eigs_matches_oracle(D, orc, dims, nev, seed, ts, cheb, rb):
+@pytest.mark.parametrize("dims,nev,seed,ts,cheb,rb,blk", [((4, 4, 4, 4), 4, 1, (0, 4), 0, 0, 0),
+                                                          ((16, 8, 8, 8), 16, 2, (3, 3), -1, 0, 0),
+                                                          ((16, 8, 8, 8), 16, 2, (3, 3), 12, 0, 0),
+                                                          ((16, 8, 8, 8), 16, 2, (3, 3), -1, 40, 0),
+                                                          ((16, 8, 8, 8), 16, 2, (3, 3), 12, 34, 0),
+                                                          ((8, 6, 6, 6), 24, 3, (0, 8), 0, 60, 0),
+                                                          ((4, 4, 4, 4), 4, 1, (0, 4), 0, 0, 8),
+                                                          ((16, 8, 8, 8), 16, 2, (3, 3), 0, 0, 24),
+                                                          ((8, 6, 6, 6), 24, 3, (0, 8), 0, 0, 40)])
+def test_lap_eigs_matches_oracle(D, orc, dims, nev, seed, ts, cheb, rb, blk):
     """Plain Lanczos (cheb = -1, and automatic on small timeslices), the
-    Chebyshev-filtered variant (cheb = 12) and thick restart (the basis capped at
-    rb vectors) against the oracle's plain Lanczos."""
+    Chebyshev-filtered variant (cheb = 12), thick restart (the basis capped at rb
+    vectors) and the block variant (Chebyshev-filtered subspace iteration on blk
+    vectors) against the oracle's plain Lanczos."""
     t0, nt = ts
-    print("lap_eigs", dims, nev, cheb, rb, flush=True)
+    print("lap_eigs", dims, nev, cheb, rb, blk, flush=True)
     U = synth.gauge_field(dims, 0.3, seed)
     v0 = synth.gaussian_start(dims, nt, 100 + seed)
     g = D.dlma_load_gauge(cu(U), 0.120, 1.0)
-    Vg, ev = D.dlma_lap_eigs(g, nev, t0, nt, cu(v0), tol=1e-12, cheb_degree=cheb, restart_basis=rb)
+    Vg, ev = D.dlma_lap_eigs(g, nev, t0, nt, cu(v0), tol=1e-12, cheb_degree=cheb, restart_basis=rb, block_size=blk)
     Vg = Vg.cpu().numpy()
     for i in range(nt):
         t = t0 + i
