@@ -104,8 +104,8 @@ def main():
                          "orthogonalisation / Ritz split), instead of the headline benchmark")
     ap.add_argument("--lap-nev", default="20,40,80,160,320", help="modes per timeslice for --lap-scaling")
     ap.add_argument("--lap-nt", type=int, default=16, help="timeslices per eigensolver call for --lap-scaling")
-    ap.add_argument("--lap-variants", default="chebyshev,thick_restart",
-                    help="eigensolver variants for --lap-scaling (chebyshev, thick_restart)")
+    ap.add_argument("--lap-variants", default="chebyshev,thick_restart,block",
+                    help="eigensolver variants for --lap-scaling (chebyshev, thick_restart, block)")
     ap.add_argument("--dist-scan", action="store_true",
                     help="C_dist / C against the number of Laplacian modes N on 16^3x32 with the cost-model "
                          "relation of the paper evaluated on measured GPU times, instead of the headline benchmark")
@@ -350,22 +350,27 @@ def lap_scaling(args):
             # chebyshev: Chebyshev-filtered Lanczos, basis growing to convergence;
             # thick_restart: the same filter with the basis capped at 2N + 32 vectors
             # (restarts keep N + half the rest as Ritz vectors)
+            # block: Chebyshev-filtered subspace iteration on N + max(8, N/2) vectors (at most 64)
             cheb = 0
             maxb = 3 * nev + 300 if variant == "chebyshev" else 0
             rb = 2 * nev + 32 if variant == "thick_restart" else 0
+            bs = min(64, nev + max(8, nev // 2)) if variant == "block" else 0
+            if variant == "block" and bs <= nev:
+                log("block nev %d: skipped (the block kernels hold at most 64 vectors)" % nev)
+                continue
             dlma.dlma_profile_reset()
             dlma.dlma_profile_enable(True)
             torch.cuda.synchronize()
             t = time.time()
             for t0 in range(0, T, nt):
                 V, ev = dlma.dlma_lap_eigs(g, nev, t0, min(nt, T - t0), v0[t0:t0 + nt], tol=1e-10,
-                                           max_basis=maxb, cheb_degree=cheb, restart_basis=rb)
+                                           max_basis=maxb, cheb_degree=cheb, restart_basis=rb, block_size=bs)
                 del V
             torch.cuda.synchronize()
             wall = time.time() - t
             dlma.dlma_profile_enable(False)
             ph = {name: dlma.dlma_profile_read(kc) for name, kc in (("matvec", 5), ("ortho", 6), ("ritz", 7))}
-            row = {"lattice": "64x32^3", "timeslices": T, "nev": nev, "variant": variant, "basis_cap": rb or maxb,
+            row = {"lattice": "64x32^3", "timeslices": T, "nev": nev, "variant": variant, "basis_cap": rb or maxb or bs,
                    "wall_s": round(wall, 3),
                    "matvec_s": round(ph["matvec"][1] / 1e3, 3), "ortho_s": round(ph["ortho"][1] / 1e3, 3),
                    "ritz_s": round(ph["ritz"][1] / 1e3, 3), "lanczos_steps_per_call": ph["ortho"][0] // max(1, -(-T // nt)),
