@@ -144,7 +144,8 @@ def main():
 
     def step(prec, timed_stats=None):
         g = dlma.dlma_load_gauge(U, KAPPA, CSW)                       # gauge ingest, clover, A_oo^-1
-        V, ev = dlma.dlma_lap_eigs(g, NEV, T0, 1, v0[T0:T0 + 1])      # Laplacian modes on t'
+        V, ev = dlma.dlma_lap_eigs(g, NEV, T0, 1, v0[T0:T0 + 1],      # Laplacian modes on t' (block variant:
+                                   block_size=min(64, NEV + 24))       # one timeslice leaves Lanczos latency-bound)
         b[:, T0].zero_()                                              # b is zero off t' (allocated so)
         for s in range(4):                                            # spin-diluted sources
             b[s:nd:4, T0, ..., s, :] = V[0]
