@@ -735,7 +735,7 @@ extern "C" int dlma_lap_eigs(dlma_gauge_t h, int nev, int t0, int nt, const void
             ee = 0.5 * (12.0 - cut);
         }
     }
-    // Second estimate of the cut (not with thick restart, whose cycles keep one filter):
+    // Second estimate of the cut (the final run, thick-restarted or not, keeps it):
     // the unfiltered run's Ritz values lie far above the eigenvalues beyond the wanted
     // ones, so the first cut damps too little of the spectrum.  A short filtered run
     // resolves the top of the filtered spectrum; its (nev + nev/4)-th largest Ritz value
@@ -744,7 +744,7 @@ extern "C" int dlma_lap_eigs(dlma_gauge_t h, int nev, int t0, int nt, const void
     // starts from the sum of the short run's wanted Ritz vectors.
     const double2* start = (const double2*)v0;
     const int mB = (int)std::min<long>(std::min(maxm - 1, nev + std::max(20, nev / 2)), n - 1);
-    if (cur_deg > 0 && !restart && mB > nev + nev / 4) {
+    if (cur_deg > 0 && mB > nev + nev / 4) {
         DLMA_TRY(lanczos(mB, true, false, m, conv, start));
         DLMA_HIP(hipMemcpyAsync(ha.data(), alpha, sizeof(double) * maxm * nt, hipMemcpyDeviceToHost, s));
         DLMA_HIP(hipMemcpyAsync(hb.data(), beta, sizeof(double) * maxm * nt, hipMemcpyDeviceToHost, s));
