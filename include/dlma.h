@@ -203,12 +203,16 @@ typedef struct {
  * timeslice).  Lanczos with full re-orthogonalisation (two passes of classical
  * Gram-Schmidt), all timeslices advanced together.  On large timeslices the
  * Lanczos operator is a Chebyshev polynomial p(-lap) that damps the spectrum
- * above a cut estimated from a short unfiltered run (p has the same eigenvectors;
- * the eigenvalues returned are Rayleigh quotients of lap itself, and the
- * stopping test is the explicit residual |lap v - lambda v|).  With
- * opts->restart_basis the run is thick-restarted: the basis never exceeds that
- * many vectors, and each restart keeps the best Ritz vectors and the last Lanczos
- * vector (the projected matrix becomes arrowhead plus tridiagonal).
+ * above a cut estimated from a short unfiltered run and refined by a short filtered
+ * one (p has the same eigenvectors; the eigenvalues returned are Rayleigh quotients
+ * of lap itself, and the stopping test is the explicit residual
+ * |lap v - lambda v|).  With opts->restart_basis the run is thick-restarted: the
+ * basis never exceeds that many vectors, and each restart keeps the best Ritz
+ * vectors and the last Lanczos vector (the projected matrix becomes arrowhead
+ * plus tridiagonal).  With opts->block_size the block variant runs instead: a
+ * Chebyshev-filtered subspace iteration on block_size vectors per timeslice (v0
+ * is the first vector of each block, the rest seeded random), with Cholesky QR
+ * and Rayleigh-Ritz steps and the same stopping test.
  *   v0       device, [nt][Z][Y][X][3] complex128 start vectors (any nonzero vectors)
  *   V_out    device, [nt][nev][Z][Y][X][3] complex128 orthonormal eigenvectors; the
  *            component of largest modulus of each vector is real and positive
@@ -276,9 +280,12 @@ int dlma_dot(const void* a, const void* b, long n, double* out, void* stream);
  *                   x += alpha w and |r|^2 (CG update, q not stored)
  *   4 = hop_k2      even sites, z = A_ee x - D_eo y               (benchmark only)
  * and the phases of dlma_lap_eigs, per Lanczos step (all timeslices of the call):
- *   5 = lap_matvec  application of -lap (or of its Chebyshev polynomial)
+ *   5 = lap_matvec  application of -lap (or of its Chebyshev polynomial; block variant: the
+ *                   filter of one iteration)
  *   6 = lap_ortho   three-term recurrence, two classical Gram-Schmidt passes, normalisation
- *   7 = lap_ritz    Ritz vectors and Rayleigh-quotient residual checks
+ *                   (block variant: the two Cholesky QR passes)
+ *   7 = lap_ritz    Ritz vectors and Rayleigh-quotient residual checks (block variant: the
+ *                   Rayleigh-Ritz step)
  * and the stencils of the BiCGStab inner solver (K1 of both applications is class 0):
  *   8 = hop_k2_dotr even sites, v = A_ee p - D_eo y, with (rh, v)
  *   9 = hop_k2_dotx even sites, t = A_ee s - D_eo y, with (t, s) and |t|^2

@@ -17,15 +17,11 @@ hipError_t launch_cheb_step(const double2* U64, const Geo& g, int t0, const doub
 hipError_t launch_rayleigh(const double2* y, const double2* ay, long n, int nvec, double* lam, double* res, hipStream_t s);
 hipError_t launch_dots(const double2* a, long tsa, long isa, const double2* b, long tsb, long n, double2* out, int ostride,
                        int ni, int nt, hipStream_t s);
-hipError_t launch_sub_combo(const double2* q, long tsq, long isq, const double2* h, int hstride, int ni, double2* w, long tsw,
-                            long n, int nt, hipStream_t s);
-// prev = false: no beta_{j-1} q_{j-1} term (the first step after a thick restart,
-// whose couplings to the kept Ritz vectors the Gram-Schmidt passes remove)
-hipError_t launch_lanczos_three(const double2* q, long tsq, long isq, double2* w, long tsw, long n, double* alpha, double* beta,
-                                int astride, int j, int nt, hipStream_t s, bool prev = true);
 // Lanczos step with split reductions: alpha from the stencil's partials (nap per
 // timeslice), Gram-Schmidt dots in GS_NCH element chunks, |w|^2 partials from the last
-// subtraction (gs_sub_blocks(n) per timeslice) consumed by the normalisation
+// subtraction (gs_sub_blocks(n) per timeslice) consumed by the normalisation.  prev =
+// false: no beta_{j-1} q_{j-1} term (the first step after a thick restart, whose
+// couplings to the kept Ritz vectors the Gram-Schmidt passes remove).
 constexpr int GS_NCH = 8;
 int gs_sub_blocks(long n);
 hipError_t launch_lanczos_three_p(const double2* q, long tsq, long isq, double2* w, long tsw, long n, const double* apart, int nap,

@@ -179,77 +179,6 @@ hipError_t launch_dots(const double2* a, long tsa, long isa, const double2* b, l
     return hipGetLastError();
 }
 
-// w_t -= sum_{i < ni} q_{t,i} h[t * hstride + i]
-__global__ void k_sub_combo(const double2* __restrict__ q, long tsq, long isq, const double2* __restrict__ h, int hstride,
-                            int ni, double2* __restrict__ w, long tsw, long n, int nt) {
-    long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    int t = blockIdx.y;
-    if (e >= n) return;
-    const double2* hq = h + (long)t * hstride;
-    const double2* pq = q + t * tsq + e;
-    double2 s = make_double2(0, 0);
-    for (int i = 0; i < ni; ++i) {
-        double2 c = cmul2(pq[(long)i * isq], hq[i]);
-        s.x += c.x;
-        s.y += c.y;
-    }
-    double2* pw = w + t * tsw + e;
-    double2 v = *pw;
-    v.x -= s.x;
-    v.y -= s.y;
-    *pw = v;
-}
-
-hipError_t launch_sub_combo(const double2* q, long tsq, long isq, const double2* h, int hstride, int ni, double2* w, long tsw,
-                            long n, int nt, hipStream_t s) {
-    if (ni <= 0 || nt <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_sub_combo, dim3((unsigned)((n + 255) / 256), nt), dim3(256), 0, s, q, tsq, isq, h, hstride, ni, w, tsw,
-                       n, nt);
-    return hipGetLastError();
-}
-
-// Lanczos three-term step: alpha_t = Re <q_j, w>; w -= alpha_t q_j + beta_t q_{j-1} (beta from the previous step)
-__global__ void __launch_bounds__(256) k_lanczos_alpha(const double2* __restrict__ q, long tsq, const double2* __restrict__ w,
-                                                       long tsw, long n, double* __restrict__ alpha, int astride, int j) {
-    __shared__ double lds[4];
-    int t = blockIdx.x;
-    const double2* pq = q + t * tsq;
-    const double2* pw = w + t * tsw;
-    double s = 0;
-    for (long e = threadIdx.x; e < n; e += 256) s += pq[e].x * pw[e].x + pq[e].y * pw[e].y;
-    s = block_sum<256>(s, lds);
-    if (threadIdx.x == 0) alpha[(long)t * astride + j] = s;
-}
-
-__global__ void k_lanczos_three(const double2* __restrict__ qj, const double2* __restrict__ qjm, long tsq,
-                                double2* __restrict__ w, long tsw, long n, const double* __restrict__ alpha,
-                                const double* __restrict__ beta, int astride, int j, int prev) {
-    long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    int t = blockIdx.y;
-    if (e >= n) return;
-    double a = alpha[(long)t * astride + j];
-    double2 v = w[t * tsw + e];
-    double2 c = qj[t * tsq + e];
-    v.x -= a * c.x;
-    v.y -= a * c.y;
-    if (prev) {
-        double b = beta[(long)t * astride + j - 1];
-        double2 d = qjm[t * tsq + e];
-        v.x -= b * d.x;
-        v.y -= b * d.y;
-    }
-    w[t * tsw + e] = v;
-}
-
-hipError_t launch_lanczos_three(const double2* q, long tsq, long isq, double2* w, long tsw, long n, double* alpha, double* beta,
-                                int astride, int j, int nt, hipStream_t s, bool prev) {
-    hipLaunchKernelGGL(k_lanczos_alpha, dim3(nt), dim3(256), 0, s, q + (long)j * isq, tsq, w, tsw, n, alpha, astride, j);
-    const double2* qjm = j > 0 ? q + (long)(j - 1) * isq : q;
-    hipLaunchKernelGGL(k_lanczos_three, dim3((unsigned)((n + 255) / 256), nt), dim3(256), 0, s, q + (long)j * isq, qjm, tsq, w, tsw,
-                       n, alpha, beta, astride, j, (prev && j > 0) ? 1 : 0);
-    return hipGetLastError();
-}
-
 // beta_t = |w_t|; q_{j+1} = w / beta (beta below 1e-300 leaves q_{j+1} = 0)
 __global__ void __launch_bounds__(256) k_norm_t(const double2* __restrict__ w, long tsw, long n, double* __restrict__ out,
                                                 int ostride, int j) {

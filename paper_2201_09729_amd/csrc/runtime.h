@@ -166,9 +166,9 @@ double hop_bytes(int prec, int kind, int flags, int Vh, int nrhs_active);
 
 enum KClass {
     KC_K1 = 0, KC_K1DAG = 1, KC_K2DAGN = 2, KC_K2CG = 3, KC_K2 = 4,  // stencils
-    KC_LAP_MATVEC = 5,  // Lanczos: applications of -lap (or of its Chebyshev polynomial)
-    KC_LAP_ORTHO = 6,   // Lanczos: three-term step, two Gram-Schmidt passes, normalisation
-    KC_LAP_RITZ = 7,    // Lanczos: Ritz vectors and Rayleigh-quotient residual checks
+    KC_LAP_MATVEC = 5,  // Lanczos: applications of -lap (or of its Chebyshev polynomial); block: the filter
+    KC_LAP_ORTHO = 6,   // Lanczos: three-term step, two Gram-Schmidt passes, normalisation; block: Cholesky QR
+    KC_LAP_RITZ = 7,    // Lanczos: Ritz vectors and Rayleigh-quotient residual checks; block: Rayleigh-Ritz
     KC_K2V = 8,         // BiCGStab: v = Dhat p (K2 with (rh, v))
     KC_K2T = 9,         // BiCGStab: t = Dhat s (K2 with (t, s), |t|^2)
     KC_N = 10
