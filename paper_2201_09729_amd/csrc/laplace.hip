@@ -510,7 +510,7 @@ __global__ void k_block_gram_sum(const double2* __restrict__ part, int nc, int k
 }
 
 int block_gram_chunks(long n, int nt) {
-    long want = (512 + nt - 1) / nt;  // enough blocks to fill the chip
+    long want = (256 + nt - 1) / nt;  // enough blocks to fill the chip, few partials to add
     long maxc = (n + GRAM_ROWS - 1) / GRAM_ROWS;
     return (int)std::max(1L, std::min(want, maxc));
 }
