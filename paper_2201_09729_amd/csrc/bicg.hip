@@ -70,10 +70,16 @@ template <int MODE> HD void bivec16(const BiVecJob<P16>& J, int r, uint32_t site
         const F16Field T = f16_field(J.t, J.Vh, r), R = f16_field(J.r, J.Vh, r), RH = f16_field(J.rh, J.Vh, r);
         const float alr = (float)J.alpha[r].x, ali = (float)J.alpha[r].y;
         const float omr = (float)J.omega[r].x, omi = (float)J.omega[r].y;
+        // every load first (the stores to x and r could alias them as far as the
+        // compiler can tell, which would otherwise hold the later loads behind them)
+        uint32_t wt[12], wh[12];
         load_words<CP_NT>(X, s16, G16, wa);
         load_words<CP_NT>(Pp, s16, G16, wb);
         load_words<CP_NT>(S, s16, G16, wc);
+        load_words<CP_NT>(T, s16, G16, wt);
+        load_words<CP_NT>(RH, s16, G16, wh);
         const float nx = wldf<CP_NT>(X.n, lo, 0), np = wldf<CP_NT>(Pp.n, lo, 0), ns = wldf<CP_NT>(S.n, lo, 0);
+        const float nt = wldf<CP_NT>(T.n, lo, 0), nh = wldf<CP_NT>(RH.n, lo, 0);
         bv16_cplx(wa, nx, a);
         bv16_cplx(wb, np, b);
         bv16_cplx(wc, ns, c);
@@ -83,20 +89,17 @@ template <int MODE> HD void bivec16(const BiVecJob<P16>& J, int r, uint32_t site
             a[2 * i] += alr * pr - ali * pi + omr * sr - omi * si;
             a[2 * i + 1] += alr * pi + ali * pr + omr * si + omi * sr;
         }
-        (void)store16(X, G16, site, a);
-        load_words<CP_NT>(T, s16, G16, wb);
-        const float nt = wldf<CP_NT>(T.n, lo, 0);
-        bv16_cplx(wb, nt, b);
+        bv16_cplx(wt, nt, b);
 #pragma unroll
         for (int i = 0; i < 12; ++i) {
             const float tr = b[2 * i], ti = b[2 * i + 1];
             c[2 * i] -= omr * tr - omi * ti;
             c[2 * i + 1] -= omr * ti + omi * tr;
         }
+        (void)store16(X, G16, site, a);
         // |r|^2 and (rh, r) of the new residual before its storage rounding
         q0 = (double)store16(R, G16, site, c);
-        load_words<CP_NT>(RH, s16, G16, wa);
-        const float nh = wldf<CP_NT>(RH.n, lo, 0);
+        for (int i = 0; i < 12; ++i) wa[i] = wh[i];
         float re = 0.f, im = 0.f;
 #pragma unroll
         for (int i = 0; i < 12; ++i) {
