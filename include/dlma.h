@@ -56,7 +56,7 @@ extern "C" {
 
 /* Precision of a solve.  FP64: every vector and operator in double precision.
  * MIX_*: FP64 defect correction (true residual r = b - D x, norms and the
- * update x += e are FP64 on the GPU) around an inner even-odd CG whose
+ * update x += e are FP64 on the GPU) around an inner even-odd Krylov solve whose
  * arithmetic is FP32 and whose links, clover matrices and vectors are stored in
  * FP32, FP16 (vectors with one FP32 scale per site and right-hand side) or BF16. */
 #define DLMA_PREC_FP64 0
@@ -170,10 +170,13 @@ typedef struct {
  * right-hand sides are solved together: each stencil launch covers every
  * configuration (uneven volumes allowed) and every right-hand side.
  * Algorithm: FP64 defect correction; each pass forms the Schur source
- * bhat_e = r_e - D_eo A_oo^-1 r_o, runs CG on the normal equations of
- * Dhat = A_ee - D_eo A_oo^-1 D_oe in the chosen precision, and reconstructs the
- * odd sites.  Stops per right-hand side when the FP64 true relative residual is
- * <= tol.
+ * bhat_e = r_e - D_eo A_oo^-1 r_o, solves Dhat e = bhat_e with
+ * Dhat = A_ee - D_eo A_oo^-1 D_oe in the chosen precision (BiCGStab on Dhat by
+ * default, or CG on its normal equations: opts->inner_solver), and reconstructs
+ * the odd sites.  After the first reconstruction the odd residual vanishes to FP64
+ * rounding, so later passes compute the residual on the even sites; the odd sites
+ * of the final x are checked before the solve reports convergence.  Stops per
+ * right-hand side when the FP64 true relative residual is <= tol.
  *   gs     host array of ngauge handles (1 <= ngauge <= 16)
  *   sets   host array of ngauge rhs sets
  *   stats  host array with one entry per right-hand side (sets in order), or NULL
