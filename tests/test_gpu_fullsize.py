@@ -166,8 +166,17 @@ def test_headline_launch_configuration(D, orc):
     T = dims[0]
     U = synth.gauge_field(dims, 0.25, 6)
     g = D.dlma_load_gauge(cu(U), kappa, csw)
-    V, ev = D.dlma_lap_eigs(g, nev, t0, 1, cu(synth.gaussian_start(dims, 1, 606)))
+    v0 = cu(synth.gaussian_start(dims, 1, 606))
+    VL, evL = D.dlma_lap_eigs(g, nev, t0, 1, v0)
+    check_modes(orc, U, t0, VL[0], evL[0], 1e-10)
+    # the benchmark takes the modes with the block variant: same eigenvalues, and the
+    # same vectors where an eigenvalue is isolated (phase rule), else the same space
+    V, ev = D.dlma_lap_eigs(g, nev, t0, 1, v0, block_size=min(64, nev + 24))
     check_modes(orc, U, t0, V[0], ev[0], 1e-10)
+    assert np.max(np.abs(ev - evL)) < 1e-11
+    O = (VL[0].reshape(nev, -1).conj() @ V[0].reshape(nev, -1).T).cpu().numpy()  # overlaps of the two bases
+    assert np.max(np.abs(O.conj().T @ O - np.eye(nev))) < 1e-8  # unitary: the same space
+    del VL
     eta = D.noise_sources(cu(synth.z2_noise(dims, t0, nn, 1006)), T, t0)
     b = torch.cat([D.dist_sources(V[0], T, t0), eta, D.dlma_project(g, t0, V[0], eta, 1)])
     del eta
