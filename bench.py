@@ -59,14 +59,17 @@ def spinor_bytes(prec):
 def hop_bytes_split(prec, kind, flags, dims):
     """Algorithmic HBM bytes of one stencil launch: (per launch, per active right-hand side).
     Links (all 8 per output site) and the clover block of the output parity are read once;
-    each right-hand side streams its spinor passes once (inputs, outputs, fused vectors)."""
+    each right-hand side streams its spinor passes once (inputs, outputs, fused vectors).
+    BiCGStab's shadow residual, read by K2 with (rh, v), is one field shared by all of them."""
     vh = dims[0] * dims[1] * dims[2] * dims[3] // 2
     pb = pair_bytes(prec)
     fixed = vh * (72 * pb + (0 if (kind == 1 and flags & 32) else 36 * pb))
+    if kind == 1 and flags & 512:
+        fixed += vh * spinor_bytes(prec)
     if kind == 0:
         passes = 2 + (1 if flags & 64 else 0) + (1 if flags & 128 else 0)
     else:
-        passes = 6 if flags & 8 else 3 + (1 if flags & 16 else 0) + (1 if flags & 512 else 0)
+        passes = 6 if flags & 8 else 3 + (1 if flags & 16 else 0)
     return fixed, vh * passes * spinor_bytes(prec)
 
 

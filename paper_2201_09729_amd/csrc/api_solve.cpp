@@ -121,12 +121,12 @@ template <int P> int alloc_cfg(Cfg& c, bool bicg, hipStream_t s) {
     if (bicg) {
         DLMA_TRY(c.bs.allocate(halfP));
         DLMA_TRY(c.bt.allocate(halfP));
-        DLMA_TRY(c.brh.allocate(halfP));
+        DLMA_TRY(c.brh.allocate(halfP / n));  // one shadow residual, shared by every RHS
         if (P == P16) {
             size_t nb = sizeof(float) * n * Vh;
             DLMA_TRY(c.nbs.allocate(nb));
             DLMA_TRY(c.nbt.allocate(nb));
-            DLMA_TRY(c.nbrh.allocate(nb));
+            DLMA_TRY(c.nbrh.allocate(nb / n));
         }
         DLMA_TRY(c.bstate.allocate(sizeof(double2) * 4 * n));
         c.brho = c.bstate.as<double2>();
@@ -283,6 +283,8 @@ template <int P> int build_tables(std::vector<Cfg>& cs, Tables<P>& t, int nb, in
             if (t.bicg) {  // BiCGStab: v = w's storage, x = xs's
                 SF<P> vs = half_view<P>(c.bs.p, nrm_of<P>(c.nbs), Vh), vt = half_view<P>(c.bt.p, nrm_of<P>(c.nbt), Vh);
                 SF<P> vrh = half_view<P>(c.brh.p, nrm_of<P>(c.nbrh), Vh);
+                vrh.rs = 0;  // every RHS reads the one shadow residual
+                vrh.ns = 0;
                 HopJob<P> k1 = j1; k1.part = nullptr;
                 HopJob<P> k2 = j2;  // partials of (rh, v), then of (t, s) and |t|^2 (hop_nq layout)
                 HopJob<P> a1 = k1; a1.in = vp; a1.out = vy; bk1p.push_back(a1);
@@ -503,9 +505,9 @@ int solve_impl(std::vector<Cfg>& cs, const dlma_solve_opts& o, hipStream_t s) {
     const int nb = tin.nb;
     Tables<P> t;
     t.bicg = o.inner_solver == 1;
-    if (t.bicg)  // BiCGStab's shadow residual: a fixed seeded random field per configuration
+    if (t.bicg)  // BiCGStab's shadow residual: one fixed seeded random field per configuration
         for (auto& c : cs)
-            DLMA_HIP(launch_fill_random<P>(half_view<P>(c.brh.p, nrm_of<P>(c.nbrh), c.g->Vh), c.g->Vh, c.nrhs,
+            DLMA_HIP(launch_fill_random<P>(half_view<P>(c.brh.p, nrm_of<P>(c.nbrh), c.g->Vh), c.g->Vh, 1,
                                            0x5eedu + (unsigned)c.gidx, s));
     DLMA_TRY(build_tables<P>(cs, t, nb, tin.sg, tin.win, t64.nb, t64.sg, s));
     int ncfg = (int)cs.size();

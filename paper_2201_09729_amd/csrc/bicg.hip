@@ -10,7 +10,9 @@
 // The shadow residual rh is a fixed seeded random field rather than the initial
 // residual: a distillation source lives on one timeslice and one spin, and with
 // rh = r_0 the scalar (rh, r) loses almost all of the spreading residual, which
-// leaves the FP16 recursion to drift from the true residual.
+// leaves the FP16 recursion to drift from the true residual.  Every right-hand
+// side of a configuration reads the same field (its views have RHS stride 0), so
+// the x/r update and K2 with (rh, v) read it once per site rather than per RHS.
 #include "kernels.h"
 
 namespace dlma {

@@ -140,10 +140,11 @@ double hop_bytes(int prec, int kind, int flags, int Vh, int n) {
     } else {
         vec = 3.0;                           // in, x, out
         if (flags & F_HASB) vec += 1.0;
-        if (flags & F_DOTR) vec += 1.0;      // the shadow residual at the own site
         if (flags & F_CG) vec = 6.0;         // in, x, r (r/w), xs (r/w)
     }
-    return (double)Vh * (links + clov + vec * sp * n);
+    // the shadow residual at the own site: one field shared by every RHS
+    const double shared = (kind == K2 && (flags & F_DOTR)) ? sp : 0.0;
+    return (double)Vh * (links + clov + shared + vec * sp * n);
 }
 
 // ---------------------------------------------------------------- profiler
