@@ -79,9 +79,9 @@ template <int MODE> HD void bivec16(const BiVecJob<P16>& J, int r, uint32_t site
         load_words<CP_NT>(Pp, s16, G16, wb);
         load_words<CP_NT>(S, s16, G16, wc);
         load_words<CP_NT>(T, s16, G16, wt);
-        load_words<CP_NT>(RH, s16, G16, wh);
+        load_words(RH, s16, G16, wh);  // cached: every RHS reads this one field
         const float nx = wldf<CP_NT>(X.n, lo, 0), np = wldf<CP_NT>(Pp.n, lo, 0), ns = wldf<CP_NT>(S.n, lo, 0);
-        const float nt = wldf<CP_NT>(T.n, lo, 0), nh = wldf<CP_NT>(RH.n, lo, 0);
+        const float nt = wldf<CP_NT>(T.n, lo, 0), nh = wldf(RH.n, lo, 0);
         bv16_cplx(wa, nx, a);
         bv16_cplx(wb, np, b);
         bv16_cplx(wc, ns, c);

@@ -629,9 +629,9 @@ HD void hop_site16(const HopJob<P16>& J, int cb, int g0, bool valid, const Windo
                     }
                     if (FL & F_DOTR) {  // sum conj(r) out, r (the shadow residual) read at the own site
                         const F16Field rf = f16_field(J.r, J.g.Vh, g0 + j);
-                        const float nr = wldf<CP_NT>(rf.n, lo, 0);
+                        const float nr = wldf(rf.n, lo, 0);  // cached: one field for every RHS
                         uint32_t rw[12];
-                        load_words<CP_NT>(rf, s16, G16, rw);
+                        load_words(rf, s16, G16, rw);
                         float re = 0.f, im = 0.f;
 #pragma unroll
                         for (int c = 0; c < 12; ++c) {
