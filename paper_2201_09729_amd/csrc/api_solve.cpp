@@ -121,12 +121,12 @@ template <int P> int alloc_cfg(Cfg& c, bool bicg, hipStream_t s) {
     if (bicg) {
         DLMA_TRY(c.bs.allocate(halfP));
         DLMA_TRY(c.bt.allocate(halfP));
-        DLMA_TRY(c.brh.allocate(halfP / n));  // one shadow residual, shared by every RHS
+        DLMA_TRY(c.brh.allocate(pair_bytes(P) * 12 * Vh));  // one shadow residual, shared by every RHS
         if (P == P16) {
             size_t nb = sizeof(float) * n * Vh;
             DLMA_TRY(c.nbs.allocate(nb));
             DLMA_TRY(c.nbt.allocate(nb));
-            DLMA_TRY(c.nbrh.allocate(nb / n));
+            DLMA_TRY(c.nbrh.allocate(sizeof(float) * Vh));
         }
         DLMA_TRY(c.bstate.allocate(sizeof(double2) * 4 * n));
         c.brho = c.bstate.as<double2>();
