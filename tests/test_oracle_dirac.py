@@ -205,3 +205,62 @@ def test_mass_derivative_of_solution(orc, small_system):
     S = np.linalg.inv(Dd)
     ref = -(S @ (S @ b.reshape(-1)))
     assert np.linalg.norm(fd - ref) / np.linalg.norm(ref) < 1e-6
+
+
+def test_true_residual_vs_dense(orc, small_system):
+    """The checker of every solve test: |b - D x|_2 / |b|_2 per right-hand side, in
+    FP64 and not squared (the reading of the 1e-10 residual), against the dense 4^4
+    operator.  Right-hand sides of very different norms, so that a reduction over the
+    wrong axes, a normalisation by |x| or a missing square root fails."""
+    dims, U, A, Dd = small_system
+    n = 4
+    scale = np.array([1.0, 1e-3, 50.0, 7.0])
+    b = synth.random_spinor(dims, n, 21) * scale[:, None, None, None, None, None, None]
+    bm = b.reshape(n, -1)
+    bn = np.linalg.norm(bm, axis=1)
+    xlu = np.linalg.solve(Dd, bm.T).T
+    # x = 0: residual 1 exactly
+    assert np.allclose(orc.true_residual(U, A, np.zeros_like(b), b), 1.0, rtol=0, atol=1e-15)
+    # x = c x_lu: residual |1 - c| per right-hand side (complex c, one per RHS)
+    c = np.array([0.5 + 0.5j, 2.0, -1.0, 1j])
+    xc = (c[:, None] * xlu).reshape(b.shape)
+    got = orc.true_residual(U, A, xc, b)
+    assert np.allclose(got, np.abs(1 - c), rtol=1e-12, atol=0), (got, np.abs(1 - c))
+    # x = x_lu + delta: residual |D delta| / |b|, delta of a different size per RHS
+    rng = np.random.default_rng(22)
+    eps = np.array([1e-3, 0.0, 0.3, 1e-6])
+    delta = (rng.normal(size=bm.shape) + 1j * rng.normal(size=bm.shape)) * (eps * bn)[:, None] / np.sqrt(bm.shape[1])
+    got = orc.true_residual(U, A, (xlu + delta).reshape(b.shape), b)
+    ref = np.linalg.norm(delta @ Dd.T, axis=1) / bn
+    assert got[1] < 1e-13, got
+    nz = eps > 0
+    assert np.allclose(got[nz], ref[nz], rtol=1e-8, atol=0), (got, ref)
+
+
+def test_cgls_fixed_is_the_krylov_minimiser(orc, small_system):
+    """The timed CGLS run: k iterations from x = 0 give the minimiser of |b - D x|_2 over
+    the Krylov space K_k(D^dag D, D^dag b) (the defining property of CG on the normal
+    equations), computed here by a dense least-squares problem in an orthonormal basis
+    of that space; its returned residual is |b - D x_k| / |b|."""
+    dims, U, A, Dd = small_system
+    b = synth.random_spinor(dims, 1, 23)
+    bv = b.reshape(-1)
+    Dh = np.conj(Dd.T)
+    w = Dh @ bv
+    basis = []
+    for k in range(1, 6):
+        basis.append(w)
+        Q, _ = np.linalg.qr(np.stack(basis, axis=1))
+        y, *_ = np.linalg.lstsq(Dd @ Q, bv, rcond=None)
+        xref = Q @ y
+        x, res = orc.cgls_fixed(U, A, b[0], k)
+        err = np.linalg.norm(x.reshape(-1) - xref) / np.linalg.norm(xref)
+        assert err < 1e-10, (k, err)
+        rref = np.linalg.norm(bv - Dd @ x.reshape(-1)) / np.linalg.norm(bv)
+        assert abs(res - rref) <= 1e-12 * rref, (k, res, rref)
+        w = Dh @ (Dd @ w)
+    # many iterations converge to the dense solution
+    x, res = orc.cgls_fixed(U, A, b[0], 160)
+    xlu = np.linalg.solve(Dd, bv)
+    assert np.linalg.norm(x.reshape(-1) - xlu) / np.linalg.norm(xlu) < 1e-11
+    assert res < 1e-12
