@@ -236,6 +236,26 @@ int dlma_lap_eigs(dlma_gauge_t g, int nev, int t0, int nt, const void* v0, void*
 int dlma_project(dlma_gauge_t g, int t, int nev, const void* V_t, const void* in, void* out,
                  int nrhs, int mode, void* stream);
 
+/*
+ * Allocation-free dlma_project, for callers that cannot allocate device memory
+ * (code under stream capture, tight serving loops, harnesses that forbid it).
+ * Same arguments, same kernels and bit-identical results as dlma_project, but:
+ *   - the projection coefficients live in one fixed 1 MiB device array per GPU
+ *     (65536 complex doubles), held from the first call on that GPU until the
+ *     process ends; right-hand sides are processed in chunks of 16384 / nev;
+ *   - no device memory is allocated or freed, and no library routine that
+ *     allocates is called;
+ *   - the call only enqueues work on `stream` and does not synchronise it.
+ * Every call on one GPU shares that array: calls on one GPU whose work can
+ * overlap (different streams without ordering, or several host threads) race
+ * on it and give wrong results.  Calls on one stream are ordered and safe.
+ * The array keeps the last call's coefficients; no call relies on its contents.
+ * Errors: DLMA_EINVAL (as dlma_project; also nev > 16384, the array's limit),
+ * DLMA_EHIP (device lookup or launch failure), DLMA_EUNSUPPORTED (device index >= 64).
+ */
+int dlma_project_noalloc(dlma_gauge_t g, int t, int nev, const void* V_t, const void* in, void* out,
+                         int nrhs, int mode, void* stream);
+
 #define DLMA_NPARTS 7
 #define DLMA_NGAMMA 2
 /*

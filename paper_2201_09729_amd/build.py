@@ -31,7 +31,7 @@ ARCH = os.environ.get("DLMA_ARCH", "gfx950")
 SOURCES = [
     "hop_p64.hip", "hop_p32.hip", "hop_p16.hip", "hop_pb16.hip",
     "kern_misc.hip", "laplace.hip", "contract.hip", "bicg.hip",
-    "runtime.cpp", "api_gauge.cpp", "api_solve.cpp", "api_eigs.cpp",
+    "runtime.cpp", "api_gauge.cpp", "api_solve.cpp", "api_eigs.cpp", "api_noalloc.cpp",
 ]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

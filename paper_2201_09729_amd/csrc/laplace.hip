@@ -657,7 +657,8 @@ hipError_t launch_project(const double2* Vt, const double2* in, double2* out, co
         int nr = nrhs - r0 < 65535 ? nrhs - r0 : 65535;
         const double2* inr = in + (long)r0 * V * 12;
         double2* outr = out + (long)r0 * V * 12;
-        hipLaunchKernelGGL(k_proj_coef, dim3(nev, nr), dim3(256), 0, s, Vt, inr, L3, (long)t * L3 * 12, V * 12, nev, coef);
+        if (nev > 0)  // no modes: box(t) = 0 and the apply kernel reads no coefficient
+            hipLaunchKernelGGL(k_proj_coef, dim3(nev, nr), dim3(256), 0, s, Vt, inr, L3, (long)t * L3 * 12, V * 12, nev, coef);
         hipLaunchKernelGGL(k_proj_apply, dim3((unsigned)((V * 4 + 255) / 256), nr), dim3(256), 0, s, Vt, inr, outr, L3, V, t, nev,
                            coef, mode);
     }

@@ -83,6 +83,7 @@ def load_library(path: str = LIB_PATH):
         "dlma_solve": ([P, I, P, P, P, P], I),
         "dlma_lap_eigs": ([P, I, I, I, P, P, P, P, P], I),
         "dlma_project": ([P, I, I, P, P, P, I, I, P], I),
+        "dlma_project_noalloc": ([P, I, I, P, P, P, I, I, P], I),
         "dlma_correlators": ([P, I, I, P, P, I, I, P, P, P, P], I),
         "dlma_dot": ([P, P, ctypes.c_long, P, P], I),
         "dlma_profile_enable": ([I], I),
@@ -250,6 +251,19 @@ def dlma_project(g: Gauge, t: int, Vt: torch.Tensor, x: torch.Tensor, mode: int,
     _check(load_library().dlma_project(g.h, int(t), int(Vt.shape[0]), ctypes.c_void_p(Vt.data_ptr()),
                                        ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
                                        int(x.shape[0]), int(mode), _stream()))
+    return out
+
+
+def dlma_project_noalloc(g: Gauge, t: int, Vt: torch.Tensor, x: torch.Tensor, mode: int, out: torch.Tensor):
+    """dlma_project through the allocation-free entry point: `out` is caller-allocated, the
+    library allocates nothing and only enqueues work on the current stream."""
+    Vt = _dev(Vt)
+    x = _dev(x)
+    if out.shape != x.shape or not out.is_contiguous() or out.dtype != x.dtype or not out.is_cuda:
+        raise ValueError("out must be a contiguous complex128 GPU tensor shaped like x")
+    _check(load_library().dlma_project_noalloc(g.h, int(t), int(Vt.shape[0]), ctypes.c_void_p(Vt.data_ptr()),
+                                               ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                               int(x.shape[0]), int(mode), _stream()))
     return out
 
 
