@@ -95,12 +95,17 @@ def main():
     ap.add_argument("--no-variants", action="store_true", help="skip the FP64 / BF16 / single-RHS comparisons")
     ap.add_argument("--copy-probe", action="store_true", help="also run a plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--prof-steps", type=int, default=1,
+                    help="extra steps run with per-launch HIP events for the kernel-class times")
     ap.add_argument("--inner-solver", type=int, default=1, choices=(0, 1),
                     help="Krylov method of the inner solves: 1 = BiCGStab on Dhat, 0 = CG on Dhat Dhat^dag")
     ap.add_argument("--rhs-block", type=int, default=None,
                     help="right-hand sides per thread in the stencil kernels (0 = autotune; default 2, 1 for fp64)")
-    ap.add_argument("--summarize", nargs=3, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR"),
-                    help="write profiles/ summaries from rocprofv3 output directories and exit")
+    ap.add_argument("--summarize", nargs="+", metavar="DIR",
+                    help="write profiles/ summaries from rocprofv3 output directories and exit: TRACE_DIR "
+                         "FETCH_DIR WRITE_DIR [COUNTER_DIR] (COUNTER_DIR: the run with SQ_INSTS_VALU, "
+                         "SQ_ACTIVE_INST_VALU, SQ_BUSY_CYCLES, SQ_WAVES, SQ_INSTS_VMEM, GRBM_GUI_ACTIVE, "
+                         "TA_TA_BUSY_sum, TD_TD_BUSY_sum, TCC_HIT_sum, TCC_MISS_sum)")
     ap.add_argument("--profile-cmd", default="", help="command line recorded in the summaries")
     ap.add_argument("--lap-scaling", action="store_true",
                     help="Laplacian eigensolver cost vs number of modes on a 64x32^3 lattice (matvec / "
@@ -144,6 +149,10 @@ def main():
     b = torch.zeros((nrhs,) + DIMS + (4, 3), dtype=torch.complex128, device=dev)
     x = torch.zeros_like(b)
     log("setup: fields on the GPU in %.1f s" % (time.time() - t_setup))
+    if not args.no_variants:  # measured copy peak, before the solves fill the library's memory pool
+        copy_torch = copy_peak(torch, dev)
+        copy_gbs = dlma.dlma_bench_copy(1 << 31, 10)
+        log("measured 2 GiB stream copy: %.0f GB/s (library kernel), %.0f GB/s (torch copy_)" % (copy_gbs, copy_torch))
 
     def step(prec, timed_stats=None):
         g = dlma.dlma_load_gauge(U, KAPPA, CSW)                       # gauge ingest, clover, A_oo^-1
@@ -166,8 +175,8 @@ def main():
         step(args.prec)
         torch.cuda.synchronize()
         log("warmup %d: %.3f s" % (w, time.time() - t))
-    dlma.dlma_profile_reset()
-    dlma.dlma_profile_enable(True)
+    # the timed steps run the product path as a caller gets it: per-launch timing off,
+    # so the inner iterations are replayed from hipGraphs
     stats = []
     torch.cuda.synchronize()
     t_start = time.time()
@@ -176,16 +185,29 @@ def main():
         log("step %d done at %.3f s" % (k, time.time() - t_start))
     torch.cuda.synchronize()
     elapsed = time.time() - t_start
-    dlma.dlma_profile_enable(False)
-    prof = {kc: dlma.dlma_profile_read(kc) for kc in KCLASS}
     ms_per_step = 1e3 * elapsed / args.steps
     value = nrhs * args.steps / elapsed
+    for st in stats:
+        assert all(s["converged"] and s["relres"] <= TOL for s in st), "not every right-hand side converged"
     st = stats[-1]
-    assert all(s["converged"] and s["relres"] <= TOL for s in st), "not every right-hand side converged"
     iters = [s["inner_iters"] for s in st]
     outer = [s["outer"] for s in st]
     log("headline: %.2f RHS/s, %.1f ms/step, inner iterations %d..%d, outer passes %d..%d"
         % (value, ms_per_step, min(iters), max(iters), min(outer), max(outer)))
+    # kernel timing: the same step again with every stencil launch bracketed by HIP events
+    # on its stream (direct launches: events around single kernels need them)
+    dlma.dlma_profile_reset()
+    dlma.dlma_profile_enable(True)
+    pstats = []
+    torch.cuda.synchronize()
+    t = time.time()
+    for k in range(args.prof_steps):
+        step(args.prec, pstats)
+    torch.cuda.synchronize()
+    prof_ms_per_step = 1e3 * (time.time() - t) / args.prof_steps
+    dlma.dlma_profile_enable(False)
+    prof = {kc: dlma.dlma_profile_read(kc) for kc in KCLASS}
+    log("profiled steps (direct launches, per-launch events): %.1f ms/step" % prof_ms_per_step)
 
     # dominant stencil kernel of the timed region (HIP events around each launch).  Its
     # algorithmic bytes count only right-hand sides still iterating: a launch reads
@@ -197,7 +219,7 @@ def main():
     n_l, ms_tot, by_all = prof[kc]
     fixed, per_rhs = hop_bytes_split(args.prec, *KTEMPLATE[kc], DIMS)
     per_iter = 2 if (args.inner_solver == 1 and kc == 0) else 1  # BiCGStab applies K1 twice per iteration
-    rhs_launches = per_iter * sum(s["inner_iters"] for stp in stats for s in stp)
+    rhs_launches = per_iter * sum(s["inner_iters"] for stp in pstats for s in stp)
     by_tot = n_l * fixed + rhs_launches * per_rhs
     achieved = by_tot / (ms_tot * 1e-3) / 1e9
     roofline = {"kernel": KCLASS[kc], "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
@@ -205,9 +227,13 @@ def main():
                 "launches": n_l, "avg_launch_ms": round(ms_tot / max(n_l, 1), 4),
                 "alg_bytes_per_launch": round(by_tot / max(n_l, 1)),
                 "active_rhs_per_launch": round(rhs_launches / max(n_l, 1), 1),
-                "bytes_model": "Vh*(72 b_pair links + 36 b_pair clover) per launch + Vh*passes*(12 b_pair [+4 FP16 scale]) "
-                               "per active RHS; passes = %d" % round(per_rhs / (DIMS[0] * DIMS[1] * DIMS[2] * DIMS[3] // 2)
-                                                                       / spinor_bytes(args.prec))}
+                "bytes_model": "Vh*(72 b_pair links + 36 b_pair clover) per launch [+ Vh*(12 b_pair [+4]) for the "
+                               "shared BiCGStab shadow residual read by K2 with (rh, v)] + Vh*passes*(12 b_pair "
+                               "[+4 FP16 scale]) per active RHS; passes = %d" % round(
+                                   per_rhs / (DIMS[0] * DIMS[1] * DIMS[2] * DIMS[3] // 2) / spinor_bytes(args.prec)),
+                "timing": "HIP events around every launch of this class on its stream, in %d extra step(s) of the "
+                          "same workload run with direct launches (%.1f ms/step); the timed steps replay hipGraphs "
+                          "and carry no per-launch events" % (args.prof_steps, prof_ms_per_step)}
     tfile = os.path.join(ROOT, "profiles", "traffic_%s.json" % KCLASS[kc].split()[0])
     if os.path.exists(tfile):
         with open(tfile) as fh:
@@ -216,6 +242,10 @@ def main():
                 and tr.get("rhs_block") == args.rhs_block):
             roofline["traffic"] = tr.get("traffic_bytes_per_launch")
             roofline["traffic_note"] = tr.get("note")
+            if tr.get("valu_busy_frac") is not None:
+                # vector-ALU issue: SQ_INSTS_VALU wave instructions x 4 cycles over the SIMD cycles
+                # of the dispatch (1024 SIMDs x GRBM_GUI_ACTIVE), from the committed counter runs
+                roofline["issue"] = {"valu_busy_frac": tr["valu_busy_frac"], "derivation": tr.get("valu_note")}
 
     out = {"metric": METRIC, "value": round(value, 3), "unit": "RHS/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": round(ms_per_step, 2), "higher_is_better": True, "scaling": "weak",
@@ -232,6 +262,7 @@ def main():
                       "step": "gauge load + clover + Laplacian modes on t' + sources + projection + batched solve"},
            "roofline": roofline,
            "iterations": {"inner_min": min(iters), "inner_max": max(iters), "outer_max": max(outer)},
+           "profiled_ms_per_step": round(prof_ms_per_step, 2),
            "kernel_classes": {KCLASS[k].split()[0]: {"launches": prof[k][0], "total_ms": round(prof[k][1], 3),
                                                      "GBps": round(prof[k][2] / max(prof[k][1], 1e-9) / 1e6, 1)}
                               for k in prof if prof[k][0] > 0}}
@@ -240,9 +271,7 @@ def main():
     if not args.no_variants:
         var = {}
         g, V, _ = step(args.prec)
-        for prec in ("fp64", "mix_bf16", "mix_fp32"):
-            if prec == args.prec:
-                continue
+        for prec in ("fp64", "mix_fp16", "mix_bf16", "mix_fp32"):
             # one short capped solve first, so the RHS-block autotuner's search is not timed
             dlma.dlma_solve([g], [b], xs=[x], opts=dlma.default_opts(tol=TOL, prec=prec, maxiter=8, max_outer=1,
                                                                      inner_solver=args.inner_solver),
@@ -275,12 +304,16 @@ def main():
         out["speedup_vs_fp64_single_rhs"] = round(value * dt, 2)
         log("fp64 single-RHS baseline: %.2f RHS/s; headline speedup %.1fx" % (1.0 / dt, value * dt))
         # Dslash (Schur operator) bandwidth per precision and right-hand sides
-        dsl = {}
+        dsl = {"copy_peak_GBps": round(copy_gbs, 1), "torch_copy_GBps": round(copy_torch, 1),
+               "note": "frac_hbm against 8 TB/s, frac_copy against the measured 2 GiB stream copy (dlma_bench_copy)"}
         for prec in ("fp64", "mix_fp32", "mix_fp16", "mix_bf16"):
-            for n in (1, 16, 64):
+            for n in (1, 8, 16, 32, 64, 128):
                 ms, by = dlma.dlma_bench_schur(g, prec, n, 0, 10)
                 dsl["%s_n%d" % (prec, n)] = {"ms_per_apply": round(ms, 4), "GBps": round(by / ms / 1e6, 1),
-                                             "frac_hbm": round(by / ms / 1e6 / HBM_PEAK_GBS, 4)}
+                                             "frac_hbm": round(by / ms / 1e6 / HBM_PEAK_GBS, 4),
+                                             "frac_copy": round(by / ms / 1e6 / copy_gbs, 4)}
+            log("Schur operator %s: %s" % (prec, ", ".join("n=%d %.2f" % (n, dsl["%s_n%d" % (prec, n)]["frac_hbm"])
+                                                          for n in (1, 8, 16, 32, 64, 128))))
         out["dslash"] = dsl
         # off the timed metric: Laplacian modes on every timeslice and the correlators
         torch.cuda.synchronize()
@@ -295,6 +328,14 @@ def main():
                              "C_dist_over_C_PS_delta1": float((C["PS"]["PP_exact"][1] / C["PS"]["11_est"][1]).real)}
         log("Laplacian modes on all %d timeslices: %.2f s; correlators %.2f s" % (T, t_lap, t_cor))
         del Vall
+
+    if not args.no_variants:
+        del b, x
+        torch.cuda.empty_cache()
+        out["uneven_batch"] = uneven_batch(torch, dlma, synth)
+        torch.cuda.empty_cache()
+        out["correlator_error"] = correlator_error(torch, dlma, synth)
+        torch.cuda.empty_cache()
 
     if args.copy_probe:
         a = torch.empty(1 << 27, dtype=torch.float64, device=dev)
@@ -330,6 +371,138 @@ def main():
                                "clover_build_s": round(t_cl, 2)}
         log("cpu baseline: %.4g RHS/s (%d threads)" % (rate, oracle.num_threads()))
     print(json.dumps(out), flush=True)
+
+
+def copy_peak(torch, dev, nbytes=1 << 31, reps=10):
+    """Measured stream bandwidth: a 2 GiB device-to-device copy, read + write bytes per second."""
+    a = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)
+    c = torch.empty_like(a)
+    c.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        c.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, c
+    return 2.0 * nbytes / (ms * 1e-3) / 1e9
+
+
+def uneven_batch(torch, dlma, synth):
+    """The uneven batch in one solve: 3 x 12^3x24 (seeds 1-3), 2 x 16^3x32 (seeds 4, 5) and
+    1 x 24^3x48 (seed 6), eps 0.25, kappa cycling 0.119, 0.120, 0.121, c_sw 1.2; per
+    configuration 4N distillation sources plus as many Z2 noise sources (N_r x 4 spins x
+    {eta, (1 - box) eta}): 256, 128 and 64 right-hand sides for the three volumes.  BF16
+    storage, FP32 inner BiCGStab, FP64 defect correction to 1e-10; every launch covers every
+    configuration.  The autotuner runs in an untimed capped solve first."""
+    shapes = [(24, 12, 12, 12)] * 3 + [(32, 16, 16, 16)] * 2 + [(48, 24, 24, 24)]
+    kappas = [0.119, 0.120, 0.121, 0.119, 0.120, 0.121]
+    nevs = {24: 32, 32: 16, 48: 8}
+    gs, bs = [], []
+    for i, dims in enumerate(shapes):
+        seed = i + 1
+        T = dims[0]
+        nev = nevs[T]
+        nn = nev // 2  # noise vectors: 4 spins x {eta, (1 - box) eta} each, as many RHS as the distillation ones
+        U = torch.from_numpy(synth.gauge_field(dims, EPS, seed)).to("cuda")
+        g = dlma.dlma_load_gauge(U, kappas[i], CSW)
+        V, _ = dlma.dlma_lap_eigs(g, nev, T0, 1, torch.from_numpy(synth.gaussian_start(dims, 1, 600 + seed)).to("cuda"),
+                                  block_size=min(64, nev + max(8, nev // 2)))
+        eta = dlma.noise_sources(torch.from_numpy(synth.z2_noise(dims, T0, nn, 1000 + seed)).to("cuda"), T, T0)
+        bs.append(torch.cat([dlma.dist_sources(V[0], T, T0), eta, dlma.dlma_project(g, T0, V[0], eta, 1)]))
+        gs.append(g)
+        del U, V, eta
+    xs = [torch.zeros_like(b) for b in bs]
+    nrhs = sum(b.shape[0] for b in bs)
+    dlma.dlma_solve(gs, bs, xs=xs, opts=dlma.default_opts(tol=TOL, prec="mix_bf16", maxiter=8, max_outer=1),
+                    allow_notconv=True)
+    torch.cuda.synchronize()
+    t = time.time()
+    xs, st = dlma.dlma_solve(gs, bs, xs=xs, opts=dlma.default_opts(tol=TOL, prec="mix_bf16"))
+    torch.cuda.synchronize()
+    dt = time.time() - t
+    assert all(s["converged"] and s["relres"] <= TOL for s in st)
+    res = {"configs": "3 x 12^3x24 (256 RHS each), 2 x 16^3x32 (128 each), 1 x 24^3x48 (64)",
+           "nrhs": nrhs, "precision": "BF16 storage, FP32 arithmetic, FP64 defect correction",
+           "solve_s": round(dt, 3), "rhs_per_s": round(nrhs / dt, 2),
+           "site_rhs_per_s": round(sum(b.shape[0] * int(np.prod(b.shape[1:5])) for b in bs) / dt, 1),
+           "inner_iters_max": max(s["inner_iters"] for s in st), "outer_max": max(s["outer"] for s in st),
+           "max_relres": max(s["relres"] for s in st)}
+    log("uneven batch: %d RHS over 6 configurations in %.2f s (%.1f RHS/s)" % (nrhs, dt, nrhs / dt))
+    del gs, bs, xs
+    return res
+
+
+def tslice_norms(torch, f):
+    """[n][T] 2-norms of each field per timeslice."""
+    return torch.sqrt((f.abs() ** 2).sum(dim=(2, 3, 4, 5, 6)))
+
+
+def correlator_error(torch, dlma, synth, dims=(32, 16, 16, 16), seed=3, nev=32, nnoise=8):
+    """Correlator error of the mixed-precision solves against FP64 solves, per timeslice (paper
+    eqs. (2)-(4): every piece dlma_correlators returns), on 16^3 x 32 (eps 0.25, kappa 0.121,
+    c_sw 1.2, seed 3): N = 32 modes on every timeslice, 128 distillation right-hand sides and
+    8 Z2 noise vectors (32 eta + 32 (1 - box) eta), solved in FP64 (to 1e-12), MIX_FP16 and
+    MIX_BF16 (to 1e-10).  For each piece, Gamma and precision: the largest relative error
+    |dC(t)| / |C(t)| over t, and the largest ratio of |dC(t)| to its bound
+      (1/N_r) sum_r [|dY_r|_t |phi_r|_t + |Y_r|_t |dphi_r|_t + |dY_r|_t |dphi_r|_t]
+    (Cauchy-Schwarz with |X_t| <= 1 and unit-modulus Gamma g5 entries; Y the source-side
+    solution of the piece, d the difference of the mixed solution from the FP64 one, norms
+    over timeslice t and the four spins of a group)."""
+    T = dims[0]
+    U = torch.from_numpy(synth.gauge_field(dims, EPS, seed)).to("cuda")
+    g = dlma.dlma_load_gauge(U, KAPPA, CSW)
+    Vall, _ = dlma.dlma_lap_eigs(g, nev, 0, T, torch.from_numpy(synth.gaussian_start(dims, T, 600 + seed)).to("cuda"))
+    eta = dlma.noise_sources(torch.from_numpy(synth.z2_noise(dims, T0, nnoise, 1000 + seed)).to("cuda"), T, T0)
+    b = torch.cat([dlma.dist_sources(Vall[T0], T, T0), eta, dlma.dlma_project(g, T0, Vall[T0], eta, 1)])
+    nd, nn = 4 * nev, 4 * nnoise
+    sol, C = {}, {}
+    for prec, tol in (("fp64", 1e-12), ("mix_fp16", TOL), ("mix_bf16", TOL)):
+        (x,), st = dlma.dlma_solve([g], [b], opts=dlma.default_opts(tol=tol, prec=prec))
+        assert all(s_["converged"] for s_ in st)
+        sol[prec] = x
+        C[prec] = dlma.dlma_correlators(g, T0, Vall, x[:nd], x[nd:nd + nn], x[nd + nn:])
+    ref = sol["fp64"]
+    # (sink solution, source-side solution, number of averaged groups) of every piece
+    parts = {"QQ_est": ("phi", "phibar", nnoise), "PQ_est": ("phi", "phibar", nnoise),
+             "QP_est": ("phi", "phiP", nnoise), "PP_est": ("phi", "phiP", nnoise), "11_est": ("phi", "phi", nnoise),
+             "PP_exact": ("dist", "dist", 1), "QP_exact": ("dist", "dist", 1)}
+
+    def fields(x):
+        return {"dist": x[:nd], "phi": x[nd:nd + nn], "phibar": x[nd + nn:], "phiP": x[nd:nd + nn] - x[nd + nn:]}
+
+    def group_norms(f):  # [groups][T]: norm over the four spins of each group, per timeslice
+        n = tslice_norms(torch, f)
+        return torch.sqrt((n.reshape(-1, 4, T) ** 2).sum(dim=1))
+
+    fr = fields(ref)
+    nref = {k: group_norms(v) for k, v in fr.items()}
+    out = {}
+    for prec in ("mix_fp16", "mix_bf16"):
+        fm = fields(sol[prec])
+        nd_ = {k: group_norms(fm[k] - fr[k]) for k in fr}
+        eps_x = float((torch.linalg.vector_norm((sol[prec] - ref).reshape(ref.shape[0], -1), dim=1)
+                       / torch.linalg.vector_norm(ref.reshape(ref.shape[0], -1), dim=1)).max())
+        rp = {"solution_rel_err_max": eps_x}
+        for gname in ("PS", "V"):
+            for part, (xs_, ys_, ngrp) in parts.items():
+                c0 = np.asarray(C["fp64"][gname][part])
+                dc = np.abs(np.asarray(C[prec][gname][part]) - c0)
+                bound = ((nd_[ys_] * nref[xs_] + nref[ys_] * nd_[xs_] + nd_[ys_] * nd_[xs_]).sum(dim=0)
+                         / ngrp).cpu().numpy()
+                rel = dc / np.maximum(np.abs(c0), 1e-300)
+                rp["%s_%s" % (gname, part)] = {"max_rel": float(rel.max()),  # time index is Delta = t - t'
+                                               "rel_at_delta_0_1_8_16": [float(rel[d]) for d in (0, 1, 8, 16)],
+                                               "max_err_over_bound": float((dc / np.maximum(bound, 1e-300)).max())}
+        out[prec] = rp
+        worst = max(v["max_rel"] for k, v in rp.items() if isinstance(v, dict))
+        wb = max(v["max_err_over_bound"] for k, v in rp.items() if isinstance(v, dict))
+        log("correlator error %s vs fp64 (16^3x32): max relative %.2e, max error/bound %.2e, solution error %.2e"
+            % (prec, worst, wb, eps_x))
+    del sol, b, Vall
+    return {"lattice": "16^3x32", "eps": EPS, "seed": seed, "kappa": KAPPA, "csw": CSW, "nev": nev,
+            "noise_vectors": nnoise, "nrhs": nd + 2 * nn, "reference": "FP64 solves to 1e-12", **out}
 
 
 def lap_scaling(args):
@@ -470,7 +643,8 @@ def summarize(args):
     launches of the same kernels do not enter them."""
     import csv
     import collections
-    trace, fetch, write = args.summarize
+    trace, fetch, write = args.summarize[:3]
+    cdir = args.summarize[3] if len(args.summarize) > 3 else None
     prec = args.prec
 
     def find(d, suffix):
@@ -539,6 +713,46 @@ def summarize(args):
                    "traffic_bytes_per_launch": tb, "avg_ms_rocprof": avg_ms,
                    "note": "FETCH_SIZE and WRITE_SIZE per dispatch scaled by the 1 GiB copy calibration",
                    "command": args.profile_cmd}
+    if cdir:
+        crows = timed_step(list(csv.DictReader(open(find(cdir, "counter_collection.csv")))))
+        cnt = collections.defaultdict(lambda: collections.defaultdict(list))
+        for r in crows:
+            cnt[r["Kernel_Name"]][r["Counter_Name"]].append(float(r["Counter_Value"]))
+        # the kernels of the timed step by their total time there
+        top = sorted(step_ms, key=lambda k: -sum(step_ms[k]))[:10]
+        nsimd, ncu = 1024, 256
+        lines += ["", "## Issue and cache counters per dispatch (rocprofv3 --pmc, one run)", "",
+                  "Per kernel: averages over its dispatches in the timed step.  VALU issue = SQ_INSTS_VALU x 4 cycles "
+                  "(a wave64 VALU instruction occupies a 16-lane SIMD for 4 cycles) / (%d SIMDs x GRBM_GUI_ACTIVE); "
+                  "VALU busy = SQ_ACTIVE_INST_VALU / (%d CUs x GRBM_GUI_ACTIVE) (rocprofv3's VALUBusy); TA, TD busy = "
+                  "TA_TA_BUSY_sum, TD_TD_BUSY_sum / (%d x GRBM_GUI_ACTIVE); L2 hit = TCC_HIT / (TCC_HIT + TCC_MISS); "
+                  "clock = GRBM_GUI_ACTIVE / the kernel-trace duration." % (nsimd, ncu, ncu), "",
+                  "| kernel | ms | clock GHz | VALU issue | VALU busy | TA busy | TD busy | L2 hit | VALU inst/wave | VMEM inst/wave |",
+                  "|---|---|---|---|---|---|---|---|---|---|"]
+        issue = {}
+        for k in top:
+            c = {n: sum(v) / len(v) for n, v in cnt.get(k, {}).items()}
+            if "GRBM_GUI_ACTIVE" not in c or c["GRBM_GUI_ACTIVE"] <= 0:
+                continue
+            gui = c["GRBM_GUI_ACTIVE"]
+            ms = sum(step_ms[k]) / len(step_ms[k])
+            vi = 4.0 * c.get("SQ_INSTS_VALU", 0) / (nsimd * gui)
+            vb = c.get("SQ_ACTIVE_INST_VALU", 0) / (ncu * gui)
+            ta = c.get("TA_TA_BUSY_sum", 0) / (ncu * gui)
+            td = c.get("TD_TD_BUSY_sum", 0) / (ncu * gui)
+            hit = c.get("TCC_HIT_sum", 0)
+            miss = c.get("TCC_MISS_sum", 0)
+            l2 = hit / (hit + miss) if hit + miss > 0 else float("nan")
+            issue[k] = vi
+            nw = c.get("SQ_WAVES", None)
+            lines.append("| `%s` | %.4f | %.2f | %.3f | %.3f | %.3f | %.3f | %.3f | %s | %s |" % (
+                k[:90], ms, gui / (ms * 1e6), vi, vb, ta, td, l2,
+                "%.0f" % (c["SQ_INSTS_VALU"] / nw) if nw else "-", "%.0f" % (c["SQ_INSTS_VMEM"] / nw) if nw else "-"))
+        for kc, d in out.items():
+            if d["kernel"] in issue:
+                d["valu_busy_frac"] = round(issue[d["kernel"]], 4)
+                d["valu_note"] = ("SQ_INSTS_VALU x 4 cycles / (1024 SIMDs x GRBM_GUI_ACTIVE), per dispatch of the timed "
+                                  "step (rocprofv3 --pmc; profiles/hop_kernels_24x48_%s.md)" % prec)
     os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
     tag = "24x48_%s" % prec
     with open(os.path.join(ROOT, "profiles", "hop_kernels_%s.md" % tag), "w") as fh:

@@ -329,6 +329,15 @@ int dlma_profile_read(int kclass, long long* launches, double* total_ms, double*
 int dlma_bench_schur(dlma_gauge_t g, int prec, int nrhs, int rhs_block, int napply,
                      double* ms_out, double* bytes_out, void* stream);
 
+/*
+ * Streaming copy of `bytes` (a positive multiple of 16) between two library-owned
+ * device buffers, reps times (after one warm-up copy); ms_out (host) receives the
+ * milliseconds per copy.  The measured peak of read + write memory bandwidth
+ * (2 * bytes per copy) against which the stencil bandwidths are also quoted.
+ * Synchronises the stream.  Errors: DLMA_EINVAL, DLMA_ENOMEM, DLMA_EHIP.
+ */
+int dlma_bench_copy(long bytes, int reps, double* ms_out, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

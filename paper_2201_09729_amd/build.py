@@ -63,30 +63,66 @@ def _vregs(tok: str) -> set:
     return {int(m.group(1))} if m else set()
 
 
-def store_data_hazards(asm: str, need: int = 2) -> list:
-    """(kernel, store, instruction) for each vector ALU write of a wide store's data
-    registers fewer than `need` wait states after the store (s_nop N counts N + 1)."""
-    out, fn, pending = [], "?", []
+_ADDR = re.compile(r"//\s*([0-9A-Fa-f]+):")
+_TARGET = re.compile(r"<(\S+)\+0x([0-9a-fA-F]+)>")
+_ENDS = ("s_endpgm", "s_setpc_b64", "s_trap", "s_rfe_b64")
+
+
+def _functions(asm: str):
+    """Per function: its name and [(address, op, tokens, text, branch target address)]."""
+    fns, cur, base = [], None, 0
     for line in asm.splitlines():
-        m = re.match(r"^[0-9a-f]+ <(\S+)>:", line)
+        m = re.match(r"^([0-9a-f]+) <(\S+)>:", line)
         if m:
-            fn, pending = m.group(1), []
+            base = int(m.group(1), 16)
+            cur = (m.group(2), [])
+            fns.append(cur)
             continue
-        ins = line.split("//")[0].strip()
+        if cur is None:
+            continue
+        code, _, comment = line.partition("//")
+        ins = code.strip()
         if not ins or ins.endswith(":"):
             continue
+        ma = _ADDR.search(line)
+        addr = int(ma.group(1), 16) if ma else (cur[1][-1][0] + 4 if cur[1] else base)
+        mt = _TARGET.search(comment)
+        tgt = base + int(mt.group(2), 16) if (mt and mt.group(1) == cur[0]) else None
         t = ins.replace(",", " ").split()
-        op = t[0]
-        if op.startswith("v_") and not op.startswith("v_cmp") and len(t) > 1:
-            dst = _vregs(t[1])
-            for data, store, _ in pending:
-                if dst & data:
-                    out.append((fn, store, ins))
-        ws = int(t[1]) + 1 if op == "s_nop" and len(t) > 1 else 1
-        pending = [(d, st, w + ws) for d, st, w in pending if w + ws < need]
-        if WIDE_STORE.match(op):
+        cur[1].append((addr, t[0], t, ins, tgt))
+    return fns
+
+
+def store_data_hazards(asm: str, need: int = 2) -> list:
+    """(kernel, store, instruction) for each vector ALU write of a wide store's data
+    registers fewer than `need` wait states after the store (s_nop N counts N + 1), on
+    every path from the store: fall-through and branch targets both.  Every issued
+    instruction other than s_nop counts as one wait state, branches included."""
+    out = []
+    for fn, code in _functions(asm):
+        at = {a: i for i, (a, *_rest) in enumerate(code)}
+        for i, (_, op, t, ins, _) in enumerate(code):
+            if not WIDE_STORE.match(op):
+                continue
             data = _vregs(t[1] if op.startswith("buffer") else t[2])
-            pending.append((data, ins, 0))
+            stack, seen = [(i + 1, 0)], set()
+            while stack:
+                j, w = stack.pop()
+                if j >= len(code) or (j, w) in seen:
+                    continue
+                seen.add((j, w))
+                _, opj, tj, insj, tgt = code[j]
+                if opj.startswith("v_") and not opj.startswith("v_cmp") and len(tj) > 1 and _vregs(tj[1]) & data:
+                    out.append((fn, ins, insj))
+                    continue
+                is_branch = opj.startswith("s_branch") or opj.startswith("s_cbranch")
+                w2 = w + (int(tj[1]) + 1 if opj == "s_nop" and len(tj) > 1 else 1)
+                if w2 >= need or opj in _ENDS:
+                    continue
+                if is_branch and tgt is not None and tgt in at:
+                    stack.append((at[tgt], w2))
+                if opj != "s_branch":
+                    stack.append((j + 1, w2))
     return out
 
 

@@ -62,6 +62,7 @@ struct Cfg {
     int* oact;  // right-hand sides iterated in the last pass: the FP64 outer stencils skip the others
     std::vector<double> bnorm2, rnorm2, relres;
     std::vector<int> used, conv, hact, hiters, hoact;
+    std::vector<char> evenonly;      // rnorm2[r] holds the even sites' residual only
     int outer = 0;
 };
 
@@ -150,6 +151,7 @@ template <int P> int alloc_cfg(Cfg& c, bool bicg, hipStream_t s) {
     DLMA_HIP(hipMemsetAsync(c.dstate.p, 0, sizeof(double) * 8 * n + sizeof(int) * 3 * n, s));
     c.bnorm2.assign(n, 0); c.rnorm2.assign(n, 0); c.relres.assign(n, 0);
     c.used.assign(n, 0); c.conv.assign(n, 0); c.hact.assign(n, 0); c.hiters.assign(n, 0); c.hoact.assign(n, 1);
+    c.evenonly.assign(n, 0);
     return DLMA_OK;
 }
 
@@ -580,10 +582,22 @@ int solve_impl(std::vector<Cfg>& cs, const dlma_solve_opts& o, hipStream_t s) {
         DLMA_HIP(hipStreamSynchronize(s));
         for (size_t i = 0; i < cs.size(); ++i)
             for (int r = 0; r < cs[i].nrhs; ++r) {
-                if (sites == 2) cs[i].rnorm2[r] += got[i][r];
-                else if (cs[i].hoact[r]) cs[i].rnorm2[r] = got[i][r];
+                Cfg& c = cs[i];
+                if (sites == 2) {  // complete the norms that hold the even sites only
+                    if (c.evenonly[r]) c.rnorm2[r] += got[i][r];
+                    c.evenonly[r] = 0;
+                } else if (c.hoact[r]) {
+                    c.rnorm2[r] = got[i][r];
+                    c.evenonly[r] = sites == 1;
+                }
             }
         return DLMA_OK;
+    };
+    auto any_even_only = [&]() {
+        for (auto& c : cs)
+            for (char e : c.evenonly)
+                if (e) return true;
+        return false;
     };
     auto upload_oact = [&](bool all) -> int {
         for (auto& c : cs) {
@@ -621,16 +635,27 @@ int solve_impl(std::vector<Cfg>& cs, const dlma_solve_opts& o, hipStream_t s) {
         }
         int nleft = 0;
         int maxused = 0;
-        for (auto& c : cs) {
-            c.outer = pass;
-            for (int r = 0; r < c.nrhs; ++r) {
-                double rr = c.rnorm2[r];
-                if (!std::isfinite(rr)) nan = true;
-                c.relres[r] = c.bnorm2[r] > 0 ? std::sqrt(rr / c.bnorm2[r]) : 0.0;
-                c.conv[r] = (c.relres[r] <= o.tol) ? 1 : 0;
-                if (!c.conv[r]) { ++nleft; maxused = std::max(maxused, c.used[r]); }
-                c.hact[r] = c.conv[r] ? 0 : 1;
+        auto evaluate = [&]() {
+            nleft = 0;
+            maxused = 0;
+            for (auto& c : cs) {
+                c.outer = pass;
+                for (int r = 0; r < c.nrhs; ++r) {
+                    double rr = c.rnorm2[r];
+                    if (!std::isfinite(rr)) nan = true;
+                    c.relres[r] = c.bnorm2[r] > 0 ? std::sqrt(rr / c.bnorm2[r]) : 0.0;
+                    c.conv[r] = (c.relres[r] <= o.tol) ? 1 : 0;
+                    if (!c.conv[r]) { ++nleft; maxused = std::max(maxused, c.used[r]); }
+                    c.hact[r] = c.conv[r] ? 0 : 1;
+                }
             }
+        };
+        evaluate();
+        // stopped by a cap with even-site norms still held: the statistics report the
+        // full residual of every right-hand side, so add the odd sites once
+        if (!nan && nleft > 0 && (pass >= o.max_outer || maxused >= o.maxiter) && any_even_only()) {
+            DLMA_TRY(true_residual(2));
+            evaluate();
         }
         if (nan) return fail(DLMA_ENAN, "non-finite residual during the solve");
         if (dlog) {
@@ -1079,4 +1104,32 @@ extern "C" int dlma_bench_schur(dlma_gauge_t h, int prec, int nrhs, int rhs_bloc
     case DLMA_PREC_MIX_BF16: return bench_impl<PB16>(g, nrhs, rhs_block, napply, ms_out, bytes_out, s);
     default: return fail(DLMA_EINVAL, "prec must be one of DLMA_PREC_*");
     }
+}
+
+extern "C" int dlma_bench_copy(long bytes, int reps, double* ms_out, void* stream) {
+    if (bytes < 16 || bytes % 16 != 0 || reps < 1 || !ms_out)
+        return fail(DLMA_EINVAL, "bytes must be a positive multiple of 16, reps >= 1, ms_out not NULL");
+    hipStream_t s = S(stream);
+    Buf a, b;
+    DLMA_TRY(a.allocate((size_t)bytes));
+    DLMA_TRY(b.allocate((size_t)bytes));
+    DLMA_HIP(hipMemsetAsync(a.p, 0, (size_t)bytes, s));
+    DLMA_HIP(launch_stream_copy(a.p, b.p, bytes / 16, s));  // warm-up
+    hipEvent_t e0, e1;
+    DLMA_HIP(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(DLMA_EHIP, "hipEventCreate failed");
+    }
+    hipError_t e = hipEventRecord(e0, s);
+    for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_stream_copy(a.p, b.p, bytes / 16, s);
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return fail(DLMA_EHIP, std::string("stream copy: ") + hipGetErrorString(e));
+    *ms_out = ms / reps;
+    return DLMA_OK;
 }

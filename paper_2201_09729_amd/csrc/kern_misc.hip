@@ -692,4 +692,33 @@ hipError_t launch_finish(const FinJob* j, int njob, int nblocks, int mode, hipSt
     return hipGetLastError();
 }
 
+
+// ---------------------------------------------------------------- measurement
+
+typedef uint32_t cp32x4 __attribute__((ext_vector_type(4)));
+
+// b = a over n 16-byte words: the plain streaming copy that measures the memory
+// system's read + write bandwidth.  Four independent 128-bit loads per thread are in
+// flight before their stores; both bypass the caches' retention (non-temporal).
+__global__ void __launch_bounds__(256) k_stream_copy(const cp32x4* __restrict__ a, cp32x4* __restrict__ b, long n) {
+    const long stride = (long)gridDim.x * 256;
+    for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += 4 * stride) {
+        cp32x4 v[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (i + k * stride < n) v[k] = __builtin_nontemporal_load(a + i + k * stride);
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (i + k * stride < n) __builtin_nontemporal_store(v[k], b + i + k * stride);
+    }
+}
+
+hipError_t launch_stream_copy(const void* a, void* b, long n16, hipStream_t s) {
+    long blocks = (n16 + 1023) / 1024;
+    if (blocks > 16384) blocks = 16384;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_stream_copy, dim3((unsigned)blocks), dim3(256), 0, s, (const cp32x4*)a, (cp32x4*)b, n16);
+    return hipGetLastError();
+}
+
 }  // namespace dlma

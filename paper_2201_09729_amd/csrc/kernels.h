@@ -109,5 +109,6 @@ template <int P> hipError_t launch_norm(const VecJob<P>* j, int njob, int nblock
 template <int P> hipError_t launch_fill_random(SF<P> f, int Vh, int nrhs, unsigned seed, hipStream_t s);
 template <int P> hipError_t launch_check_field(SF<P> f, int Vh, int nrhs, double* out, hipStream_t s);
 hipError_t launch_finish(const FinJob* j, int njob, int nblocks, int mode, hipStream_t s);
+hipError_t launch_stream_copy(const void* a, void* b, long n16, hipStream_t s);  // n16 16-byte words
 
 }  // namespace dlma

@@ -90,6 +90,7 @@ def load_library(path: str = LIB_PATH):
         "dlma_profile_reset": ([], I),
         "dlma_profile_read": ([I, P, P, P], I),
         "dlma_bench_schur": ([P, I, I, I, I, P, P, P], I),
+        "dlma_bench_copy": ([ctypes.c_long, I, P, P], I),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -427,3 +428,10 @@ class DiracSolve(torch.autograd.Function):
 def dirac_solve(b: torch.Tensor, m0: torch.Tensor, gauge: Gauge, opts: SolveOpts | None = None) -> torch.Tensor:
     """Differentiable solve; m0 is a 0-dim float64 tensor (bare mass, m0 = 1/(2 kappa) - 4)."""
     return DiracSolve.apply(b, m0, gauge, opts or default_opts())
+
+
+def dlma_bench_copy(nbytes: int = 1 << 31, reps: int = 10) -> float:
+    """Measured stream bandwidth in GB/s (read + write) of the library's copy kernel."""
+    ms = ctypes.c_double()
+    _check(load_library().dlma_bench_copy(int(nbytes), int(reps), ctypes.byref(ms), _stream()))
+    return 2.0 * nbytes / (ms.value * 1e-3) / 1e9

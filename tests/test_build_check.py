@@ -40,3 +40,28 @@ def test_built_objects_are_clean():
         pytest.skip("library not built here")
     for o in objs:
         assert build.check_object(o) == [], o
+
+
+def test_branch_targets_are_followed():
+    """A write at a branch target counts too (the branch is one wait state)."""
+    body = ("0000000000001000 <_ZN4dlma6kernelEv>:\n"
+            "\tbuffer_store_dwordx4 v[4:7], v1, s[12:15], 0 offen // 000000001000: E07C1000\n"
+            "\ts_branch 2 // 000000001008: BF820002 <_ZN4dlma6kernelEv+0x14>\n"
+            "\ts_nop 7 // 00000000100C: BF800007\n"
+            "\ts_nop 7 // 000000001010: BF800007\n"
+            "\tv_mov_b32_e32 v6, 0 // 000000001014: 7E0C0280\n")
+    assert len(build.store_data_hazards(body)) == 1
+    # the same write past two wait states on the taken path is clean
+    clean = body.replace("s_branch 2 // 000000001008", "s_nop 1 // 000000001008")
+    assert build.store_data_hazards(clean) == []
+    # one more instruction before the branch: two wait states, clean
+    two = body.replace("\ts_branch", "\ts_mov_b32 s0, 0 // 000000001004: BE800080\n\ts_branch")
+    two = two.replace("offen // 000000001000", "offen // 000000000FFC")
+    assert build.store_data_hazards(two) == []
+    # conditional branch: both the fall-through and the target path are scanned
+    cond = ("0000000000001000 <_ZN4dlma6kernelEv>:\n"
+            "\tbuffer_store_dwordx4 v[4:7], v1, s[12:15], 0 offen // 000000001000: E07C1000\n"
+            "\ts_cbranch_execz 1 // 000000001008: BF880001 <_ZN4dlma6kernelEv+0x10>\n"
+            "\ts_nop 7 // 00000000100C: BF800007\n"
+            "\tv_add_u32_e32 v7, 1, v7 // 000000001010: 680E0E81\n")
+    assert len(build.store_data_hazards(cond)) == 1

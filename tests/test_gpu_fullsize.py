@@ -130,6 +130,78 @@ def test_fp16_multi_rhs_16x32(D, orc):
     assert np.linalg.norm(got - want) / np.linalg.norm(want) < 1e-8
 
 
+def _tslice_group_norms(f, T):
+    """[groups][T]: 2-norm over timeslice t and the four spins of each group of 4 fields."""
+    n = (f.abs() ** 2).sum(dim=(2, 3, 4, 5, 6))
+    return torch.sqrt(n.reshape(-1, 4, T).sum(dim=1))
+
+
+def test_correlator_error_16x32_mixed_vs_fp64(D, orc):
+    """16^3 x 32, eps 0.25, kappa 0.121, c_sw 1.2 (seed 3): N = 32 modes on every
+    timeslice, 128 distillation + 32 eta + 32 (1 - box) eta right-hand sides, solved in
+    FP64 (to 1e-12), MIX_FP16 and MIX_BF16 (to 1e-10).  The FP64 solves are checked by
+    the oracle (true residuals of sampled right-hand sides and its own solve of one);
+    every correlator piece of eqs. (2)-(4) from the mixed solves is compared with the
+    same contraction of the FP64 solves per timeslice, against the bound
+      |dC(t)| <= (1/N_r) sum_r [|dY_r|_t |phi_r|_t + |Y_r|_t |dphi_r|_t + |dY_r|_t |dphi_r|_t]
+    (Y: the piece's source-side solution; d: mixed minus FP64; norms over timeslice t and
+    the four spins of a group; X_t has norm <= 1 and Gamma g5 one unit entry per row)."""
+    dims = (32, 16, 16, 16)
+    kappa, csw, nev, t0, nn = 0.121, 1.2, 32, 0, 8
+    T = dims[0]
+    U = synth.gauge_field(dims, 0.25, 3)
+    g = D.dlma_load_gauge(cu(U), kappa, csw)
+    Vall, ev = D.dlma_lap_eigs(g, nev, 0, T, cu(synth.gaussian_start(dims, T, 603)))
+    for t in (t0, 17):
+        check_modes(orc, U, t, Vall[t], ev[t], 1e-10)
+    eta = D.noise_sources(cu(synth.z2_noise(dims, t0, nn, 1003)), T, t0)
+    b = torch.cat([D.dist_sources(Vall[t0], T, t0), eta, D.dlma_project(g, t0, Vall[t0], eta, 1)])
+    del eta
+    nd, n4 = 4 * nev, 4 * nn
+    A = orc.clover(U, kappa, csw)
+    sol, C = {}, {}
+    for prec, tol in (("fp64", 1e-12), ("mix_fp16", TOL), ("mix_bf16", TOL)):
+        print("correlator error: solve", prec, flush=True)
+        (x,), st = D.dlma_solve([g], [b], opts=D.default_opts(tol=tol, prec=prec))
+        assert all(s["converged"] and s["relres"] <= tol for s in st), prec
+        slack = RES_SLACK if tol >= TOL else 1.01  # at 1e-12 the FP64 residual itself carries ~1e-3 rounding
+        for i in (0, nd - 1, nd, nd + n4):
+            assert oracle_relres(orc, U, A, x[i].cpu().numpy(), b[i].cpu().numpy()) <= tol * slack, (prec, i)
+        sol[prec] = x
+        C[prec] = D.dlma_correlators(g, t0, Vall, x[:nd], x[nd:nd + n4], x[nd + n4:])
+    # the oracle's own solve of one noise source against the FP64 GPU solution
+    want = orc.solve(U, A, b[nd:nd + 1].cpu().numpy(), tol=1e-12)[0][0]
+    got = sol["fp64"][nd].cpu().numpy()
+    assert np.linalg.norm(got - want) / np.linalg.norm(want) < 1e-9
+
+    def fields(x):
+        return {"dist": x[:nd], "phi": x[nd:nd + n4], "phibar": x[nd + n4:], "phiP": x[nd:nd + n4] - x[nd + n4:]}
+
+    parts = {"QQ_est": ("phi", "phibar", nn), "PQ_est": ("phi", "phibar", nn), "QP_est": ("phi", "phiP", nn),
+             "PP_est": ("phi", "phiP", nn), "11_est": ("phi", "phi", nn), "PP_exact": ("dist", "dist", 1),
+             "QP_exact": ("dist", "dist", 1)}
+    fr = fields(sol["fp64"])
+    nref = {k: _tslice_group_norms(v, T) for k, v in fr.items()}
+    for prec in ("mix_fp16", "mix_bf16"):
+        fm = fields(sol[prec])
+        nd_ = {k: _tslice_group_norms(fm[k] - fr[k], T) for k in fr}
+        for gname in ("PS", "V"):
+            split = sum(C[prec][gname][p] for p in ("QQ_est", "PQ_est", "QP_est", "PP_est"))
+            sc = np.max(np.abs(C[prec][gname]["11_est"]))
+            assert np.max(np.abs(split - C[prec][gname]["11_est"])) < 1e-12 * sc
+            for part, (xs, ys, ngrp) in parts.items():
+                c0 = np.asarray(C["fp64"][gname][part])
+                dc = np.abs(np.asarray(C[prec][gname][part]) - c0)
+                bound = ((nd_[ys] * nref[xs] + nref[ys] * nd_[xs] + nd_[ys] * nd_[xs]).sum(dim=0) / ngrp).cpu().numpy()
+                # the contraction's own rounding, on both sides, at the scale of the products
+                floor = 1e-13 * (nref[ys] * nref[xs]).sum(dim=0).cpu().numpy() / ngrp
+                rel = dc / np.abs(c0)
+                print("%s %s %-8s rel. error per timeslice: max %.2e, Delta 0/1/8/16: %s; |dC|/bound max %.3f"
+                      % (prec, gname, part, rel.max(), " ".join("%.1e" % rel[d] for d in (0, 1, 8, 16)),
+                         np.max(dc / (bound + floor))), flush=True)
+                assert np.all(dc <= bound + floor), (prec, gname, part)
+
+
 def test_uneven_batch_bf16(D, orc):
     """3 x 12^3x24 (seeds 1-3), 2 x 16^3x32 (seeds 4, 5), 1 x 24^3x48 (seed 6), kappa
     cycling 0.119, 0.120, 0.121, c_sw 1.2, eps 0.25; 64 right-hand sides each
@@ -181,21 +253,34 @@ def test_headline_launch_configuration(D, orc):
     b = torch.cat([D.dist_sources(V[0], T, t0), eta, D.dlma_project(g, t0, V[0], eta, 1)])
     del eta
     # one defect-correction pass brings every right-hand side to the inner tolerance's
-    # level (2e-3): a corrupted store in the solution update of some RHS shows as
-    # several times worse residuals there and extra passes.  CGNE's passes are uniform
-    # (1.4e-3 .. 3.6e-3 measured); BiCGStab's spread more (up to 1.1e-2 measured).
-    for solver, bound in ((0, 5e-3), (1, 3e-2)):
+    # level (2e-3).  A corrupted store in the solution update made the first right-hand
+    # side of every 2-RHS group about 15x worse than the others.  Measured spread of one
+    # pass, as max / median per source kind: CGNE 1.06 .. 1.15, BiCGStab 1.20 .. 1.77;
+    # first / second RHS of a group, median over groups: 0.98 .. 1.00.
+    A = orc.clover(U, kappa, csw)
+    kinds = {"distillation": slice(0, 4 * nev), "eta": slice(4 * nev, 4 * nev + 4 * nn),
+             "(1-box) eta": slice(4 * nev + 4 * nn, 4 * nev + 8 * nn)}
+    for solver, bound in ((0, 5e-3), (1, 1e-2)):
         opts1 = D.default_opts(tol=TOL, prec="mix_fp16", rhs_block=2, max_outer=1, inner_solver=solver)
-        _, st1 = D.dlma_solve([g], [b], opts=opts1, allow_notconv=True)
-        worst = max(s["relres"] for s in st1)
-        print("one pass, inner solver %d: worst relres %.3e" % (solver, worst), flush=True)
-        assert worst <= bound, (solver, worst)
+        (x1,), st1 = D.dlma_solve([g], [b], opts=opts1, allow_notconv=True)
+        r = np.array([s["relres"] for s in st1])
+        for name, sl in kinds.items():
+            med = np.median(r[sl])
+            print("one pass, inner solver %d, %s: median %.3e, max %.3e" % (solver, name, med, r[sl].max()), flush=True)
+            assert r[sl].max() <= 3.0 * med, (solver, name, r[sl].max(), med)
+        pair = np.median(r[0::2] / r[1::2])
+        assert 0.7 <= pair <= 1.4, (solver, pair)
+        assert r.max() <= bound, (solver, r.max())
+        # a capped solve still reports the full residual (both parities) of its last iterate
+        for i in (0, 4 * nev + 4 * nn):
+            ro = oracle_relres(orc, U, A, x1[i].cpu().numpy(), b[i].cpu().numpy())
+            assert abs(ro - r[i]) <= 1e-6 * ro, (solver, i, ro, r[i])
+        del x1
     opts = D.default_opts(tol=TOL, prec="mix_fp16", rhs_block=2)
     (x,), st = D.dlma_solve([g], [b], opts=opts)
     assert len(st) == 192
     assert all(s["converged"] and s["relres"] <= TOL for s in st)
     assert max(s["outer"] for s in st) <= 5, sorted(set(s["outer"] for s in st))
-    A = orc.clover(U, kappa, csw)
     for i in (0, 63, 127, 128, 159, 160, 191):
         assert oracle_relres(orc, U, A, x[i].cpu().numpy(), b[i].cpu().numpy()) <= TOL * RES_SLACK, i
     # the projected sources carry no component along V(t')
