@@ -498,3 +498,78 @@ def correlators(Vall, t0: int, phi_dist, phi, phibar, names=GAMMA_NAMES, ndil: i
         }
         out[name] = res
     return out
+
+
+def correlators_vjp(Vall, t0: int, phi_dist, phi, phibar, G, ndil: int = 1):
+    """Gradient of a real loss L through `correlators` (the backward of eqs. (3)-(4)'s
+    contractions): G[name][part] is dL/dRe C + i dL/dIm C for each piece ([T], indexed by
+    Delta = (t - t0) mod T; missing entries count as zero).  Returns (grad_phi_dist,
+    grad_phi, grad_phibar), shaped like the inputs, such that to first order
+    dL = Re sum_f <grad_f, d f>.
+
+    Every piece has the form  c / |Gamma list| sum_Gamma sum_grp sum_{s,s'} N_{s s'}
+    <A_{grp,s'}, M X_t B_{grp,s}>_t  with M = g5 Gamma, N = Gamma g5 (see `estimator`,
+    `c_dist_exact`, `c_qp_exact`: for C_dist, A = B = phi_dist and X = box, since
+    box(t') S^dag collapses to the distillation solutions).  Differentiating the
+    sesquilinear form term by term:
+        grad B_{grp,s}  += w(t) conj(N_{s s'}) X_t M^dag A_{grp,s'}
+        grad A_{grp,s'} += conj(w(t)) N_{s s'} M X_t B_{grp,s}
+    on timeslice t, with w(t) = G(t - t0) c / |Gamma list|."""
+    g = gammas()
+    g5 = g[4]
+    sh = phi_dist.shape[1:]
+    nd = phi_dist.shape[0] // 4
+    Ng = phi.shape[0] // 4 if phi is not None else 0
+    pd = phi_dist.reshape((nd, 4) + sh)
+    gd = np.zeros_like(pd)
+    if Ng:
+        p1 = phi.reshape((Ng, 4) + sh)
+        pq = phibar.reshape((Ng, 4) + sh)
+        pp = p1 - pq
+        g1 = np.zeros_like(p1)
+        gq = np.zeros_like(pq)
+        Nr = Ng // ndil
+    # piece: (A rows, B rows, X, normalisation, how grad A splits into (grad phi, grad phibar, grad dist))
+    pieces = {"PP_exact": ("dist", "dist", "P", 1.0), "QP_exact": ("dist", "dist", "Q", 1.0)}
+    if Ng:
+        pieces.update({"QQ_est": ("bar", "one", "Q", 1.0 / Nr), "PQ_est": ("bar", "one", "P", 1.0 / Nr),
+                       "QP_est": ("P", "one", "Q", 1.0 / Nr), "PP_est": ("P", "one", "P", 1.0 / Nr),
+                       "11_est": ("one", "one", "1", 1.0 / Nr)})
+    rows = {"dist": pd}
+    if Ng:
+        rows.update({"one": p1, "bar": pq, "P": pp})
+
+    def add_grad(kind, grp, s, v):
+        if kind == "dist":
+            gd[grp, s] += v
+        elif kind == "one":
+            g1[grp, s] += v
+        elif kind == "bar":
+            gq[grp, s] += v
+        else:  # phi - phibar
+            g1[grp, s] += v
+            gq[grp, s] -= v
+
+    for name, parts in G.items():
+        glist = _gamma_list(name, g)
+        for part, Gt in parts.items():
+            if part not in pieces:
+                continue
+            akind, bkind, X, c = pieces[part]
+            w = np.roll(np.asarray(Gt, dtype=np.complex128), t0) * c / len(glist)  # w[t] = G(t - t0) ...
+            wt = w[:, None, None, None, None, None]
+            A, B = rows[akind], rows[bkind]
+            for Gm in glist:
+                M = g5 @ Gm
+                N = Gm @ g5
+                for grp in range(A.shape[0]):
+                    for s in range(4):
+                        for sp in range(4):
+                            if N[s, sp] == 0:
+                                continue
+                            add_grad(bkind, grp, s, wt * np.conj(N[s, sp]) * _apply_X(X, Vall, _spin(np.conj(M.T), A[grp, sp])))
+                            add_grad(akind, grp, sp, np.conj(wt) * N[s, sp] * _spin(M, _apply_X(X, Vall, B[grp, s])))
+    out_d = gd.reshape(phi_dist.shape)
+    if not Ng:
+        return out_d, None, None
+    return out_d, g1.reshape(phi.shape), gq.reshape(phibar.shape)

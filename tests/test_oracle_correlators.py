@@ -188,3 +188,45 @@ def test_complex_z2_noise():
     assert set(np.unique(np.round(xi.imag * np.sqrt(2)))) == {-1.0, 1.0}
     # real Z2 draws are unchanged by the option
     assert np.array_equal(synth.z2_noise((4, 4, 4, 4), 0, 3, 9), np.sign(xi.real) * 1.0)
+
+
+@pytest.mark.parametrize("ndil", [1, 2])
+def test_correlator_vjp_is_the_derivative_of_the_contraction(orc, ndil):
+    """The backward of the contractions against the forward: every piece is a Hermitian
+    quadratic form in the solution fields u = (phi_dist, phi, phibar), so
+    [C(u + d) - C(u - d)] / 2 is its exact directional derivative.  For random weights G
+    and directions d, Re sum conj(G) [C(u + d) - C(u - d)] / 2 must equal
+    Re <grad, d> from correlators_vjp, to rounding.  Also with fewer distillation solution
+    groups than modes (the pieces are sums over source groups)."""
+    dims = (4, 4, 2, 4)
+    T = dims[0]
+    rng = np.random.default_rng(31)
+    nev, ndist, ng, t0 = 3, 2, 2 * ndil, 1
+    U = synth.gauge_field(dims, 0.3, 2)
+    Vall = np.stack([orc.lap_eigs(U, t, nev, synth.gaussian_start(dims, 1, 70 + t)[0], tol=1e-12)[1] for t in range(T)])
+
+    def rnd(n):
+        return rng.normal(size=(n,) + dims + (4, 3)) + 1j * rng.normal(size=(n,) + dims + (4, 3))
+
+    u = [rnd(4 * ndist), rnd(4 * ng), rnd(4 * ng)]
+    d = [rnd(4 * ndist), rnd(4 * ng), rnd(4 * ng)]
+    G = {name: {p: rng.normal(size=T) + 1j * rng.normal(size=T) for p in orc.PARTS} for name in ("PS", "V")}
+    cp = orc.correlators(Vall, t0, *[a + b for a, b in zip(u, d)], ndil=ndil)
+    cm = orc.correlators(Vall, t0, *[a - b for a, b in zip(u, d)], ndil=ndil)
+    lhs = sum(np.sum(np.conj(G[n][p]) * (cp[n][p] - cm[n][p]) / 2).real for n in G for p in orc.PARTS)
+    grads = orc.correlators_vjp(Vall, t0, *u, G, ndil=ndil)
+    rhs = sum(np.vdot(gf, df).real for gf, df in zip(grads, d))
+    assert abs(lhs - rhs) <= 1e-12 * (abs(lhs) + sum(np.abs(gf).sum() * np.abs(df).max() for gf, df in zip(grads, d))), (lhs, rhs)
+    # and piece by piece for one (Gamma, piece, Delta) at a time: the weights act where they should
+    for n, p, dl in (("PS", "PP_exact", 2), ("V", "QQ_est", 0), ("PS", "11_est", 3)):
+        G1 = {n: {p: np.eye(T)[dl]}}
+        g1 = orc.correlators_vjp(Vall, t0, *u, G1, ndil=ndil)
+        lhs1 = ((cp[n][p][dl] - cm[n][p][dl]) / 2).real
+        rhs1 = sum(np.vdot(gf, df).real for gf, df in zip(g1, d))
+        assert abs(lhs1 - rhs1) <= 1e-12 * max(1.0, abs(lhs1)) * 1e2, (n, p, lhs1, rhs1)
+        # the gradient lives on the sink timeslice t0 + Delta only
+        tt = (t0 + dl) % T
+        for gf in g1:
+            mask = np.ones(T, bool)
+            mask[tt] = False
+            assert np.max(np.abs(gf[:, mask])) == 0.0
