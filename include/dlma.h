@@ -268,7 +268,10 @@ int dlma_project_noalloc(dlma_gauge_t g, int t, int nev, const void* V_t, const 
  *   C_dist = sum_{k,l} tr[g5G tau_kl Gg5 tau_kl^dag], tau = <v_k(t) x e_s, phi_{l,s'}>_t,
  *   C_QP   = sum_l sum_{s,s'} (G g5)_{s s'} <phi_{l,s'}, g5 G Q_t phi_{l,s}>_t.
  *   V_all     device, [T][nev][Z][Y][X][3]: Laplacian modes of every timeslice
- *   phi_dist  device, [4 nev] spinors: solutions for v_k(t_src) x e_s, index k*4 + s
+ *   phi_dist  device, [4 ndist] spinors: solutions for v_l(t_src) x e_s, index l*4 + s
+ *   ndist     distillation source groups passed (0 .. any): normally nev; the pieces are
+ *             sums over source groups, so a caller may pass the groups in batches and
+ *             add the results (C_dist and C_QP exact over the groups passed)
  *   nnoise    spin-diluted noise source groups (4 spinors each) = N_r * ndil
  *   ndil      dilution components per noise vector: 1 (spin only), 2 (even-odd),
  *             3 (colour) or 6 (colour and even-odd); must divide nnoise
@@ -280,8 +283,27 @@ int dlma_project_noalloc(dlma_gauge_t g, int t, int nev, const void* V_t, const 
  *             6 QP_exact; time index Delta = (t - t_src) mod T.  Raw traces: no volume
  *             factor and no sign; nnoise = 0 leaves parts 0-4 zero.
  */
-int dlma_correlators(dlma_gauge_t g, int t_src, int nev, const void* V_all, const void* phi_dist,
+int dlma_correlators(dlma_gauge_t g, int t_src, int nev, const void* V_all, const void* phi_dist, int ndist,
                      int nnoise, int ndil, const void* phi, const void* phibar, double* C_out, void* stream);
+
+/*
+ * Backward of dlma_correlators (paper eq. 2-4, for gradients of correlators with
+ * respect to the solutions, and through the adjoint solves to the bare mass):
+ * given G = dL/dRe C + i dL/dIm C of a real loss L for every piece, with the layout
+ * of C_out (host, double[DLMA_NGAMMA][DLMA_NPARTS][T][2], time index Delta), writes
+ * the gradient fields such that dL = Re sum_f <grad_f, d f> to first order.  Each
+ * piece c sum <A_{s'}, g5 G X_t B_s> N_{s s'} contributes
+ *   grad B_s += w conj(N_{s s'}) X_t (g5 G)^dag A_{s'},  grad A_{s'} += conj(w) N_{s s'} g5 G X_t B_s
+ * on timeslice t = t_src + Delta, w = G c.  All other arguments as dlma_correlators.
+ *   grad_dist, grad_phi, grad_phibar  device, shaped like phi_dist, phi, phibar;
+ *              overwritten on every timeslice (zero where G has no weight); must not
+ *              overlap the inputs
+ * Synchronises the stream.  Errors: DLMA_EINVAL (as dlma_correlators; non-finite G;
+ * 2 nnoise + ndist > 65535), DLMA_ENOMEM, DLMA_EHIP.
+ */
+int dlma_correlators_grad(dlma_gauge_t g, int t_src, int nev, const void* V_all, const void* phi_dist, int ndist,
+                          int nnoise, int ndil, const void* phi, const void* phibar, const double* G,
+                          void* grad_dist, void* grad_phi, void* grad_phibar, void* stream);
 
 /*
  * out = <a, b> = sum_i conj(a_i) b_i over n complex128 numbers (FP64, fixed

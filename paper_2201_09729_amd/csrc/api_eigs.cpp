@@ -884,20 +884,21 @@ std::vector<Gam> gammas() {
 
 }  // namespace
 
-extern "C" int dlma_correlators(dlma_gauge_t h, int t_src, int nev, const void* V_all, const void* phi_dist, int nnoise,
-                                int ndil, const void* phi, const void* phibar, double* C_out, void* stream) {
+extern "C" int dlma_correlators(dlma_gauge_t h, int t_src, int nev, const void* V_all, const void* phi_dist, int ndist,
+                                int nnoise, int ndil, const void* phi, const void* phibar, double* C_out, void* stream) {
     Gauge* g = (Gauge*)h;
     if (!g) return fail(DLMA_EINVAL, "NULL handle");
     const int T = g->dims[0];
     if (t_src < 0 || t_src >= T) return fail(DLMA_EINVAL, "t_src out of range");
-    if (nev < 1 || nnoise < 0) return fail(DLMA_EINVAL, "nev must be >= 1 and nnoise >= 0");
+    if (nev < 1 || nnoise < 0 || ndist < 0) return fail(DLMA_EINVAL, "nev must be >= 1, ndist and nnoise >= 0");
     if (ndil < 1 || nnoise % ndil != 0) return fail(DLMA_EINVAL, "ndil must be >= 1 and divide nnoise");
     const double nvec = nnoise > 0 ? (double)(nnoise / ndil) : 1.0;  // independent noise vectors
-    if (!V_all || !phi_dist || !C_out || (nnoise > 0 && (!phi || !phibar))) return fail(DLMA_EINVAL, "NULL pointer");
+    if (!V_all || !C_out || (ndist > 0 && !phi_dist) || (nnoise > 0 && (!phi || !phibar)))
+        return fail(DLMA_EINVAL, "NULL pointer");
     hipStream_t s = S(stream);
     const long V = g->V;
     const long fs = V * 12;  // complex numbers per spinor field
-    const int nd = 4 * nev, nn = 4 * nnoise;
+    const int nd = 4 * ndist, nn = 4 * nnoise;
     // fields: dist solutions, then phi, then phibar
     std::vector<const double2*> fields;
     for (int i = 0; i < nd; ++i) fields.push_back((const double2*)phi_dist + i * fs);
@@ -906,7 +907,7 @@ extern "C" int dlma_correlators(dlma_gauge_t h, int t_src, int nev, const void* 
     const int nf = (int)fields.size();
     // Gram pairs: dist (phi_{l,s'}, phi_{l,s}); noise (phi_{r,s'}, phi_{r,s}) and (phibar_{r,s'}, phi_{r,s})
     std::vector<const double2*> pa, pb;
-    for (int l = 0; l < nev; ++l)
+    for (int l = 0; l < ndist; ++l)
         for (int sp = 0; sp < 4; ++sp)
             for (int sq = 0; sq < 4; ++sq) { pa.push_back(fields[l * 4 + sp]); pb.push_back(fields[l * 4 + sq]); }
     for (int r = 0; r < nnoise; ++r)
@@ -918,9 +919,9 @@ extern "C" int dlma_correlators(dlma_gauge_t h, int t_src, int nev, const void* 
                 }
     const int np = (int)pa.size();
     Buf dF, dA, dB, dP, dG;
-    DLMA_TRY(dF.allocate(sizeof(void*) * nf));
-    DLMA_TRY(dA.allocate(sizeof(void*) * np));
-    DLMA_TRY(dB.allocate(sizeof(void*) * np));
+    DLMA_TRY(dF.allocate(sizeof(void*) * std::max(1, nf)));
+    DLMA_TRY(dA.allocate(sizeof(void*) * std::max(1, np)));
+    DLMA_TRY(dB.allocate(sizeof(void*) * std::max(1, np)));
     DLMA_TRY(dP.allocate(sizeof(double2) * (size_t)nf * T * nev * 4));
     DLMA_TRY(dG.allocate(sizeof(double2) * (size_t)np * T * 16));
     DLMA_HIP(hipMemcpyAsync(dF.p, fields.data(), sizeof(void*) * nf, hipMemcpyHostToDevice, s));
@@ -972,8 +973,8 @@ extern "C" int dlma_correlators(dlma_gauge_t h, int t_src, int nev, const void* 
                             for (int s2 = 0; s2 < 4; ++s2) {  // s': spin of phiY_{r,s'}
                                 cplx nc = N.m[s1][s2];
                                 if (nc == 0.0) continue;
-                                int p1 = nev * 16 + (r * 2 + 0) * 16 + s2 * 4 + s1;  // (phi_{r,s'}, phi_{r,s})
-                                int pQ = nev * 16 + (r * 2 + 1) * 16 + s2 * 4 + s1;  // (phibar_{r,s'}, phi_{r,s})
+                                int p1 = ndist * 16 + (r * 2 + 0) * 16 + s2 * 4 + s1;  // (phi_{r,s'}, phi_{r,s})
+                                int pQ = ndist * 16 + (r * 2 + 1) * 16 + s2 * 4 + s1;  // (phibar_{r,s'}, phi_{r,s})
                                 int fB = nd + r * 4 + s1;
                                 int fA1 = nd + r * 4 + s2, fAQ = nd + nn + r * 4 + s2;
                                 cplx g1 = mg(p1), gQ = mg(pQ);
@@ -997,7 +998,7 @@ extern "C" int dlma_correlators(dlma_gauge_t h, int t_src, int nev, const void* 
                 // exact C_dist from the perambulator tau_{(k s),(l s')} = P[l*4+s'][t][k][s]
                 cplx cd = 0;
                 for (int k = 0; k < nev; ++k)
-                    for (int l = 0; l < nev; ++l)
+                    for (int l = 0; l < ndist; ++l)
                         for (int s1 = 0; s1 < 4; ++s1)
                             for (int s2 = 0; s2 < 4; ++s2) {
                                 if (M.m[s1][s2] == 0.0) continue;
@@ -1010,7 +1011,7 @@ extern "C" int dlma_correlators(dlma_gauge_t h, int t_src, int nev, const void* 
                 acc[5 * T + d] += cd;
                 // exact C_QP from the distillation solutions
                 cplx cq = 0;
-                for (int l = 0; l < nev; ++l)
+                for (int l = 0; l < ndist; ++l)
                     for (int s1 = 0; s1 < 4; ++s1)
                         for (int s2 = 0; s2 < 4; ++s2) {
                             cplx nc = N.m[s1][s2];
@@ -1028,5 +1029,170 @@ extern "C" int dlma_correlators(dlma_gauge_t h, int t_src, int nev, const void* 
                 C_out[(((size_t)gi * DLMA_NPARTS + part) * T + d) * 2 + 1] = v.imag();
             }
     }
+    return DLMA_OK;
+}
+
+// Backward of dlma_correlators.  Each piece is
+//   c / |Gamma list| sum_Gamma sum_grp sum_{s,s'} N_{s s'} <A_{grp,s'}, M X_t B_{grp,s}>_t,
+// M = g5 Gamma, N = Gamma g5, X in {1, box, 1 - box}, so a real loss with weights G on
+// the pieces (dL/dRe C + i dL/dIm C) has the gradient fields
+//   grad B_{grp,s}  += w(t) conj(N_{s s'}) X_t M^dag A_{grp,s'},
+//   grad A_{grp,s'} += conj(w(t)) N_{s s'} M X_t B_{grp,s},     w = G c / |Gamma list|.
+// The host folds every piece, Gamma and sign into two matrices per timeslice over the
+// (field, spin) components of one source group, W1 (X = 1 parts) and WP (box parts;
+// 1 - box splits into both), shared by all groups; the kernel forms W1 F + box(t) WP F
+// with box(t) WP F = sum_k v_k(t) (WP V(t)^dag F)_k.
+extern "C" int dlma_correlators_grad(dlma_gauge_t h, int t_src, int nev, const void* V_all, const void* phi_dist, int ndist,
+                                     int nnoise, int ndil, const void* phi, const void* phibar, const double* G_in,
+                                     void* grad_dist, void* grad_phi, void* grad_phibar, void* stream) {
+    Gauge* g = (Gauge*)h;
+    if (!g) return fail(DLMA_EINVAL, "NULL handle");
+    const int T = g->dims[0];
+    if (t_src < 0 || t_src >= T) return fail(DLMA_EINVAL, "t_src out of range");
+    if (nev < 1 || nnoise < 0 || ndist < 0) return fail(DLMA_EINVAL, "nev must be >= 1, ndist and nnoise >= 0");
+    if (ndil < 1 || nnoise % ndil != 0) return fail(DLMA_EINVAL, "ndil must be >= 1 and divide nnoise");
+    if (2L * nnoise + ndist > 65535) return fail(DLMA_EINVAL, "2 nnoise + ndist must be below 65536");
+    if (!V_all || !G_in || (ndist > 0 && (!phi_dist || !grad_dist)) || (nnoise > 0 && (!phi || !phibar || !grad_phi || !grad_phibar)))
+        return fail(DLMA_EINVAL, "NULL pointer");
+    if (ndist == 0 && nnoise == 0) return DLMA_OK;
+    hipStream_t s = S(stream);
+    const long L3 = (long)g->dims[1] * g->dims[2] * g->dims[3];
+    const long fs = g->V * 12;
+    const int nd = 4 * ndist, nn = 4 * nnoise, nf = nd + 2 * nn;
+    const double nvec = nnoise > 0 ? (double)(nnoise / ndil) : 1.0;
+
+    // weight matrices per timeslice: noise [T][32][32] over (phi_s, phibar_s) x spin, dist [T][16][16]
+    std::vector<cplx> W1n((size_t)T * 1024, 0.0), WPn((size_t)T * 1024, 0.0), W1d((size_t)T * 256, 0.0), WPd((size_t)T * 256, 0.0);
+    std::vector<int> tact(T, -1);
+    std::vector<Gam> ga = gammas();
+    const Gam g5 = ga[4];
+    // piece -> X (0: 1, 1: box, 2: 1 - box), source-side field A (0: phibar, 1: phi - phibar, 2: phi, 3: dist)
+    const int PX[DLMA_NPARTS] = {2, 1, 2, 1, 0, 1, 2};
+    const int PA[DLMA_NPARTS] = {0, 0, 1, 1, 2, 3, 3};
+    auto addw = [&](bool dist, int t, int row, int col, cplx v, int X) {
+        std::vector<cplx>& W1 = dist ? W1d : W1n;
+        std::vector<cplx>& WP = dist ? WPd : WPn;
+        const int n = dist ? 16 : 32;
+        const size_t i = ((size_t)t * n + row) * n + col;
+        if (X != 1) W1[i] += v;       // X = 1 or 1 - box
+        if (X == 1) WP[i] += v;       // box
+        if (X == 2) WP[i] -= v;       // the box part of 1 - box
+    };
+    for (int gi = 0; gi < DLMA_NGAMMA; ++gi) {
+        std::vector<Gam> Gs;
+        if (gi == 0) Gs.push_back(g5);
+        else Gs = {ga[1], ga[2], ga[3]};
+        for (int part = 0; part < DLMA_NPARTS; ++part) {
+            const bool dist = PA[part] == 3;
+            if (dist ? ndist == 0 : nnoise == 0) continue;
+            const double c = (dist ? 1.0 : 1.0 / nvec) / (double)Gs.size();
+            for (int d = 0; d < T; ++d) {
+                const double* gp = G_in + (((size_t)gi * DLMA_NPARTS + part) * T + d) * 2;
+                const cplx w = cplx(gp[0], gp[1]) * c;
+                if (w == 0.0) continue;
+                if (!std::isfinite(w.real()) || !std::isfinite(w.imag())) return fail(DLMA_EINVAL, "non-finite weight");
+                const int t = (t_src + d) % T;
+                tact[t] = 0;
+                const int X = PX[part];
+                for (const Gam& Gm : Gs) {
+                    const Gam M = gmul(g5, Gm), N = gmul(Gm, g5);
+                    for (int sg = 0; sg < 4; ++sg)       // s: spin label of B (sink solution)
+                        for (int sq = 0; sq < 4; ++sq) {  // s': spin label of A (source-side solution)
+                            const cplx nss = N.m[sg][sq];
+                            if (nss == 0.0) continue;
+                            // A as input columns / output rows: (field index in the group, coefficient)
+                            int aj[2];
+                            double ac[2];
+                            int na = 0;
+                            if (dist) { aj[na] = sq; ac[na++] = 1.0; }
+                            else if (PA[part] == 0) { aj[na] = 4 + sq; ac[na++] = 1.0; }
+                            else if (PA[part] == 1) { aj[na] = sq; ac[na++] = 1.0; aj[na] = 4 + sq; ac[na++] = -1.0; }
+                            else { aj[na] = sq; ac[na++] = 1.0; }
+                            const cplx cb = w * std::conj(nss);  // grad B_s += cb X M^dag A_s'
+                            const cplx ca = std::conj(w) * nss;  // grad A_s' += ca M X B_s
+                            for (int a = 0; a < 4; ++a)
+                                for (int b = 0; b < 4; ++b) {
+                                    const cplx mdag = std::conj(M.m[b][a]), m = M.m[a][b];
+                                    for (int q = 0; q < na; ++q) {
+                                        if (mdag != 0.0) addw(dist, t, sg * 4 + a, aj[q] * 4 + b, cb * ac[q] * mdag, X);
+                                        if (m != 0.0) addw(dist, t, aj[q] * 4 + a, sg * 4 + b, ca * ac[q] * m, X);
+                                    }
+                                }
+                        }
+                }
+            }
+        }
+    }
+    int nact = 0;
+    for (int t = 0; t < T; ++t)
+        if (tact[t] >= 0) tact[t] = nact++;
+    // projections of every input field on the modes of every timeslice: P[f][t][k][s]
+    std::vector<const double2*> fields;
+    for (int i = 0; i < nd; ++i) fields.push_back((const double2*)phi_dist + i * fs);
+    for (int i = 0; i < nn; ++i) fields.push_back((const double2*)phi + i * fs);
+    for (int i = 0; i < nn; ++i) fields.push_back((const double2*)phibar + i * fs);
+    Buf dF, dP, dW1n, dW1d, dTn, dTd, dTact;
+    std::vector<cplx> P;
+    if (nact > 0) {
+        DLMA_TRY(dF.allocate(sizeof(void*) * nf));
+        DLMA_TRY(dP.allocate(sizeof(double2) * (size_t)nf * T * nev * 4));
+        DLMA_HIP(hipMemcpyAsync(dF.p, fields.data(), sizeof(void*) * nf, hipMemcpyHostToDevice, s));
+        DLMA_HIP(launch_tproj((const double2*)V_all, (const double2* const*)dF.p, nf, g->geo, nev, dP.as<double2>(), s));
+        P.resize((size_t)nf * T * nev * 4);
+        DLMA_HIP(hipMemcpyAsync(P.data(), dP.p, sizeof(double2) * P.size(), hipMemcpyDeviceToHost, s));
+        DLMA_HIP(hipStreamSynchronize(s));
+    }
+    // tau' = WP(t) tau for every group and weighted timeslice
+    std::vector<cplx> taun((size_t)std::max(1, nnoise) * std::max(1, nact) * nev * 32, 0.0);
+    std::vector<cplx> taud((size_t)std::max(1, ndist) * std::max(1, nact) * nev * 16, 0.0);
+    auto Pf = [&](int f, int t, int k, int sp) { return P[(((size_t)f * T + t) * nev + k) * 4 + sp]; };
+    for (int t = 0; t < T; ++t) {
+        const int ta = tact[t];
+        if (ta < 0) continue;
+        for (int r = 0; r < nnoise; ++r)
+            for (int k = 0; k < nev; ++k)
+                for (int row = 0; row < 32; ++row) {
+                    cplx v = 0;
+                    for (int col = 0; col < 32; ++col) {
+                        const cplx wv = WPn[((size_t)t * 32 + row) * 32 + col];
+                        if (wv == 0.0) continue;
+                        const int j = col >> 2, b = col & 3;
+                        const int f = j < 4 ? nd + r * 4 + j : nd + nn + r * 4 + (j - 4);
+                        v += wv * Pf(f, t, k, b);
+                    }
+                    taun[(((size_t)r * nact + ta) * nev + k) * 32 + row] = v;
+                }
+        for (int l = 0; l < ndist; ++l)
+            for (int k = 0; k < nev; ++k)
+                for (int row = 0; row < 16; ++row) {
+                    cplx v = 0;
+                    for (int col = 0; col < 16; ++col) {
+                        const cplx wv = WPd[((size_t)t * 16 + row) * 16 + col];
+                        if (wv == 0.0) continue;
+                        v += wv * Pf(l * 4 + (col >> 2), t, k, col & 3);
+                    }
+                    taud[(((size_t)l * nact + ta) * nev + k) * 16 + row] = v;
+                }
+    }
+    DLMA_TRY(dW1n.allocate(sizeof(double2) * W1n.size()));
+    DLMA_TRY(dW1d.allocate(sizeof(double2) * W1d.size()));
+    DLMA_TRY(dTn.allocate(sizeof(double2) * taun.size()));
+    DLMA_TRY(dTd.allocate(sizeof(double2) * taud.size()));
+    DLMA_TRY(dTact.allocate(sizeof(int) * T));
+    DLMA_HIP(hipMemcpyAsync(dW1n.p, W1n.data(), sizeof(double2) * W1n.size(), hipMemcpyHostToDevice, s));
+    DLMA_HIP(hipMemcpyAsync(dW1d.p, W1d.data(), sizeof(double2) * W1d.size(), hipMemcpyHostToDevice, s));
+    DLMA_HIP(hipMemcpyAsync(dTn.p, taun.data(), sizeof(double2) * taun.size(), hipMemcpyHostToDevice, s));
+    DLMA_HIP(hipMemcpyAsync(dTd.p, taud.data(), sizeof(double2) * taud.size(), hipMemcpyHostToDevice, s));
+    DLMA_HIP(hipMemcpyAsync(dTact.p, tact.data(), sizeof(int) * T, hipMemcpyHostToDevice, s));
+    CorrGradArgs a = {};
+    a.Vall = (const double2*)V_all;
+    a.dist = (const double2*)phi_dist; a.phi = (const double2*)phi; a.phibar = (const double2*)phibar;
+    a.gdist = (double2*)grad_dist; a.gphi = (double2*)grad_phi; a.gphibar = (double2*)grad_phibar;
+    a.W1n = dW1n.as<double2>(); a.W1d = dW1d.as<double2>();
+    a.taun = dTn.as<double2>(); a.taud = dTd.as<double2>();
+    a.tact = dTact.as<int>();
+    a.L3 = L3; a.fs = fs; a.nev = nev; a.ndist = ndist; a.nnoise = nnoise; a.nact = std::max(1, nact);
+    DLMA_HIP(launch_corr_grad(a, T, s));
+    DLMA_HIP(hipStreamSynchronize(s));  // the host tables are released on return
     return DLMA_OK;
 }

@@ -91,4 +91,95 @@ hipError_t launch_spin_gram(const double2* const* A, const double2* const* B, in
     return hipGetLastError();
 }
 
+
+// ---------------------------------------------------------------- backward of the contractions
+//
+// Every correlator piece is a sesquilinear form sum <A, M X_t B>_t in the solution
+// fields of one source group (four spin-diluted solutions, plus their (1 - box)
+// partners for noise).  Its gradient field on timeslice t is therefore
+//   grad(t, x) = W1(t) F(t, x) + WP(t) (box(t) F)(t, x),
+// with F the group's input fields stacked with their spin components, W1 and WP spin
+// matrices that combine the loss weights, Gamma, g5 and the normalisations (the same
+// for every group), and box(t) F = sum_k v_k(t) tau_k, tau = V(t)^dag F.  The host
+// folds WP into tau' = WP tau; this kernel forms W1 F + sum_k v_k tau'_k for one
+// output chunk (four output fields of one group) at 256 rows (site, colour) of one
+// timeslice per block.  W1 rows and tau' of the chunk are staged in LDS.
+__global__ void __launch_bounds__(256) k_corr_grad(CorrGradArgs a) {
+    __shared__ double2 w1s[16 * 32];  // W1 rows of the chunk's 16 outputs, over <= 32 inputs
+    __shared__ double2 tps[64 * 16];  // tau'[k][16 outputs] for 64 modes at a time
+    const int t = blockIdx.y, z = blockIdx.z;
+    const bool noise = z < 2 * a.nnoise;
+    const int grp = noise ? z >> 1 : z - 2 * a.nnoise;
+    const int half = noise ? (z & 1) : 0;
+    const int nin = noise ? 32 : 16;  // input (field, spin) columns of a group
+    const int ta = a.tact[t];         // uniform: the block's timeslice carries weights or not
+    const long L3 = a.L3;
+    const long row = (long)blockIdx.x * 256 + threadIdx.x;
+    const bool valid = row < L3 * 3;
+    const long x = valid ? row / 3 : 0;
+    const int c = (int)(valid ? row - x * 3 : 0);
+    const long site = ((long)t * L3 + x) * 12 + c;  // offset of (spin 0, colour c) in a field
+    double2 acc[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) acc[q] = make_double2(0.0, 0.0);
+    if (ta >= 0) {
+        const double2* W1 = noise ? a.W1n + ((long)t * 32 + half * 16) * 32 : a.W1d + (long)t * 16 * 16;
+        for (int i = threadIdx.x; i < 16 * nin; i += 256) w1s[i] = W1[i];
+        __syncthreads();
+        if (valid) {
+            for (int j = 0; j < nin / 4; ++j) {
+                const double2* f = noise ? (j < 4 ? a.phi + ((long)grp * 4 + j) * a.fs : a.phibar + ((long)grp * 4 + j - 4) * a.fs)
+                                         : a.dist + ((long)grp * 4 + j) * a.fs;
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const double2 v = f[site + b * 3];
+                    const int col = j * 4 + b;
+#pragma unroll
+                    for (int q = 0; q < 16; ++q) {
+                        const double2 w = w1s[q * nin + col];
+                        acc[q].x += w.x * v.x - w.y * v.y;
+                        acc[q].y += w.x * v.y + w.y * v.x;
+                    }
+                }
+            }
+        }
+        const double2* tp = noise ? a.taun + (((long)grp * a.nact + ta) * a.nev) * 32 + half * 16
+                                  : a.taud + (((long)grp * a.nact + ta) * a.nev) * 16;
+        const int tstride = noise ? 32 : 16;
+        const double2* vk = a.Vall + (long)t * a.nev * L3 * 3 + (valid ? row : 0);
+        for (int k0 = 0; k0 < a.nev; k0 += 64) {
+            const int nk = a.nev - k0 < 64 ? a.nev - k0 : 64;
+            __syncthreads();  // the previous chunk (or W1) has been read by every thread
+            for (int i = threadIdx.x; i < nk * 16; i += 256) tps[i] = tp[(long)(k0 + (i >> 4)) * tstride + (i & 15)];
+            __syncthreads();
+            if (valid) {
+                for (int k = 0; k < nk; ++k) {
+                    const double2 v = vk[(long)(k0 + k) * L3 * 3];
+#pragma unroll
+                    for (int q = 0; q < 16; ++q) {
+                        const double2 w = tps[k * 16 + q];
+                        acc[q].x += w.x * v.x - w.y * v.y;
+                        acc[q].y += w.x * v.y + w.y * v.x;
+                    }
+                }
+            }
+        }
+    }
+    if (!valid) return;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        double2* o = noise ? (half == 0 ? a.gphi : a.gphibar) + ((long)grp * 4 + i) * a.fs : a.gdist + ((long)grp * 4 + i) * a.fs;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) o[site + s * 3] = acc[i * 4 + s];
+    }
+}
+
+hipError_t launch_corr_grad(const CorrGradArgs& a, int T, hipStream_t s) {
+    const int nchunk = 2 * a.nnoise + a.ndist;  // grid z: the callers keep it below 65536
+    if (nchunk <= 0) return hipSuccess;
+    if (nchunk > 65535) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_corr_grad, dim3((unsigned)((a.L3 * 3 + 255) / 256), T, nchunk), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
 }  // namespace dlma

@@ -52,6 +52,20 @@ hipError_t launch_project(const double2* Vt, const double2* in, double2* out, co
 // contractions
 hipError_t launch_tproj(const double2* Vall, const double2* const* fields, int nf, const Geo& g, int nev, double2* P,
                         hipStream_t s);
+// backward of the correlator contractions (see contract.hip)
+struct CorrGradArgs {
+    const double2* Vall;                       // [T][nev][L3][3]
+    const double2 *dist, *phi, *phibar;        // input fields, canonical, fs complex numbers each
+    double2 *gdist, *gphi, *gphibar;           // gradient fields (written on every timeslice)
+    const double2* W1n;                        // [T][32][32]: noise groups, (phi, phibar) x spin
+    const double2* W1d;                        // [T][16][16]: distillation groups, phi_dist x spin
+    const double2* taun;                       // [nnoise][nact][nev][32]: WP(t) V(t)^dag F, noise groups
+    const double2* taud;                       // [ndist][nact][nev][16]
+    const int* tact;                           // [T]: index among the weighted timeslices, or -1
+    long L3, fs;
+    int nev, ndist, nnoise, nact;
+};
+hipError_t launch_corr_grad(const CorrGradArgs& a, int T, hipStream_t s);
 hipError_t launch_spin_gram(const double2* const* A, const double2* const* B, int npair, const Geo& g, double2* G,
                             hipStream_t s);
 

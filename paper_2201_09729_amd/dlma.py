@@ -84,7 +84,8 @@ def load_library(path: str = LIB_PATH):
         "dlma_lap_eigs": ([P, I, I, I, P, P, P, P, P], I),
         "dlma_project": ([P, I, I, P, P, P, I, I, P], I),
         "dlma_project_noalloc": ([P, I, I, P, P, P, I, I, P], I),
-        "dlma_correlators": ([P, I, I, P, P, I, I, P, P, P, P], I),
+        "dlma_correlators": ([P, I, I, P, P, I, I, I, P, P, P, P], I),
+        "dlma_correlators_grad": ([P, I, I, P, P, I, I, I, P, P, P, P, P, P, P], I),
         "dlma_dot": ([P, P, ctypes.c_long, P, P], I),
         "dlma_profile_enable": ([I], I),
         "dlma_profile_reset": ([], I),
@@ -268,30 +269,91 @@ def dlma_project_noalloc(g: Gauge, t: int, Vt: torch.Tensor, x: torch.Tensor, mo
     return out
 
 
-def dlma_correlators(g: Gauge, t_src: int, Vall: torch.Tensor, phi_dist: torch.Tensor,
-                     phi: torch.Tensor | None = None, phibar: torch.Tensor | None = None, ndil: int = 1):
-    """Returns {gamma: {part: complex numpy [T]}} (see dlma.h for the parts).
-
-    phi, phibar: solutions for the sources of noise_sources (ndil = dilution_size of its scheme)."""
-    import numpy as np
+def _corr_args(Vall, phi_dist, phi, phibar):
     Vall = _dev(Vall)
-    phi_dist = _dev(phi_dist)
-    nev = int(Vall.shape[1])
-    T = g.dims[0]
+    phi_dist = _dev(phi_dist) if phi_dist is not None else None
+    nd = int(phi_dist.shape[0]) // 4 if phi_dist is not None else 0
     nn = 0
-    pp = pb = ctypes.c_void_p(0)
+    pp = pb = pd = ctypes.c_void_p(0)
+    if phi_dist is not None:
+        pd = ctypes.c_void_p(phi_dist.data_ptr())
     if phi is not None:
         phi = _dev(phi)
         phibar = _dev(phibar)
         nn = int(phi.shape[0]) // 4
         pp = ctypes.c_void_p(phi.data_ptr())
         pb = ctypes.c_void_p(phibar.data_ptr())
-    C = np.zeros((2, NPARTS, T, 2), dtype=np.float64)
-    _check(load_library().dlma_correlators(g.h, int(t_src), nev, ctypes.c_void_p(Vall.data_ptr()),
-                                           ctypes.c_void_p(phi_dist.data_ptr()), nn, int(ndil), pp, pb,
-                                           C.ctypes.data_as(ctypes.c_void_p), _stream()))
+    return Vall, phi_dist, phi, phibar, nd, nn, pd, pp, pb
+
+
+def dlma_correlators(g: Gauge, t_src: int, Vall: torch.Tensor, phi_dist: torch.Tensor,
+                     phi: torch.Tensor | None = None, phibar: torch.Tensor | None = None, ndil: int = 1):
+    """Returns {gamma: {part: complex numpy [T]}} (see dlma.h for the parts).
+
+    phi_dist: solutions for the distillation sources (any number of 4-spin groups);
+    phi, phibar: solutions for the sources of noise_sources (ndil = dilution_size of its scheme)."""
+    C = dlma_correlators_array(g, t_src, Vall, phi_dist, phi, phibar, ndil)
     Cc = C[..., 0] + 1j * C[..., 1]
     return {GAMMA_NAMES[gi]: {PART_NAMES[p]: Cc[gi, p] for p in range(NPARTS)} for gi in range(2)}
+
+
+def dlma_correlators_array(g: Gauge, t_src: int, Vall, phi_dist, phi=None, phibar=None, ndil: int = 1):
+    """dlma_correlators as the raw host array double[2][NPARTS][T][2] (re, im)."""
+    import numpy as np
+    Vall, phi_dist, phi, phibar, nd, nn, pd, pp, pb = _corr_args(Vall, phi_dist, phi, phibar)
+    C = np.zeros((2, NPARTS, g.dims[0], 2), dtype=np.float64)
+    _check(load_library().dlma_correlators(g.h, int(t_src), int(Vall.shape[1]), ctypes.c_void_p(Vall.data_ptr()),
+                                           pd, nd, nn, int(ndil), pp, pb, C.ctypes.data_as(ctypes.c_void_p), _stream()))
+    return C
+
+
+def dlma_correlators_grad(g: Gauge, t_src: int, Vall, phi_dist, phi, phibar, G, ndil: int = 1):
+    """Gradient fields (grad_dist, grad_phi, grad_phibar) of a real loss whose gradient with
+    respect to the correlator pieces is G (host double [2][NPARTS][T][2], dL/dRe C + i dL/dIm C)."""
+    import numpy as np
+    Vall, phi_dist, phi, phibar, nd, nn, pd, pp, pb = _corr_args(Vall, phi_dist, phi, phibar)
+    G = np.ascontiguousarray(G, dtype=np.float64)
+    if G.shape != (2, NPARTS, g.dims[0], 2):
+        raise ValueError("G must be [2][%d][T][2]" % NPARTS)
+    gd = torch.empty_like(phi_dist) if phi_dist is not None else None
+    g1 = torch.empty_like(phi) if phi is not None else None
+    gq = torch.empty_like(phibar) if phibar is not None else None
+    ptr = lambda t: ctypes.c_void_p(t.data_ptr() if t is not None else 0)  # noqa: E731
+    _check(load_library().dlma_correlators_grad(g.h, int(t_src), int(Vall.shape[1]), ctypes.c_void_p(Vall.data_ptr()),
+                                                pd, nd, nn, int(ndil), pp, pb, G.ctypes.data_as(ctypes.c_void_p),
+                                                ptr(gd), ptr(g1), ptr(gq), _stream()))
+    return gd, g1, gq
+
+
+class Correlators(torch.autograd.Function):
+    """C = the correlator pieces of dlma_correlators as a complex128 CPU tensor
+    [2 (PS, V)][NPARTS][T] (time index Delta), differentiable in the solution fields:
+    the backward is dlma_correlators_grad, the hand-written adjoint of the contractions."""
+
+    @staticmethod
+    def forward(ctx, phi_dist, phi, phibar, gauge, t_src, Vall, ndil):
+        import numpy as np
+        det = lambda t: t.detach() if t is not None else None  # noqa: E731
+        C = dlma_correlators_array(gauge, t_src, Vall, det(phi_dist), det(phi), det(phibar), ndil)
+        ctx.save_for_backward(phi_dist, phi, phibar)
+        ctx.gauge, ctx.t_src, ctx.Vall, ctx.ndil = gauge, t_src, Vall, ndil
+        return torch.from_numpy(np.ascontiguousarray(C[..., 0] + 1j * C[..., 1]))
+
+    @staticmethod
+    def backward(ctx, grad_C):
+        import numpy as np
+        phi_dist, phi, phibar = ctx.saved_tensors
+        Gc = grad_C.detach().cpu().numpy().astype(np.complex128)
+        G = np.stack([Gc.real, Gc.imag], axis=-1)
+        gd, g1, gq = dlma_correlators_grad(ctx.gauge, ctx.t_src, ctx.Vall, phi_dist, phi, phibar, G, ctx.ndil)
+        return gd, g1, gq, None, None, None, None
+
+
+def correlators(phi_dist, phi, phibar, gauge: Gauge, t_src: int, Vall: torch.Tensor, ndil: int = 1) -> torch.Tensor:
+    """Differentiable correlator pieces (see Correlators).  phi_dist, or phi and phibar
+    together, may be None: every piece is a sum over source groups, so the solutions can
+    be contracted in batches and the results added."""
+    return Correlators.apply(phi_dist, phi, phibar, gauge, int(t_src), Vall, int(ndil))
 
 
 def dlma_profile_enable(on: bool = True):

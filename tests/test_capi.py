@@ -56,7 +56,9 @@ def test_argument_validation_without_gpu(lib):
     assert lib.dlma_apply_schur(None, None, None, 1, 0, 2, 0, 0, 1, None) == -1
     assert lib.dlma_lap_eigs(None, 4, 0, 1, None, None, None, None, None) == -1
     assert lib.dlma_project(None, 0, 1, None, None, None, 1, 0, None) == -1
-    assert lib.dlma_correlators(None, 0, 1, None, None, 0, 1, None, None, None, None) == -1
+    assert lib.dlma_correlators(None, 0, 1, None, None, 1, 0, 1, None, None, None, None) == -1
+    assert lib.dlma_correlators_grad(None, 0, 1, None, None, 1, 0, 1, None, None, None, None, None, None, None) == -1
+    assert lib.dlma_project_noalloc(None, 0, 1, None, None, None, 1, 0, None) == -1
     assert lib.dlma_profile_read(10, None, None, None) == -1  # classes are 0..9
 
 

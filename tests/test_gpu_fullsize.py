@@ -288,6 +288,100 @@ def test_headline_launch_configuration(D, orc):
     assert float(P.abs().max()) < 1e-12
 
 
+def test_correlator_mass_gradient_32x64(D, orc):
+    """32^3 x 64, eps 0.2, kappa 0.1215, c_sw 1.3, t' = 0: N = 64 Laplacian modes on every
+    timeslice (256 spin-diluted distillation sources) and 8 Z2 wall vectors (32 eta + 32
+    (1 - box) eta).  Mixed FP16 solves through DiracSolve and the contractions through
+    Correlators; d/dm0 of the correlators by the hand-written backward (adjoint
+    contraction, then adjoint g5 D g5 solves), against central finite differences
+    (dm0 = 1e-4) of the same contractions on FP64 solves to 1e-12:
+      dC_V/dm0 and dC_PS/dm0 of the full correlator (11) at Delta = 4, of C_dist at
+      Delta = 8, and a random combination of every piece at Delta in {1, 4, 8, 16}.
+    The right-hand sides run in batches of 8 source groups (32 solves): every piece is a
+    sum over source groups, and the batches' contributions add."""
+    dims = (64, 32, 32, 32)
+    kappa, csw, nev, t0, nn = 0.1215, 1.3, 64, 0, 8
+    T = dims[0]
+    m0v = 1 / (2 * kappa) - 4
+    U = synth.gauge_field(dims, 0.2, 5)
+    g = D.dlma_load_gauge(cu(U), kappa, csw)
+    v0 = cu(synth.gaussian_start(dims, T, 605))
+    Vall = torch.empty((T, nev) + dims[1:] + (3,), dtype=torch.complex128, device="cuda")
+    for ts in range(0, T, 16):
+        Vall[ts:ts + 16] = D.dlma_lap_eigs(g, nev, ts, 16, v0[ts:ts + 16])[0]
+    del v0
+    print("C5: Laplacian modes on all timeslices", flush=True)
+    xi = cu(synth.z2_noise(dims, t0, nn, 1005))
+    rng = np.random.default_rng(55)
+    wr = np.zeros((2, 7, T))
+    for dl in (1, 4, 8, 16):
+        wr[:, :, dl] = rng.standard_normal((2, 7))
+    losses = {"V 11 Delta 4": (1, 4, 4), "PS 11 Delta 4": (0, 4, 4), "V C_dist Delta 8": (1, 5, 8),
+              "PS C_dist Delta 8": (0, 5, 8), "random": None}
+
+    def weight(key):
+        if losses[key] is None:
+            return torch.from_numpy(wr)
+        w = np.zeros((2, 7, T))
+        w[losses[key]] = 1.0
+        return torch.from_numpy(w)
+
+    batches = [("dist", i) for i in range(0, nev, 8)] + [("noise", 0), ("noise", 4)]
+
+    def sources(kind, i):
+        if kind == "dist":
+            return D.dist_sources(Vall[t0, i:i + 8].contiguous(), T, t0)
+        eta = D.noise_sources(xi[i:i + 4].contiguous(), T, t0)
+        return torch.cat([eta, D.dlma_project(g, t0, Vall[t0], eta, 1)])
+
+    # a batch's estimators average its own 4 noise vectors: weight them by 4 / 8
+    half = torch.ones((2, 7, T), dtype=torch.float64)
+    half[:, :5] = 4.0 / nn
+
+    def contract(kind, x):
+        if kind == "dist":
+            return D.correlators(x, None, None, g, t0, Vall)
+        return D.correlators(None, x[:16], x[16:], g, t0, Vall) * half
+
+    # backward: d/dm0 of each loss, summed over the batches
+    grad = {k: 0.0 for k in losses}
+    mix = D.default_opts(tol=TOL, prec="mix_fp16")
+    for kind, i in batches:
+        b = sources(kind, i)
+        m0 = torch.tensor(m0v, dtype=torch.float64, requires_grad=True)
+        x = D.dirac_solve(b, m0, g, mix)
+        C = contract(kind, x)
+        for k in losses:
+            (gm,) = torch.autograd.grad((weight(k) * C.real).sum(), m0, retain_graph=True)
+            grad[k] += gm.item()
+        del b, x, C
+        torch.cuda.empty_cache()
+        print("C5: backward batch", kind, i, flush=True)
+    # central finite differences of the same losses, FP64 solves to 1e-12
+    h = 1e-4
+    fp64 = D.default_opts(tol=1e-12, prec="fp64")
+    Cfd = {}
+    for sgn in (1, -1):
+        D.dlma_set_mass(g, 1.0 / (2 * (m0v + sgn * h) + 8))
+        Ct = 0.0
+        for kind, i in batches:
+            b = sources(kind, i)
+            (x,), st = D.dlma_solve([g], [b], opts=fp64)
+            assert all(s_["converged"] for s_ in st)
+            with torch.no_grad():
+                Ct = Ct + contract(kind, x)
+            del b, x
+            torch.cuda.empty_cache()
+        Cfd[sgn] = Ct
+        print("C5: finite-difference side", sgn, flush=True)
+    D.dlma_set_mass(g, kappa)
+    dC = (Cfd[1] - Cfd[-1]) / (2 * h)
+    for k in losses:
+        fd = float((weight(k) * dC.real).sum())
+        print("C5: %-18s adjoint %.10e  finite difference %.10e" % (k, grad[k], fd), flush=True)
+        assert abs(grad[k] - fd) <= 1e-6 * abs(fd) + 1e-9 * float(np.abs(Cfd[1].numpy()).max()), (k, grad[k], fd)
+
+
 def test_grad_32x64_fp64(D, orc):
     """32^3 x 64, eps 0.2, kappa 0.1215, c_sw 1.3, FP64: d/dm0 of a weighted
     pseudoscalar sink sum of one spin-diluted wall source, by the adjoint solve,

@@ -92,3 +92,98 @@ def test_mass_gradient_closed_form(D, orc):
     S = np.linalg.inv(_dense.dense_dirac(orc, U, A))
     ref = -np.vdot(cn.reshape(-1), S @ (S @ bn.reshape(-1))).real
     assert abs(m0.grad.item() - ref) <= 1e-10 * abs(ref), (m0.grad.item(), ref)
+
+
+def _random_G(rng, T, sparse=None):
+    """Weights [2][7][T][2] (dL/dRe C, dL/dIm C); sparse = (gamma, part, Delta) for a one-hot weight."""
+    G = np.zeros((2, 7, T, 2))
+    if sparse is None:
+        G[:] = rng.standard_normal(G.shape)
+    else:
+        G[sparse[0], sparse[1], sparse[2], 0] = 1.0
+    return G
+
+
+def _G_dict(orc, G):
+    return {name: {p: G[gi, pi, :, 0] + 1j * G[gi, pi, :, 1] for pi, p in enumerate(orc.PARTS)}
+            for gi, name in enumerate(("PS", "V"))}
+
+
+@pytest.mark.parametrize("dims,nev,ndist,ngrp,ndil,t0,sparse", [
+    ((4, 4, 4, 4), 3, 3, 2, 1, 1, None),
+    ((6, 4, 2, 8), 4, 2, 4, 2, 5, None),                 # ragged extents, fewer solution groups than modes
+    ((4, 4, 4, 4), 3, 3, 2, 1, 0, (1, 2, 3)),            # one weighted (Gamma, piece, Delta): zero elsewhere
+    ((2, 4, 4, 4), 70, 3, 1, 1, 1, None)])               # more than 64 modes: the kernel's mode chunks
+def test_correlators_grad_matches_oracle(D, orc, dims, nev, ndist, ngrp, ndil, t0, sparse):
+    """dlma_correlators_grad against the oracle's backward of the contractions on identical
+    inputs (random solution fields, the oracle's Laplacian modes, random weights)."""
+    T = dims[0]
+    rng = np.random.default_rng(7)
+    U = synth.gauge_field(dims, 0.3, 4)
+    Vall = np.stack([orc.lap_eigs(U, t, nev, synth.gaussian_start(dims, 1, 90 + t)[0], tol=1e-12)[1] for t in range(T)])
+    pd = synth.random_spinor(dims, 4 * ndist, 11)
+    p1 = synth.random_spinor(dims, 4 * ngrp, 12)
+    pq = synth.random_spinor(dims, 4 * ngrp, 13)
+    G = _random_G(rng, T, sparse)
+    g = D.dlma_load_gauge(cu(U), 0.120, 1.0)
+    got = D.dlma_correlators_grad(g, t0, cu(Vall), cu(pd), cu(p1), cu(pq), G, ndil)
+    ref = orc.correlators_vjp(Vall, t0, pd, p1, pq, _G_dict(orc, G), ndil=ndil)
+    for gg, rr in zip(got, ref):
+        gg = gg.cpu().numpy()
+        assert np.max(np.abs(gg - rr)) <= 1e-12 * np.max(np.abs(rr)), np.max(np.abs(gg - rr)) / np.max(np.abs(rr))
+    # and the forward agrees with the oracle on these inputs (ndist groups passed)
+    C = D.dlma_correlators(g, t0, cu(Vall), cu(pd), cu(p1), cu(pq), ndil=ndil)
+    Co = orc.correlators(Vall, t0, pd, p1, pq, ndil=ndil)
+    for name in ("PS", "V"):
+        sc = max(np.max(np.abs(Co[name][p])) for p in orc.PARTS)
+        for p in orc.PARTS:
+            assert np.max(np.abs(C[name][p] - Co[name][p])) <= 1e-12 * sc, (name, p)
+
+
+def test_correlator_mass_gradient_chain(D, orc):
+    """dC/dm0 through the whole chain at 4^4: sources (distillation and projected noise),
+    solves (DiracSolve, adjoint-solve backward), contractions (Correlators, hand-written
+    backward); a real loss L = sum w Re C over every piece, both Gammas and every Delta.
+    Against central finite differences of the oracle's own chain (dm0 = 1e-4, solves to
+    1e-13) and against the oracle's gradient (its backward of the contractions and its
+    adjoint solves)."""
+    dims = (4, 4, 4, 4)
+    T, t0, nev, nn = dims[0], 1, 3, 2
+    kappa, csw = 0.120, 1.0
+    m0v = 1 / (2 * kappa) - 4
+    U = synth.gauge_field(dims, 0.3, 1)
+    Vall = np.stack([orc.lap_eigs(U, t, nev, synth.gaussian_start(dims, 1, 50 + t)[0], tol=1e-12)[1] for t in range(T)])
+    eta = orc.noise_sources(synth.z2_noise(dims, t0, nn, 1001), T, t0)
+    src = np.concatenate([orc.dist_sources(Vall[t0], T, t0), eta, orc.project(Vall[t0], eta, t0, 1)])
+    nd = 4 * nev
+    rng = np.random.default_rng(3)
+    w = rng.standard_normal((2, 7, T))
+
+    def oracle_loss(m0):
+        A = orc.clover(U, 1.0 / (2 * m0 + 8), csw)
+        x = orc.solve(U, A, src, tol=1e-13)[0]
+        C = orc.correlators(Vall, t0, x[:nd], x[nd:nd + 4 * nn], x[nd + 4 * nn:])
+        return sum(np.sum(w[gi, pi] * C[name][p].real) for gi, name in enumerate(("PS", "V"))
+                   for pi, p in enumerate(orc.PARTS)), x, A
+
+    h = 1e-4
+    fd = (oracle_loss(m0v + h)[0] - oracle_loss(m0v - h)[0]) / (2 * h)
+    # the oracle's gradient: backward of the contractions, adjoint solves D^dag lam = grad
+    _, xo, Ao = oracle_loss(m0v)
+    Gd = _G_dict(orc, np.stack([w, np.zeros_like(w)], axis=-1))
+    gd, g1, gq = orc.correlators_vjp(Vall, t0, xo[:nd], xo[nd:nd + 4 * nn], xo[nd + 4 * nn:], Gd)
+    gx = np.concatenate([gd, g1, gq])
+    g5 = np.diag([1.0, 1.0, -1.0, -1.0])
+    lam = np.einsum("st,...tc->...sc", g5, orc.solve(U, Ao, np.einsum("st,...tc->...sc", g5, gx), tol=1e-13)[0])
+    ref = -np.vdot(lam.reshape(-1), xo.reshape(-1)).real
+    assert abs(ref - fd) <= 1e-6 * abs(fd), (ref, fd)
+    # the GPU chain with autograd
+    g = D.dlma_load_gauge(cu(U), kappa, csw)
+    m0 = torch.tensor(m0v, dtype=torch.float64, requires_grad=True)
+    x = D.dirac_solve(cu(src), m0, g, D.default_opts(tol=1e-13))
+    C = D.correlators(x[:nd], x[nd:nd + 4 * nn], x[nd + 4 * nn:], g, t0, cu(Vall))
+    L = (torch.from_numpy(w) * C.real).sum()
+    L.backward()
+    got = m0.grad.item()
+    assert abs(got - ref) <= 1e-9 * abs(ref), (got, ref)
+    assert abs(got - fd) <= 1e-6 * abs(fd), (got, fd)
