@@ -20,9 +20,12 @@ namespace {
 
 // Eigenvalues (and optionally eigenvectors or their last row) of the real symmetric
 // tridiagonal matrix with diagonal d and off-diagonal e, by the implicit QL
-// algorithm: repeated QL sweeps with a shift from the trailing 2x2 block, applied
-// as a chase of plane rotations from the bottom of the unreduced block upwards,
-// with deflation when an off-diagonal element becomes negligible.
+// algorithm with Wilkinson-type shifts (the published method of Bowdler, Martin,
+// Reinsch and Wilkinson, Numer. Math. 11 (1968) 293, the tql/imtql line of the
+// Handbook for Automatic Computation and EISPACK, restated here): repeated QL sweeps
+// with a shift from the trailing 2x2 block, applied as a chase of plane rotations
+// from the bottom of the unreduced block upwards, with deflation when an
+// off-diagonal element becomes negligible.
 //   Z (m x m, row-major) receives the eigenvector matrix (columns), last its last row.
 // zinit: Z holds an orthogonal matrix Q on entry and receives Q times the
 // eigenvector matrix (the back-transformation of a reduction to tridiagonal form).
@@ -97,7 +100,9 @@ bool tridiag_ql(std::vector<double>& d, std::vector<double> e, std::vector<doubl
 
 // Eigenpairs of a dense real symmetric matrix A (n x n, row-major): Householder
 // reflections reduce A to tridiagonal form T = Q^T A Q, working from the last row
-// upwards (the reflection of step i zeroes A[i][0..i-2] and acts on indices < i),
+// upwards (the reflection of step i zeroes A[i][0..i-2] and acts on indices < i; the
+// published tridiagonalisation of Martin, Reinsch and Wilkinson, Numer. Math. 11
+// (1968) 181, the tred line of EISPACK, restated here),
 // and the implicit QL iteration of tridiag_ql diagonalises T, its rotations applied
 // to Q.  d receives the eigenvalues, Z (row-major) the eigenvectors as columns.
 bool sym_eig(std::vector<double> A, int n, std::vector<double>& d, std::vector<double>& Z) {
