@@ -43,6 +43,13 @@ KCLASS = {0: "hop_k1 (odd sites: y = A_oo^-1 D_oe x)",
           8: "hop_k2_dotr (even sites: v = A_ee p - D_eo y with (rh, v))",
           9: "hop_k2_dotx (even sites: t = A_ee s - D_eo y with (t, s) and |t|^2)"}
 KTEMPLATE = {0: (0, 0), 1: (0, 1), 2: (1, 6), 3: (1, 8), 4: (1, 0), 8: (1, 512), 9: (1, 256)}
+
+
+def ktemplate(kc, prec):
+    """(kind, flags) of a class's hop_kernel: FP16 BiCGStab's K2 for t also forms (rh, t) (flag 1024)."""
+    if kc == 9 and prec == "mix_fp16":
+        return (1, 256 | 1024)
+    return KTEMPLATE[kc]
 PREC_ID = {"fp64": 0, "mix_fp32": 1, "mix_fp16": 2, "mix_bf16": 3}
 HOP_SOURCES = ["paper_2201_09729_amd/csrc/hop.h", "paper_2201_09729_amd/csrc/hop16.h", "paper_2201_09729_amd/csrc/common.h",
                "paper_2201_09729_amd/csrc/hop_inst.h"]
@@ -65,7 +72,7 @@ def hop_bytes_split(prec, kind, flags, dims):
     vh = dims[0] * dims[1] * dims[2] * dims[3] // 2
     pb = pair_bytes(prec)
     fixed = vh * (72 * pb + (0 if (kind == 1 and flags & 32) else 36 * pb))
-    if kind == 1 and flags & 512:
+    if kind == 1 and flags & (512 | 1024):  # the shared shadow residual
         fixed += vh * spinor_bytes(prec)
     if kind == 0:
         passes = 2 + (1 if flags & 64 else 0) + (1 if flags & 128 else 0)
@@ -217,7 +224,7 @@ def main():
     # v = Dhat p and for t = Dhat s.
     kc = max(prof, key=lambda k: prof[k][1])
     n_l, ms_tot, by_all = prof[kc]
-    fixed, per_rhs = hop_bytes_split(args.prec, *KTEMPLATE[kc], DIMS)
+    fixed, per_rhs = hop_bytes_split(args.prec, *ktemplate(kc, args.prec), DIMS)
     per_iter = 2 if (args.inner_solver == 1 and kc == 0) else 1  # BiCGStab applies K1 twice per iteration
     rhs_launches = per_iter * sum(s["inner_iters"] for stp in pstats for s in stp)
     by_tot = n_l * fixed + rhs_launches * per_rhs
@@ -676,7 +683,7 @@ def summarize(args):
     pid = PREC_ID[prec]
 
     def hop_name(kc, nb):
-        kind, fl = KTEMPLATE[kc]
+        kind, fl = ktemplate(kc, prec)
         return "void dlma::hop_kernel<%d, %d, %d, %d, 128>(dlma::HopJob<%d> const*, int, int)" % (pid, nb, kind, fl, pid)
 
     by_name = {r["Name"]: r for r in stats}
@@ -704,7 +711,8 @@ def summarize(args):
         tb = (fk * scale["FETCH_SIZE"] + wk * scale["WRITE_SIZE"]) * 1024.0
         avg_ms = sum(step_ms[nm]) / len(step_ms[nm])
         lines.append("| %s | `hop_kernel<%d,%d,%d,%d>` | %d | %.0f | %.0f | %.3f | %.4f |"
-                     % (KCLASS[kc].split()[0], pid, nb, KTEMPLATE[kc][0], KTEMPLATE[kc][1], len(f), fk, wk, tb / 1e9, avg_ms))
+                     % (KCLASS[kc].split()[0], pid, nb, ktemplate(kc, prec)[0], ktemplate(kc, prec)[1], len(f), fk, wk,
+                        tb / 1e9, avg_ms))
         out[kc] = {"kernel": nm, "precision": prec, "rhs_block": nb, "source_sha": sources_sha(),
                    "fetch_kib_per_dispatch": fk, "write_kib_per_dispatch": wk, "copy_scale": scale,
                    "traffic_bytes_per_launch": tb, "avg_ms_rocprof": avg_ms,

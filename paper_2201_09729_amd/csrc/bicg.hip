@@ -111,6 +111,70 @@ template <int MODE> HD void bivec16(const BiVecJob<P16>& J, int r, uint32_t site
         }
         q1 = (double)re * nh;
         q2 = (double)im * nh;
+    } else if (MODE == BV_SH) {  // s = r - alpha v, and (rh, s) of the stored s
+        const F16Field R = f16_field(J.r, J.Vh, r), V = f16_field(J.v, J.Vh, r), S = f16_field(J.s, J.Vh, r);
+        const F16Field RH = f16_field(J.rh, J.Vh, r);
+        const float ar = (float)J.alpha[r].x, ai = (float)J.alpha[r].y;
+        uint32_t wh[12];
+        load_words<CP_NT>(R, s16, G16, wa);
+        load_words<CP_NT>(V, s16, G16, wb);
+        load_words(RH, s16, G16, wh);  // cached: every RHS reads this one field
+        const float nr = wldf<CP_NT>(R.n, lo, 0), nv = wldf<CP_NT>(V.n, lo, 0), nh = wldf(RH.n, lo, 0);
+        bv16_cplx(wa, nr, a);
+        bv16_cplx(wb, nv, b);
+#pragma unroll
+        for (int i = 0; i < 12; ++i) {
+            c[2 * i] = a[2 * i] - (ar * b[2 * i] - ai * b[2 * i + 1]);
+            c[2 * i + 1] = a[2 * i + 1] - (ar * b[2 * i + 1] + ai * b[2 * i]);
+        }
+        float ms;
+        (void)store16w(S, G16, site, c, wc, ms);
+        float re, im;
+        dot16(wh, wc, re, im);
+        q0 = (double)re * ((double)nh * ms);
+        q1 = (double)im * ((double)nh * ms);
+    } else if (MODE == BV_XRP) {  // x += alpha p + omega s; r = s - omega t; p = r + beta (p - omega v); |r|^2
+        const F16Field X = f16_field(J.x, J.Vh, r), Pp = f16_field(J.p, J.Vh, r), S = f16_field(J.s, J.Vh, r);
+        const F16Field T = f16_field(J.t, J.Vh, r), R = f16_field(J.r, J.Vh, r), V = f16_field(J.v, J.Vh, r);
+        const float alr = (float)J.alpha[r].x, ali = (float)J.alpha[r].y;
+        const float omr = (float)J.omega[r].x, omi = (float)J.omega[r].y;
+        const float ber = (float)J.beta[r].x, bei = (float)J.beta[r].y;
+        // every load first (the stores could alias them as far as the compiler can tell)
+        uint32_t wt[12], wv[12];
+        load_words<CP_NT>(X, s16, G16, wa);
+        load_words<CP_NT>(Pp, s16, G16, wb);
+        load_words<CP_NT>(S, s16, G16, wc);
+        load_words<CP_NT>(T, s16, G16, wt);
+        load_words<CP_NT>(V, s16, G16, wv);
+        const float nx = wldf<CP_NT>(X.n, lo, 0), np = wldf<CP_NT>(Pp.n, lo, 0), ns = wldf<CP_NT>(S.n, lo, 0);
+        const float nt = wldf<CP_NT>(T.n, lo, 0), nv = wldf<CP_NT>(V.n, lo, 0);
+        bv16_cplx(wa, nx, a);
+        bv16_cplx(wb, np, b);
+        bv16_cplx(wc, ns, c);
+#pragma unroll
+        for (int i = 0; i < 12; ++i) {  // x += alpha p + omega s
+            const float pr = b[2 * i], pi = b[2 * i + 1], sr = c[2 * i], si = c[2 * i + 1];
+            a[2 * i] += alr * pr - ali * pi + omr * sr - omi * si;
+            a[2 * i + 1] += alr * pi + ali * pr + omr * si + omi * sr;
+        }
+        (void)store16(X, G16, site, a);
+        bv16_cplx(wt, nt, a);
+#pragma unroll
+        for (int i = 0; i < 12; ++i) {  // r = s - omega t
+            const float tr = a[2 * i], ti = a[2 * i + 1];
+            c[2 * i] -= omr * tr - omi * ti;
+            c[2 * i + 1] -= omr * ti + omi * tr;
+        }
+        q0 = (double)store16(R, G16, site, c);
+        bv16_cplx(wv, nv, a);
+#pragma unroll
+        for (int i = 0; i < 12; ++i) {  // p = r + beta (p - omega v)
+            const float dr = b[2 * i] - (omr * a[2 * i] - omi * a[2 * i + 1]);
+            const float di = b[2 * i + 1] - (omr * a[2 * i + 1] + omi * a[2 * i]);
+            b[2 * i] = c[2 * i] + ber * dr - bei * di;
+            b[2 * i + 1] = c[2 * i + 1] + ber * di + bei * dr;
+        }
+        (void)store16(Pp, G16, site, b);
     } else {  // BV_P: p = r + beta (p - omega v)
         const F16Field R = f16_field(J.r, J.Vh, r), Pp = f16_field(J.p, J.Vh, r), V = f16_field(J.v, J.Vh, r);
         const float ber = (float)J.beta[r].x, bei = (float)J.beta[r].y;
@@ -145,8 +209,10 @@ template <int P, int MODE> __global__ void __launch_bounds__(VEC_BS) k_bivec(con
     const int cb = sb * VEC_BS + (int)threadIdx.x;
     const bool act = rhs_active(J, r);  // uniform over the block
     double q0 = 0, q1 = 0, q2 = 0;
-    if constexpr (P == P16 && (MODE == BV_S || MODE == BV_XR || MODE == BV_P)) {
+    if constexpr (P == P16 && (MODE == BV_S || MODE == BV_XR || MODE == BV_P || MODE == BV_SH || MODE == BV_XRP)) {
         if (act && cb < J.Vh) bivec16<MODE>(J, r, (uint32_t)cb, q0, q1, q2);
+    } else if constexpr (MODE == BV_SH || MODE == BV_XRP) {
+        // the merged iteration exists for FP16 fields only (launch_bivec refuses the others)
     } else if (act && cb < J.Vh) {
         R a[24], b[24], c[24];
         if (MODE == BV_RR || MODE == BV_RV) {
@@ -216,10 +282,12 @@ template <int P, int MODE> __global__ void __launch_bounds__(VEC_BS) k_bivec(con
             store_spinor<P, R>(J.p, J.Vh, r, cb, b);
         }
     }
-    constexpr int NQ = (MODE == BV_RR || MODE == BV_RV) ? 2 : ((MODE == BV_TS || MODE == BV_XR) ? 3 : 0);
-    if (NQ > 0) bi_partial(q0, J.part, ((long)r * NQ + 0) * J.pstride + sb);
-    if (NQ > 1) bi_partial(q1, J.part, ((long)r * NQ + 1) * J.pstride + sb);
-    if (NQ > 2) bi_partial(q2, J.part, ((long)r * NQ + 2) * J.pstride + sb);
+    constexpr int NQ = (MODE == BV_RR || MODE == BV_RV || MODE == BV_SH) ? 2
+                       : ((MODE == BV_TS || MODE == BV_XR) ? 3 : (MODE == BV_XRP ? 1 : 0));
+    double* part = MODE == BV_SH ? J.part_s : J.part;
+    if (NQ > 0) bi_partial(q0, part, ((long)r * NQ + 0) * J.pstride + sb);
+    if (NQ > 1) bi_partial(q1, part, ((long)r * NQ + 1) * J.pstride + sb);
+    if (NQ > 2) bi_partial(q2, part, ((long)r * NQ + 2) * J.pstride + sb);
 }
 
 template <int P> hipError_t launch_bivec(const BiVecJob<P>* j, int njob, int nblocks, int mode, hipStream_t s) {
@@ -231,6 +299,14 @@ template <int P> hipError_t launch_bivec(const BiVecJob<P>* j, int njob, int nbl
     case BV_TS: hipLaunchKernelGGL((k_bivec<P, BV_TS>), dim3(nblocks), dim3(VEC_BS), 0, s, j, njob); break;
     case BV_XR: hipLaunchKernelGGL((k_bivec<P, BV_XR>), dim3(nblocks), dim3(VEC_BS), 0, s, j, njob); break;
     case BV_P: hipLaunchKernelGGL((k_bivec<P, BV_P>), dim3(nblocks), dim3(VEC_BS), 0, s, j, njob); break;
+    case BV_SH:
+        if (P != P16) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_bivec<P, BV_SH>), dim3(nblocks), dim3(VEC_BS), 0, s, j, njob);
+        break;
+    case BV_XRP:
+        if (P != P16) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_bivec<P, BV_XRP>), dim3(nblocks), dim3(VEC_BS), 0, s, j, njob);
+        break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -253,16 +329,23 @@ __global__ void __launch_bounds__(256) k_bifinish(const BiFinJob* jobs, int njob
     const BiFinJob& J = jobs[jb];
     const int r = bid - J.rhs0;
     if (r >= J.nrhs) return;  // uniform over the block
-    const int NQ = (mode == BF_ALPHA || mode == BF_INIT) ? 2 : 3;
-    const int np = (mode == BF_ALPHA || mode == BF_OMEGA) ? J.nparth : J.npart;
+    const int NQ = (mode == BF_ALPHA || mode == BF_INIT) ? 2 : (mode == BF_OMBETA ? 5 : (mode == BF_CONV ? 1 : 3));
+    const int np = (mode == BF_ALPHA || mode == BF_OMEGA || mode == BF_OMBETA) ? J.nparth : J.npart;
     __shared__ double lds[4];
-    double q[3] = {0, 0, 0};
+    double q[7] = {0, 0, 0, 0, 0, 0, 0};
     for (int k = 0; k < NQ; ++k) {
         double v = 0;
         const double* pp = J.part + ((size_t)r * NQ + k) * np;
         for (int i = threadIdx.x; i < np; i += 256) v += pp[i];
         q[k] = block_sum<256>(v, lds);
     }
+    if (mode == BF_OMBETA)  // (rh, s) from the s step's own partials
+        for (int k = 0; k < 2; ++k) {
+            double v = 0;
+            const double* pp = J.part_s + ((size_t)r * 2 + k) * J.npart;
+            for (int i = threadIdx.x; i < J.npart; i += 256) v += pp[i];
+            q[5 + k] = block_sum<256>(v, lds);
+        }
     if (threadIdx.x != 0) return;
     const Cd one = {1.0, 0.0}, zero = {0.0, 0.0};
     auto st = [](double2* a, int i, Cd v) { a[i] = make_double2(v.r, v.i); };
@@ -287,6 +370,27 @@ __global__ void __launch_bounds__(256) k_bifinish(const BiFinJob* jobs, int njob
     } else if (mode == BF_OMEGA) {
         const Cd ts = {q[0], q[1]};
         st(J.omega, r, (finite2(ts) && q[2] > 0.0 && isfinite(q[2])) ? Cd{ts.r / q[2], ts.i / q[2]} : zero);
+    } else if (mode == BF_OMBETA) {
+        // omega = (t, s) / |t|^2; rho' = (rh, s) - omega (rh, t), both on the stored s and t, is
+        // (rh, s - omega t) for the r = s - omega t that the merged update forms from them
+        const Cd ts = {q[0], q[1]}, rt = {q[3], q[4]}, rs = {q[5], q[6]};
+        const Cd om = (finite2(ts) && q[2] > 0.0 && isfinite(q[2])) ? Cd{ts.r / q[2], ts.i / q[2]} : zero;
+        st(J.omega, r, om);
+        const Cd ort = cmulc(om, rt);
+        const Cd rho1 = {rs.r - ort.r, rs.i - ort.i};
+        const Cd rho = ld2(J.rho, r), al = ld2(J.alpha, r);
+        const bool brk = (om.r == 0.0 && om.i == 0.0) || (rho.r == 0.0 && rho.i == 0.0) || !finite2(rho1) ||
+                         (rho1.r == 0.0 && rho1.i == 0.0);
+        // on a breakdown the update still runs (with beta = 0) and BF_CONV stops the right-hand side
+        st(J.beta, r, brk ? zero : cmulc(cdivc(rho1, rho), cdivc(al, om)));
+        st(J.rho, r, brk ? zero : rho1);
+    } else if (mode == BF_CONV) {
+        const double rr = q[0];
+        J.rr[r] = rr;
+        const int it = J.iters[r] + 1;
+        J.iters[r] = it;
+        const Cd rho = ld2(J.rho, r);  // zero after a breakdown
+        if (!isfinite(rr) || rr <= J.tol2[r] || it >= J.maxit || (rho.r == 0.0 && rho.i == 0.0)) J.active[r] = 0;
     } else {  // BF_BETA
         const double rr = q[0];
         const Cd rho1 = {q[1], q[2]};

@@ -34,12 +34,16 @@ enum HopFlags {
     F_ACCUM = 128,  // K1: out += result
     F_DOTX = 256,   // K2: partials of sum conj(out) x (re, im) and |out|^2
     F_DOTR = 512,   // K2: partials of sum conj(r) out (re, im), r the job's r field
+    F_DOTXH = 1024, // K2, FP16, with F_DOTX: also sum conj(r) out of the stored (rounded) out (re, im)
 };
 
-// Partial sums a stencil launch writes per right-hand side: F_DOTX 3, F_DOTR 2,
-// F_NORM or F_CG 1 (|out|^2 or the updated |r|^2).  Layout: one quantity at
-// part[r * pstride + block]; several at part[(r * NQ + q) * pstride + block].
-constexpr int hop_nq(int fl) { return (fl & F_DOTX) ? 3 : ((fl & F_DOTR) ? 2 : ((fl & (F_NORM | F_CG)) ? 1 : 0)); }
+// Partial sums a stencil launch writes per right-hand side: F_DOTX | F_DOTXH 5,
+// F_DOTX 3, F_DOTR 2, F_NORM or F_CG 1 (|out|^2 or the updated |r|^2).  Layout: one
+// quantity at part[r * pstride + block]; several at part[(r * NQ + q) * pstride + block].
+constexpr int hop_nq(int fl) {
+    return (fl & F_DOTXH) ? 5 : ((fl & F_DOTX) ? 3 : ((fl & F_DOTR) ? 2 : ((fl & (F_NORM | F_CG)) ? 1 : 0)));
+}
+constexpr int HOP_NQ_MAX = 5;
 
 template <int P> struct HopJob {
     Geo g;
@@ -120,7 +124,7 @@ HD void hop_dir(const HopJob<P>& J, const Nbr& nb, int cb, int g0, bool (&use)[N
 // Per-site body.  Returns the site's contributions to the partial sums of hop_nq(FL)
 // quantities in qs.
 template <int P, int NB, int KIND, int FL>
-HD void hop_site(const HopJob<P>& J, int cb, int g0, double (&qs)[NB][3]) {
+HD void hop_site(const HopJob<P>& J, int cb, int g0, double (&qs)[NB][HOP_NQ_MAX]) {
     static_assert(P != P16, "FP16 fields take hop_site16");
     using R = typename PT<P>::R;
     const int Vh = J.g.Vh;
@@ -129,7 +133,7 @@ HD void hop_site(const HopJob<P>& J, int cb, int g0, double (&qs)[NB][3]) {
     for (int j = 0; j < NB; ++j) {
         int r = g0 + j;
         use[j] = rhs_active(J, r);
-        qs[j][0] = qs[j][1] = qs[j][2] = 0.0;
+        for (int q = 0; q < HOP_NQ_MAX; ++q) qs[j][q] = 0.0;
     }
     R acc[NB][24];
 #pragma unroll
@@ -303,7 +307,7 @@ template <int BS> __device__ __forceinline__ double block_sum(double v, double* 
 // The per-site body for the FP64, FP32 and BF16 fields (FP16 fields take the
 // raw-word path of hop16.h, called from the kernel directly).
 template <int P, int NB, int KIND, int FL>
-HD void site_body(const HopJob<P>& J, int cb, int g0, double (&qs)[NB][3]) {
+HD void site_body(const HopJob<P>& J, int cb, int g0, double (&qs)[NB][HOP_NQ_MAX]) {
     hop_site<P, NB, KIND, FL>(J, cb, g0, qs);
 }
 
@@ -361,7 +365,7 @@ hop_kernel(const HopJob<P>* __restrict__ jobs, int njob, int wn_cap) {
             J.part[(size_t)(g0 * NQ + (int)threadIdx.x) * J.pstride + sb] = 0.0;
         return;
     }
-    double qs[NB][3];
+    double qs[NB][HOP_NQ_MAX];
     if constexpr (P == P16) {
         // Every thread runs the body, whose LDS staging has a block barrier: a thread
         // past the timeslice's last site works on that site and stores nothing.
@@ -376,7 +380,8 @@ hop_kernel(const HopJob<P>* __restrict__ jobs, int njob, int wn_cap) {
             site_body<P, NB, KIND, FL>(J, cb, g0, qs);
         } else {
 #pragma unroll
-            for (int j = 0; j < NB; ++j) qs[j][0] = qs[j][1] = qs[j][2] = 0.0;
+            for (int j = 0; j < NB; ++j)
+                for (int q = 0; q < HOP_NQ_MAX; ++q) qs[j][q] = 0.0;
         }
     }
     if (NQ > 0) {

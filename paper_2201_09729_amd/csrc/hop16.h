@@ -308,16 +308,16 @@ HD void load_clover16(const WSrc& C, uint32_t G16, int blk, uint32_t site16, uin
 // ---------------------------------------------------------------- spinor store
 
 // Stores 24 FP32 values as binary16 words scaled by their largest magnitude
-// (the rule of store_spinor in common.h) and returns the sum of their squares.
-HD float store16(const F16Field& f, uint32_t G16, uint32_t site, const float s[24]) {
-    float m = 0.f;
+// (the rule of store_spinor in common.h) and returns the sum of their squares;
+// the stored words and scale are left in w and m (the stored value is w * m).
+HD float store16w(const F16Field& f, uint32_t G16, uint32_t site, const float s[24], uint32_t w[12], float& m) {
+    m = 0.f;
 #pragma unroll
     for (int i = 0; i < 24; ++i) m = fmaxf(m, fabsf(s[i]));
     if (!(m >= 1e-30f)) m = 0.f;
     const float inv = m > 0.f ? 1.0f / m : 0.f;
     wst(f.n, 4u * site, 0, __builtin_bit_cast(uint32_t, m));
     float q = 0.f;
-    uint32_t w[12];
 #pragma unroll
     for (int c = 0; c < 12; ++c) {
         w[c] = f_to_h(s[2 * c] * inv) | (f_to_h(s[2 * c + 1] * inv) << 16);
@@ -329,6 +329,25 @@ HD float store16(const F16Field& f, uint32_t G16, uint32_t site, const float s[2
     for (int g = 0; g < 3; ++g) wst4(f.v, 16u * site, (uint32_t)g * G16, (u32x4){w[4 * g], w[4 * g + 1], w[4 * g + 2], w[4 * g + 3]});
     wide_store_end();
     return q;
+}
+
+HD float store16(const F16Field& f, uint32_t G16, uint32_t site, const float s[24]) {
+    uint32_t w[12];
+    float m;
+    return store16w(f, G16, site, s, w, m);
+}
+
+// sum conj(a) b over the 12 complex components of two stored sites (binary16 words;
+// the caller multiplies by both scales): exact binary16 products, FP32 sums
+HD void dot16(const uint32_t a[12], const uint32_t b[12], float& re, float& im) {
+    re = 0.f;
+    im = 0.f;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+        const float ar = lo16(a[c]), ai = hi16(a[c]), br = lo16(b[c]), bi = hi16(b[c]);
+        re = __builtin_fmaf(ar, br, __builtin_fmaf(ai, bi, re));
+        im = __builtin_fmaf(ar, bi, __builtin_fmaf(-ai, br, im));
+    }
 }
 
 // ---------------------------------------------------------------- LDS window
@@ -452,7 +471,7 @@ HD void hop_dir16(const HopJob<P16>& J, const WSrc& U, const F16Field (&in)[NB],
 // as there.  Every thread of the block calls it (W's staging has a block barrier); a
 // thread with !valid works on a real site but stores nothing and returns qs = 0.
 template <int NB, int KIND, int FL, int BS>
-HD void hop_site16(const HopJob<P16>& J, int cb, int g0, bool valid, const Window16& W, double (&qs)[NB][3]) {
+HD void hop_site16(const HopJob<P16>& J, int cb, int g0, bool valid, const Window16& W, double (&qs)[NB][HOP_NQ_MAX]) {
     const uint32_t G16 = 16u * (uint32_t)J.g.Vh;  // bytes per 16-byte group plane
     const uint32_t site = (uint32_t)cb, lo = 4u * site, s16 = 16u * site;
     constexpr bool G5IN = (FL & F_G5IN) != 0;
@@ -465,7 +484,7 @@ HD void hop_site16(const HopJob<P16>& J, int cb, int g0, bool valid, const Windo
     for (int j = 0; j < NB; ++j) {
         const int r = g0 + j;
         use[j] = rhs_active(J, r);
-        qs[j][0] = qs[j][1] = qs[j][2] = 0.0;
+        for (int q = 0; q < HOP_NQ_MAX; ++q) qs[j][q] = 0.0;
         in[j] = f16_field(J.in, J.g.Vh, r);
         al[j] = CG ? (float)J.alpha[r < J.nrhs ? r : 0] : 0.f;
         // K2 with the CG update accumulates -alpha * out directly
@@ -613,7 +632,9 @@ HD void hop_site16(const HopJob<P16>& J, int cb, int g0, bool valid, const Windo
                     if (valid) (void)store16(sf, G16, site, acc[j]);
                 } else if (valid) {
                     const F16Field o = f16_field(J.out, J.g.Vh, g0 + j);
-                    const float q = store16(o, G16, site, acc[j]);
+                    uint32_t ow[12];
+                    float om;
+                    const float q = store16w(o, G16, site, acc[j], ow, om);
                     if (FL & F_NORM) qs[j][0] = (double)q;
                     if (FL & F_DOTX) {  // sum conj(out) x, with x's words and scale in registers
                         float re = 0.f, im = 0.f;
@@ -626,6 +647,16 @@ HD void hop_site16(const HopJob<P16>& J, int cb, int g0, bool valid, const Windo
                         qs[j][0] = (double)re * nx[j];
                         qs[j][1] = (double)im * nx[j];
                         qs[j][2] = (double)q;
+                    }
+                    if (FL & F_DOTXH) {  // sum conj(r) out of the stored out, r (the shadow residual) at the own site
+                        const F16Field rf = f16_field(J.r, J.g.Vh, g0 + j);
+                        const float nr = wldf(rf.n, lo, 0);  // cached: one field for every RHS
+                        uint32_t rw[12];
+                        load_words(rf, s16, G16, rw);
+                        float re, im;
+                        dot16(rw, ow, re, im);
+                        qs[j][3] = (double)re * ((double)nr * om);
+                        qs[j][4] = (double)im * ((double)nr * om);
                     }
                     if (FL & F_DOTR) {  // sum conj(r) out, r (the shadow residual) read at the own site
                         const F16Field rf = f16_field(J.r, J.g.Vh, g0 + j);

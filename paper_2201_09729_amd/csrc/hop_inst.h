@@ -33,6 +33,10 @@ hipError_t launch_hop<DLMA_PREC>(const HopCfg& c, const HopJob<DLMA_PREC>* djobs
     // BiCGStab: v = Dhat p with (rh, v); t = Dhat s with (t, s) and |t|^2
     DLMA_HOP_ALLNB(K2, F_DOTR)
     DLMA_HOP_ALLNB(K2, F_DOTX)
+#if DLMA_PREC == 2
+    // FP16: t = Dhat s with (t, s), |t|^2 and (rh, t) of the stored t (the merged iteration)
+    DLMA_HOP_ALLNB(K2, F_DOTX | F_DOTXH)
+#endif
 #if DLMA_PREC == 0
     // FP64 only: full operator, defect-correction residual, Schur source, reconstruction
     DLMA_HOP_ALLNB(K2, F_G5IN | F_G5OUT)

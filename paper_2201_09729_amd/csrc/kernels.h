@@ -45,6 +45,7 @@ template <int P> struct BiVecJob {
     const int* active;
     double* part;
     int pstride;
+    double* part_s;  // BV_SH's partials of (rh, s), part_s[(r * 2 + q) * pstride + block] (FP16 path)
 };
 enum BiVecMode {
     BV_RR = 0,    // part: (rh, r)                                   NQ = 2 (re, im)
@@ -53,6 +54,9 @@ enum BiVecMode {
     BV_TS = 3,    // part: (t, s), |t|^2                             NQ = 3
     BV_XR = 4,    // x += alpha p + omega s; r = s - omega t; part: |r|^2, (rh, r)   NQ = 3
     BV_P = 5,     // p = r + beta (p - omega v)
+    // FP16 fields only: the merged iteration (beta known before the updates)
+    BV_SH = 6,    // s = r - alpha v; part_s: (rh, s) of the stored s  NQ = 2
+    BV_XRP = 7,   // x += alpha p + omega s; r = s - omega t; p = r + beta (p - omega v); part: |r|^2  NQ = 1
 };
 template <int P> hipError_t launch_bivec(const BiVecJob<P>* j, int njob, int nblocks, int mode, hipStream_t s);
 
@@ -62,14 +66,19 @@ struct BiFinJob {
     int nrhs, rhs0, npart;     // npart: partials per quantity of the vector kernels (their pstride)
     int nparth;                // the same for the stencil kernels (alpha's and omega's sums come from K2)
     const double* part;
+    const double* part_s;      // BV_SH's partials of (rh, s) (pstride npart)
     double2 *rho, *alpha, *omega, *beta;
     double *rr, *tol2;
     int *active, *iters;
     int maxit;
 };
-enum BiFinMode { BF_INIT = 0, BF_ALPHA = 1, BF_OMEGA = 2, BF_BETA = 3 };
+enum BiFinMode { BF_INIT = 0, BF_ALPHA = 1, BF_OMEGA = 2, BF_BETA = 3, BF_OMBETA = 4, BF_CONV = 5 };
 // BF_ALPHA reads (rh, v) from K2 with F_DOTR, BF_OMEGA (t, s) and |t|^2 from K2 with
 // F_DOTX (layout of hop_nq), BF_INIT and BF_BETA the vector kernels' sums.
+// Merged iteration: BF_OMBETA reads (t, s), |t|^2 and (rh, t) from K2 with F_DOTX |
+// F_DOTXH and (rh, s) from BV_SH, and forms omega, rho' = (rh, s) - omega (rh, t) =
+// (rh, s - omega t) and beta before the updates; BF_CONV reads BV_XRP's |r|^2 and
+// decides convergence and breakdown.
 hipError_t launch_bifinish(const BiFinJob* j, int njob, int nblocks, int mode, hipStream_t s);
 
 // wn: LDS window sites per right-hand side of the launch's FP16 jobs (the largest

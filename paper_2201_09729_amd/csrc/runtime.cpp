@@ -143,7 +143,7 @@ double hop_bytes(int prec, int kind, int flags, int Vh, int n) {
         if (flags & F_CG) vec = 6.0;         // in, x, r (r/w), xs (r/w)
     }
     // the shadow residual at the own site: one field shared by every RHS
-    const double shared = (kind == K2 && (flags & F_DOTR)) ? sp : 0.0;
+    const double shared = (kind == K2 && (flags & (F_DOTR | F_DOTXH))) ? sp : 0.0;
     return (double)Vh * (links + clov + shared + vec * sp * n);
 }
 
