@@ -338,10 +338,13 @@ def main():
 
     if not args.no_variants:
         del b, x
+        dlma.dlma_release_cache()
         torch.cuda.empty_cache()
         out["uneven_batch"] = uneven_batch(torch, dlma, synth)
+        dlma.dlma_release_cache()
         torch.cuda.empty_cache()
         out["correlator_error"] = correlator_error(torch, dlma, synth)
+        dlma.dlma_release_cache()
         torch.cuda.empty_cache()
 
     if args.copy_probe:

@@ -66,6 +66,11 @@ extern "C" {
 
 typedef struct dlma_gauge_s* dlma_gauge_t;
 
+/* Frees the device memory the library keeps cached between calls (the work buffers
+ * of solves, eigensolvers and contractions, reused by later calls of the same sizes).
+ * Synchronises the device.  Handles stay valid.  Returns DLMA_OK. */
+int dlma_release_cache(void);
+
 /* Library version string (static storage). */
 const char* dlma_version(void);
 

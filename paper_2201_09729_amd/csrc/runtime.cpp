@@ -195,3 +195,8 @@ void Profiler::collect() {
 }
 
 }  // namespace dlma
+
+extern "C" int dlma_release_cache(void) {
+    dlma::Pool::get().trim();
+    return DLMA_OK;
+}

@@ -72,6 +72,7 @@ def load_library(path: str = LIB_PATH):
     P, I, D = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
     sig = {
         "dlma_version": ([], ctypes.c_char_p),
+        "dlma_release_cache": ([], I),
         "dlma_last_error": ([], ctypes.c_char_p),
         "dlma_load_gauge": ([P, P, D, D, P, P], I),
         "dlma_set_mass": ([P, D, P], I),
@@ -118,6 +119,11 @@ def _dev(t: torch.Tensor, dtype=torch.complex128) -> torch.Tensor:
     if t.dtype != dtype:
         raise ValueError("tensor must be %s" % dtype)
     return t.contiguous()
+
+
+def dlma_release_cache() -> None:
+    """Free the device memory the library caches between calls (synchronises the device)."""
+    _check(load_library().dlma_release_cache())
 
 
 def dlma_version() -> str:

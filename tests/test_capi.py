@@ -60,6 +60,7 @@ def test_argument_validation_without_gpu(lib):
     assert lib.dlma_correlators_grad(None, 0, 1, None, None, 1, 0, 1, None, None, None, None, None, None, None) == -1
     assert lib.dlma_project_noalloc(None, 0, 1, None, None, None, 1, 0, None) == -1
     assert lib.dlma_profile_read(10, None, None, None) == -1  # classes are 0..9
+    assert lib.dlma_release_cache() == 0  # nothing cached: no device call
 
 
 def test_solve_opts_defaults(lib):

@@ -288,36 +288,29 @@ def test_headline_launch_configuration(D, orc):
     assert float(P.abs().max()) < 1e-12
 
 
-def test_correlator_mass_gradient_32x64(D, orc):
+@pytest.fixture(scope="module")
+def c5(D):
     """32^3 x 64, eps 0.2, kappa 0.1215, c_sw 1.3, t' = 0: N = 64 Laplacian modes on every
     timeslice (256 spin-diluted distillation sources) and 8 Z2 wall vectors (32 eta + 32
-    (1 - box) eta).  Mixed FP16 solves through DiracSolve and the contractions through
-    Correlators; d/dm0 of the correlators by the hand-written backward (adjoint
-    contraction, then adjoint g5 D g5 solves), against central finite differences
-    (dm0 = 1e-4) of the same contractions on FP64 solves to 1e-12:
-      dC_V/dm0 and dC_PS/dm0 of the full correlator (11) at Delta = 4, of C_dist at
-      Delta = 8, and a random combination of every piece at Delta in {1, 4, 8, 16}.
-    The right-hand sides run in batches of 8 source groups (32 solves): every piece is a
-    sum over source groups, and the batches' contributions add."""
+    (1 - box) eta), in batches of 8 source groups (32 solves): every piece is a sum over
+    source groups, and the batches' contributions add."""
     dims = (64, 32, 32, 32)
     kappa, csw, nev, t0, nn = 0.1215, 1.3, 64, 0, 8
     T = dims[0]
-    m0v = 1 / (2 * kappa) - 4
     U = synth.gauge_field(dims, 0.2, 5)
     g = D.dlma_load_gauge(cu(U), kappa, csw)
+    del U
     v0 = cu(synth.gaussian_start(dims, T, 605))
     Vall = torch.empty((T, nev) + dims[1:] + (3,), dtype=torch.complex128, device="cuda")
     for ts in range(0, T, 16):
         Vall[ts:ts + 16] = D.dlma_lap_eigs(g, nev, ts, 16, v0[ts:ts + 16])[0]
     del v0
-    print("C5: Laplacian modes on all timeslices", flush=True)
     xi = cu(synth.z2_noise(dims, t0, nn, 1005))
     rng = np.random.default_rng(55)
     wr = np.zeros((2, 7, T))
     for dl in (1, 4, 8, 16):
         wr[:, :, dl] = rng.standard_normal((2, 7))
-    losses = {"V 11 Delta 4": (1, 4, 4), "PS 11 Delta 4": (0, 4, 4), "V C_dist Delta 8": (1, 5, 8),
-              "PS C_dist Delta 8": (0, 5, 8), "random": None}
+    losses = {"V 11 Delta 4": (1, 4, 4), "PS C_dist Delta 8": (0, 5, 8), "random": None}
 
     def weight(key):
         if losses[key] is None:
@@ -343,43 +336,60 @@ def test_correlator_mass_gradient_32x64(D, orc):
             return D.correlators(x, None, None, g, t0, Vall)
         return D.correlators(None, x[:16], x[16:], g, t0, Vall) * half
 
-    # backward: d/dm0 of each loss, summed over the batches
-    grad = {k: 0.0 for k in losses}
+    yield {"g": g, "kappa": kappa, "m0": 1 / (2 * kappa) - 4, "losses": losses, "weight": weight,
+           "batches": batches, "sources": sources, "contract": contract}
+    del Vall, xi
+
+
+def test_correlator_mass_gradient_32x64_backward(D, c5):
+    """The 32^3 x 64 configuration through DiracSolve (mixed FP16 solves) and Correlators:
+    d/dm0 of three losses by the hand-written backward (adjoint contraction, then adjoint
+    g5 D g5 solves): dC_V/dm0 of the full correlator at Delta = 4, dC_PS/dm0 of C_dist at
+    Delta = 8, and a random combination of every piece at Delta in {1, 4, 8, 16}.  The
+    next test checks them against finite differences."""
+    grad = {k: 0.0 for k in c5["losses"]}
     mix = D.default_opts(tol=TOL, prec="mix_fp16")
-    for kind, i in batches:
-        b = sources(kind, i)
-        m0 = torch.tensor(m0v, dtype=torch.float64, requires_grad=True)
-        x = D.dirac_solve(b, m0, g, mix)
-        C = contract(kind, x)
-        for k in losses:
-            (gm,) = torch.autograd.grad((weight(k) * C.real).sum(), m0, retain_graph=True)
+    for kind, i in c5["batches"]:
+        b = c5["sources"](kind, i)
+        m0 = torch.tensor(c5["m0"], dtype=torch.float64, requires_grad=True)
+        x = D.dirac_solve(b, m0, c5["g"], mix)
+        C = c5["contract"](kind, x)
+        for k in c5["losses"]:
+            (gm,) = torch.autograd.grad((c5["weight"](k) * C.real).sum(), m0, retain_graph=True)
             grad[k] += gm.item()
         del b, x, C
         torch.cuda.empty_cache()
-        print("C5: backward batch", kind, i, flush=True)
-    # central finite differences of the same losses, FP64 solves to 1e-12
-    h = 1e-4
+    c5["grad"] = grad
+    assert all(np.isfinite(v) for v in grad.values())
+
+
+def test_correlator_mass_gradient_32x64_vs_finite_differences(D, c5):
+    """The gradients of the previous test against central finite differences (dm0 = 1e-4)
+    of the same contractions on FP64 solves to 1e-12."""
+    if "grad" not in c5:
+        pytest.skip("needs test_correlator_mass_gradient_32x64_backward")
+    g, m0v, h = c5["g"], c5["m0"], 1e-4
     fp64 = D.default_opts(tol=1e-12, prec="fp64")
     Cfd = {}
     for sgn in (1, -1):
         D.dlma_set_mass(g, 1.0 / (2 * (m0v + sgn * h) + 8))
         Ct = 0.0
-        for kind, i in batches:
-            b = sources(kind, i)
+        for kind, i in c5["batches"]:
+            b = c5["sources"](kind, i)
             (x,), st = D.dlma_solve([g], [b], opts=fp64)
             assert all(s_["converged"] for s_ in st)
             with torch.no_grad():
-                Ct = Ct + contract(kind, x)
+                Ct = Ct + c5["contract"](kind, x)
             del b, x
             torch.cuda.empty_cache()
         Cfd[sgn] = Ct
-        print("C5: finite-difference side", sgn, flush=True)
-    D.dlma_set_mass(g, kappa)
+    D.dlma_set_mass(g, c5["kappa"])
     dC = (Cfd[1] - Cfd[-1]) / (2 * h)
-    for k in losses:
-        fd = float((weight(k) * dC.real).sum())
-        print("C5: %-18s adjoint %.10e  finite difference %.10e" % (k, grad[k], fd), flush=True)
-        assert abs(grad[k] - fd) <= 1e-6 * abs(fd) + 1e-9 * float(np.abs(Cfd[1].numpy()).max()), (k, grad[k], fd)
+    for k in c5["losses"]:
+        fd = float((c5["weight"](k) * dC.real).sum())
+        got = c5["grad"][k]
+        print("C5: %-18s adjoint %.10e  finite difference %.10e" % (k, got, fd), flush=True)
+        assert abs(got - fd) <= 1e-6 * abs(fd) + 1e-9 * float(np.abs(Cfd[1].numpy()).max()), (k, got, fd)
 
 
 def test_grad_32x64_fp64(D, orc):
