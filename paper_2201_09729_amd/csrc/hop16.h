@@ -338,15 +338,16 @@ HD float store16(const F16Field& f, uint32_t G16, uint32_t site, const float s[2
 }
 
 // sum conj(a) b over the 12 complex components of two stored sites (binary16 words;
-// the caller multiplies by both scales): exact binary16 products, FP32 sums
+// the caller multiplies by both scales): exact binary16 products, FP32 sums, as
+// v_dot2: re = ar br + ai bi, im = ar bi - ai br = (ar, ai) . (bi, -br)
 HD void dot16(const uint32_t a[12], const uint32_t b[12], float& re, float& im) {
     re = 0.f;
     im = 0.f;
 #pragma unroll
     for (int c = 0; c < 12; ++c) {
-        const float ar = lo16(a[c]), ai = hi16(a[c]), br = lo16(b[c]), bi = hi16(b[c]);
-        re = __builtin_fmaf(ar, br, __builtin_fmaf(ai, bi, re));
-        im = __builtin_fmaf(ar, bi, __builtin_fmaf(-ai, br, im));
+        const half2_t bb = as_h2(b[c]);
+        re = dot2(a[c], bb, re);
+        im = dot2(a[c], (half2_t){bb.y, -bb.x}, im);
     }
 }
 
