@@ -121,6 +121,7 @@ def main():
     ap.add_argument("--lap-nt", type=int, default=16, help="timeslices per eigensolver call for --lap-scaling")
     ap.add_argument("--lap-variants", default="chebyshev,thick_restart,block",
                     help="eigensolver variants for --lap-scaling (chebyshev, thick_restart, block)")
+    ap.add_argument("--dist-noise", type=int, default=64, help="Z2 noise vectors of C for --dist-scan")
     ap.add_argument("--dist-scan", action="store_true",
                     help="C_dist / C against the number of Laplacian modes N on 16^3x32 with the cost-model "
                          "relation of the paper evaluated on measured GPU times, instead of the headline benchmark")
@@ -577,8 +578,11 @@ def dist_scan(args):
     Figs. 3-5 and the cost relations of eqs. 6-9), on the synthetic 16^3 x 32 field
     (eps 0.25, seed 3, kappa 0.121, c_sw 1.2), source timeslice 0.
 
-    C is the one-end estimate of the full correlator from R_1 spin-diluted Z2 noise
-    solves; C_dist(N) is exact from the perambulator of the first N modes.  Times are
+    C is the one-end estimate of the full correlator from --dist-noise Z2 noise vectors
+    (spin-diluted: 4 solves each; 64 by default, so that its own noise stays below the
+    ratios at the larger distances); C_dist(N) is exact from the perambulator of the
+    first N modes.  The cost relation takes R_1 = 32 stochastic solves (8 vectors x 4
+    spins, as in the headline workload).  Times are
     measured on the GPU: t_lap(N) (modes of every timeslice), the per-right-hand-side
     time of the batched mixed-precision solve, from which t_{N,D} = 4N * t_rhs and
     t_{R,D} = R * t_rhs.  Equal cost, eq. (6): R_0 = (t_lap + t_{N,D}) / t_rhs + 2 R_1
@@ -587,7 +591,7 @@ def dist_scan(args):
     from paper_2201_09729_amd import dlma, synth
     dims = (32, 16, 16, 16)
     T = dims[0]
-    t0, nnoise = 0, 8
+    t0, nnoise = 0, args.dist_noise
     nlist = [8, 16, 32, 64, 128]
     nmax = max(nlist)
     dlma.load_library()
@@ -621,7 +625,7 @@ def dist_scan(args):
     assert all(s_["converged"] for s_ in st)
     log("batched solve of %d right-hand sides: %.3f ms per right-hand side" % (b.shape[0], 1e3 * t_rhs))
     nd = 4 * nmax
-    R1 = 4 * nnoise  # stochastic solves (spin-diluted) per estimate
+    R1 = 32  # stochastic solves (spin-diluted) of one estimate in the cost relation
     rows = []
     for nev in nlist:
         C = dlma.dlma_correlators(g, t0, Vall[:, :nev].contiguous(), x[:4 * nev], x[nd:], x[nd:])
