@@ -187,3 +187,26 @@ def test_correlator_mass_gradient_chain(D, orc):
     got = m0.grad.item()
     assert abs(got - ref) <= 1e-9 * abs(ref), (got, ref)
     assert abs(got - fd) <= 1e-6 * abs(fd), (got, fd)
+
+
+def test_correlators_add_over_source_batches(D, orc):
+    """Every piece is a sum over source groups: contracting the distillation solutions in
+    two batches (fewer groups than modes) and the noise in two halves (each half
+    averaging its own vectors) and adding the results gives the single contraction."""
+    dims = (4, 4, 4, 4)
+    T, t0, nev = dims[0], 2, 4
+    U = synth.gauge_field(dims, 0.3, 6)
+    Vall = np.stack([orc.lap_eigs(U, t, nev, synth.gaussian_start(dims, 1, 30 + t)[0], tol=1e-12)[1] for t in range(T)])
+    pd = cu(synth.random_spinor(dims, 4 * nev, 31))
+    p1 = cu(synth.random_spinor(dims, 16, 32))
+    pq = cu(synth.random_spinor(dims, 16, 33))
+    g = D.dlma_load_gauge(cu(U), 0.120, 1.0)
+    Vg = cu(Vall)
+    full = D.dlma_correlators_array(g, t0, Vg, pd, p1, pq)
+    parts = (D.dlma_correlators_array(g, t0, Vg, pd[:4], None, None) + D.dlma_correlators_array(g, t0, Vg, pd[4:], None, None))
+    halves = D.dlma_correlators_array(g, t0, Vg, None, p1[:8], pq[:8]) + D.dlma_correlators_array(g, t0, Vg, None, p1[8:], pq[8:])
+    est = halves / 2.0  # each half averaged 2 of the 4 noise vectors
+    sc = np.max(np.abs(full))
+    assert np.max(np.abs(full[:, 5:] - parts[:, 5:])) <= 1e-13 * sc  # exact pieces: distillation solutions only
+    assert np.max(np.abs(full[:, :5] - est[:, :5])) <= 1e-13 * sc    # estimators: noise solutions only
+    assert np.max(np.abs(parts[:, :5])) == 0.0 and np.max(np.abs(halves[:, 5:])) == 0.0
