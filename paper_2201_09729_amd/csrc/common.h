@@ -164,6 +164,27 @@ template <int P, class R> HD void load_spinor(const SF<P>& f, int Vh, int r, int
     }
 }
 
+// An FP16-stored site widened to FP64 and multiplied by fac: component = binary16
+// value * (scale * fac), where the binary16 value times the FP32 scale is exact in
+// FP64 and (scale * fac) is rounded once.  Every FP64 consumer of the same stored
+// field (the accumulation into x and the odd-site reconstruction) goes through this
+// one function, so all of them see bit-identical values.  The three 16-byte word
+// groups load as one 128-bit access each.
+HD void load_spinor16_f64(const SF<P16>& f, int Vh, int r, int cb, double fac, double s[24]) {
+    const double n = (double)f.nrm[(size_t)r * f.ns + cb] * fac;
+    const uint4* q = (const uint4*)(f.v + (size_t)r * f.rs);
+#pragma unroll
+    for (int g = 0; g < 3; ++g) {
+        const uint4 v = q[(size_t)g * Vh + cb];
+        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            s[8 * g + 2 * k] = (double)h_to_f(w[k] & 0xffffu) * n;
+            s[8 * g + 2 * k + 1] = (double)h_to_f(w[k] >> 16) * n;
+        }
+    }
+}
+
 template <int P, class R> HD void store_spinor(const SF<P>& f, int Vh, int r, int cb, const R s[24]) {
     if constexpr (P == P16) {
         float m = 0.f;

@@ -35,6 +35,7 @@ enum HopFlags {
     F_DOTX = 256,   // K2: partials of sum conj(out) x (re, im) and |out|^2
     F_DOTR = 512,   // K2: partials of sum conj(r) out (re, im), r the job's r field
     F_DOTXH = 1024, // K2, FP16, with F_DOTX: also sum conj(r) out of the stored (rounded) out (re, im)
+    F_IN16 = 2048,  // FP64 kernels: the hopping input is the FP16 field in16 times sqrt(in16s[r])
 };
 
 // Partial sums a stencil launch writes per right-hand side: F_DOTX | F_DOTXH 5,
@@ -59,6 +60,8 @@ template <int P> struct HopJob {
     const typename PT<P>::S* U;  // links, all parities
     const typename PT<P>::S* C;  // clover blocks of the output parity (A or A^-1)
     SF<P> in, x, b, out, r, xs;
+    SF<P16> in16;         // F_IN16: hopping input in FP16 storage (grouped words, site scales)
+    const double* in16s;  // F_IN16: [nrhs] squared factor of in16
     const double* alpha;  // [nrhs] (F_CG)
     const int* active;    // [nrhs] or nullptr: inactive right-hand sides are skipped
     double* part;         // partial squared norms (F_NORM / F_CG): part[r * pstride + site block]
@@ -98,8 +101,16 @@ template <int P, class R> HD void load_half_spinor(const SF<P>& f, int Vh, int r
     }
 }
 
-template <int P, int NB, int MU, bool G5IN>
-HD void hop_dir(const HopJob<P>& J, const Nbr& nb, int cb, int g0, bool (&use)[NB],
+// The hopping input of right-hand side r at site cb: the job's field, or with IN16
+// (FP64 kernels) the FP16 field in16 times fac.
+template <int P, bool IN16, class R>
+HD void load_input(const HopJob<P>& J, int Vh, int r, int cb, double fac, R psi[24]) {
+    if constexpr (IN16 && P == P64) load_spinor16_f64(J.in16, Vh, r, cb, fac, psi);
+    else load_spinor<P, R>(J.in, Vh, r, cb, psi);
+}
+
+template <int P, int NB, int MU, bool G5IN, bool IN16>
+HD void hop_dir(const HopJob<P>& J, const Nbr& nb, int cb, int g0, bool (&use)[NB], const double (&fac)[NB],
                 typename PT<P>::R (&acc)[NB][24]) {
     using R = typename PT<P>::R;
     const int Vh = J.g.Vh;
@@ -109,14 +120,14 @@ HD void hop_dir(const HopJob<P>& J, const Nbr& nb, int cb, int g0, bool (&use)[N
 #pragma unroll
     for (int j = 0; j < NB; ++j)
         if (use[j]) {
-            load_spinor<P, R>(J.in, Vh, g0 + j, nb.n[2 * MU], psi);
+            load_input<P, IN16, R>(J, Vh, g0 + j, nb.n[2 * MU], fac[j], psi);
             hop_term<MU, true, G5IN, R>(u, psi, acc[j]);
         }
     load_link<P, R>(J.U, Vh, 1 - J.par, MU, nb.n[2 * MU + 1], u);
 #pragma unroll
     for (int j = 0; j < NB; ++j)
         if (use[j]) {
-            load_spinor<P, R>(J.in, Vh, g0 + j, nb.n[2 * MU + 1], psi);
+            load_input<P, IN16, R>(J, Vh, g0 + j, nb.n[2 * MU + 1], fac[j], psi);
             hop_term<MU, false, G5IN, R>(u, psi, acc[j]);
         }
 }
@@ -143,10 +154,15 @@ HD void hop_site(const HopJob<P>& J, int cb, int g0, double (&qs)[NB][HOP_NQ_MAX
 
     Nbr nb = neighbours(J.g, J.par, cb);
     constexpr bool G5IN = (FL & F_G5IN) != 0;
-    hop_dir<P, NB, 0, G5IN>(J, nb, cb, g0, use, acc);
-    hop_dir<P, NB, 1, G5IN>(J, nb, cb, g0, use, acc);
-    hop_dir<P, NB, 2, G5IN>(J, nb, cb, g0, use, acc);
-    hop_dir<P, NB, 3, G5IN>(J, nb, cb, g0, use, acc);
+    constexpr bool IN16 = (FL & F_IN16) != 0;
+    static_assert(!IN16 || P == P64, "an FP16 hopping input is for the FP64 kernels");
+    double fac[NB];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) fac[j] = (IN16 && use[j]) ? sqrt(J.in16s[g0 + j]) : 1.0;
+    hop_dir<P, NB, 0, G5IN, IN16>(J, nb, cb, g0, use, fac, acc);
+    hop_dir<P, NB, 1, G5IN, IN16>(J, nb, cb, g0, use, fac, acc);
+    hop_dir<P, NB, 2, G5IN, IN16>(J, nb, cb, g0, use, fac, acc);
+    hop_dir<P, NB, 3, G5IN, IN16>(J, nb, cb, g0, use, fac, acc);
 
     const R ch = (R)J.ch;
     if (KIND == K1) {

@@ -44,6 +44,9 @@ hipError_t launch_hop<DLMA_PREC>(const HopCfg& c, const HopJob<DLMA_PREC>* djobs
     DLMA_HOP_ALLNB(K2, F_NOA)
     DLMA_HOP_ALLNB(K1, F_HASD | F_ACCUM)
     DLMA_HOP_ALLNB(K1, F_ACCUM)
+    // reconstruction after an FP16 inner solve, which reads the FP16 solution itself
+    DLMA_HOP_ALLNB(K1, F_HASD | F_ACCUM | F_IN16)
+    DLMA_HOP_ALLNB(K1, F_ACCUM | F_IN16)
 #endif
     return hipErrorInvalidValue;
 }

@@ -509,19 +509,27 @@ template <int P> __global__ void __launch_bounds__(VEC_BS) k_accum_to64(const Ve
     vec_locate(jobs, njob, J, r, cb, sb);
     if (cb >= J->Vh) return;
     const VecJob<P64>* S = &j64[J - jobs];
+    // S->a receives the FP64 copy of the correction; a null view skips it (the FP16
+    // solves' reconstruction reads the FP16 field itself, through load_spinor16_f64)
+    const bool keep = S->a.v != nullptr;
     if (J->active && !J->active[r]) {
         double z[24];
         for (int i = 0; i < 24; ++i) z[i] = 0.0;
-        store_spinor<P64, double>(S->a, J->Vh, r, cb, z);
+        if (keep) store_spinor<P64, double>(S->a, J->Vh, r, cb, z);
         return;
     }
-    typename PT<P>::R e[24];
-    load_spinor<P, typename PT<P>::R>(J->a, J->Vh, r, cb, e);
     double sc = sqrt(J->s[r]);
     double ed[24], x[24];
+    if constexpr (P == P16) {
+        load_spinor16_f64(J->a, J->Vh, r, cb, sc, ed);
+    } else {
+        typename PT<P>::R e[24];
+        load_spinor<P, typename PT<P>::R>(J->a, J->Vh, r, cb, e);
+        for (int i = 0; i < 24; ++i) ed[i] = (double)e[i] * sc;
+    }
     load_spinor<P64, double>(S->b, J->Vh, r, cb, x);
-    for (int i = 0; i < 24; ++i) { ed[i] = (double)e[i] * sc; x[i] += ed[i]; }
-    store_spinor<P64, double>(S->a, J->Vh, r, cb, ed);
+    for (int i = 0; i < 24; ++i) x[i] += ed[i];
+    if (keep) store_spinor<P64, double>(S->a, J->Vh, r, cb, ed);
     store_spinor<P64, double>(S->b, J->Vh, r, cb, x);
 }
 

@@ -252,8 +252,8 @@ def test_headline_launch_configuration(D, orc):
     eta = D.noise_sources(cu(synth.z2_noise(dims, t0, nn, 1006)), T, t0)
     b = torch.cat([D.dist_sources(V[0], T, t0), eta, D.dlma_project(g, t0, V[0], eta, 1)])
     del eta
-    # one defect-correction pass brings every right-hand side to the inner tolerance's
-    # level (2e-3).  A corrupted store in the solution update made the first right-hand
+    # one defect-correction pass brings every right-hand side to within a few times the
+    # inner tolerance (1e-3 for FP16).  A corrupted store in the solution update made the first right-hand
     # side of every 2-RHS group about 15x worse than the others.  Measured spread of one
     # pass, as max / median per source kind: CGNE 1.06 .. 1.15, BiCGStab 1.20 .. 1.77;
     # first / second RHS of a group, median over groups: 0.98 .. 1.00.
