@@ -70,13 +70,34 @@ HD void wide_store_end() {
 
 // load / store one complex element
 template <int P> HD void ldp(const typename PT<P>::S* a, size_t i, typename PT<P>::R& re, typename PT<P>::R& im);
-template <> HD void ldp<P64>(const double2* a, size_t i, double& re, double& im) { double2 v = a[i]; re = v.x; im = v.y; }
+// FP64 fields are global memory: addressed as such, the loads and stores are
+// global_* instructions, which count against the vector-memory counter only (a flat
+// access also counts against the LDS/scalar counter that the scalar loads wait on).
+#if defined(__HIP_DEVICE_COMPILE__)
+typedef const __attribute__((address_space(1))) double2* GlobalD2;
+typedef __attribute__((address_space(1))) double2* GlobalD2w;
+#endif
+template <> HD void ldp<P64>(const double2* a, size_t i, double& re, double& im) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    const double2 v = ((GlobalD2)a)[i];
+#else
+    const double2 v = a[i];
+#endif
+    re = v.x;
+    im = v.y;
+}
 template <> HD void ldp<P32>(const float2* a, size_t i, float& re, float& im) { float2 v = a[i]; re = v.x; im = v.y; }
 template <> HD void ldp<P16>(const uint32_t* a, size_t i, float& re, float& im) { uint32_t v = a[i]; re = h_to_f(v & 0xffffu); im = h_to_f(v >> 16); }
 template <> HD void ldp<PB16>(const uint32_t* a, size_t i, float& re, float& im) { uint32_t v = a[i]; re = bf16_to_f(v & 0xffffu); im = bf16_to_f(v >> 16); }
 
 template <int P> HD void stp(typename PT<P>::S* a, size_t i, typename PT<P>::R re, typename PT<P>::R im);
-template <> HD void stp<P64>(double2* a, size_t i, double re, double im) { a[i] = make_double2(re, im); }
+template <> HD void stp<P64>(double2* a, size_t i, double re, double im) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    ((GlobalD2w)a)[i] = make_double2(re, im);
+#else
+    a[i] = make_double2(re, im);
+#endif
+}
 template <> HD void stp<P32>(float2* a, size_t i, float re, float im) { a[i] = make_float2(re, im); }
 template <> HD void stp<P16>(uint32_t* a, size_t i, float re, float im) { a[i] = f_to_h(re) | (f_to_h(im) << 16); }
 template <> HD void stp<PB16>(uint32_t* a, size_t i, float re, float im) { a[i] = f_to_bf16(re) | (f_to_bf16(im) << 16); }
@@ -172,7 +193,11 @@ template <int P, class R> HD void load_spinor(const SF<P>& f, int Vh, int r, int
 // groups load as one 128-bit access each.
 HD void load_spinor16_f64(const SF<P16>& f, int Vh, int r, int cb, double fac, double s[24]) {
     const double n = (double)f.nrm[(size_t)r * f.ns + cb] * fac;
+#if defined(__HIP_DEVICE_COMPILE__)
+    const __attribute__((address_space(1))) uint4* q = (const __attribute__((address_space(1))) uint4*)(f.v + (size_t)r * f.rs);
+#else
     const uint4* q = (const uint4*)(f.v + (size_t)r * f.rs);
+#endif
 #pragma unroll
     for (int g = 0; g < 3; ++g) {
         const uint4 v = q[(size_t)g * Vh + cb];

@@ -26,23 +26,32 @@ struct LapMode {
 
 // out = -lap(t) in = 6 in - sum_j [U_j(m,t) in(m+j) + U_j(m-j,t)^dag in(m-j)],  j = x, y, z,
 // for nv vectors on each of nt timeslices: vector (tl, kv) at base + tl*tstride + kv*vstride.
-// Grid: (site blocks of one timeslice, nv, nt).
+// Grid: (site blocks of one timeslice, ceil(nv / VPT), nt).  Each thread takes VPT
+// vectors at one site: the six links of the site are loaded once and applied to all
+// of them, which halves the load instructions per vector at VPT = 4 (the kernel is
+// bound by the texture address path, like the stencils).  The partials of qd are
+// for nv = 1 (one vector per timeslice).
+template <int VPT>
 __global__ void __launch_bounds__(256) k_neg_lap(const double2* __restrict__ U64, Geo g, int t0, const double2* __restrict__ in,
                                                  double2* __restrict__ out, long tstride_in, long tstride_out, long vstride_in,
-                                                 long vstride_out, LapMode md) {
+                                                 long vstride_out, int nv, LapMode md) {
     const int L3 = g.Z * g.Y * g.X;
     const int m = blockIdx.x * blockDim.x + threadIdx.x;
-    const int kv = blockIdx.y, tl = blockIdx.z;
+    const int kv0 = blockIdx.y * VPT, tl = blockIdx.z;
+    const int nk = min(VPT, nv - kv0);  // uniform over the block
     double dq = 0.0;
     if (m < L3) {
         const int t = t0 + tl;
         int x = m % g.X, y = (m / g.X) % g.Y, z = m / (g.X * g.Y);
-        const double2* v = in + tl * tstride_in + kv * vstride_in;
-        double2 acc[3];
-        for (int a = 0; a < 3; ++a) {
-            double2 q = v[(long)m * 3 + a];
-            acc[a] = make_double2(6.0 * q.x, 6.0 * q.y);
-        }
+        const double2* v = in + tl * tstride_in + kv0 * vstride_in;
+        double2 acc[VPT][3];
+#pragma unroll
+        for (int i = 0; i < VPT; ++i)
+            if (i < nk)
+                for (int a = 0; a < 3; ++a) {
+                    double2 q = v[i * vstride_in + (long)m * 3 + a];
+                    acc[i][a] = make_double2(6.0 * q.x, 6.0 * q.y);
+                }
         for (int j = 1; j <= 3; ++j) {
             int xf = x, yf = y, zf = z, xb = x, yb = y, zb = z;
             if (j == 1) { xf = x + 1 == g.X ? 0 : x + 1; xb = x == 0 ? g.X - 1 : x - 1; }
@@ -55,34 +64,44 @@ __global__ void __launch_bounds__(256) k_neg_lap(const double2* __restrict__ U64
             long cbb = (((long)t * g.Z + zb) * g.Y + yb) * g.Xh + (xb >> 1);
             const double2* uf = U64 + ((size_t)(par * 4 + j) * 9) * g.Vh + cb;
             const double2* ub = U64 + ((size_t)(parb * 4 + j) * 9) * g.Vh + cbb;
-            double2 vf[3], vb[3];
-            for (int b = 0; b < 3; ++b) { vf[b] = v[(long)mf * 3 + b]; vb[b] = v[(long)mb * 3 + b]; }
-            for (int a = 0; a < 3; ++a) {
-                double2 s = make_double2(0, 0);
-                for (int b = 0; b < 3; ++b) {
-                    double2 u = uf[(size_t)(a * 3 + b) * g.Vh];
-                    double2 p = cmul2(u, vf[b]);
-                    double2 w = ub[(size_t)(b * 3 + a) * g.Vh];  // (U^dag)_{ab} = conj(U_{ba})
-                    double2 q = cconjmul(w, vb[b]);
-                    s.x += p.x + q.x;
-                    s.y += p.y + q.y;
+            double2 u[9], w[9];
+#pragma unroll
+            for (int e = 0; e < 9; ++e) { u[e] = uf[(size_t)e * g.Vh]; w[e] = ub[(size_t)e * g.Vh]; }
+#pragma unroll
+            for (int i = 0; i < VPT; ++i)
+                if (i < nk) {
+                    const double2* vi = v + i * vstride_in;
+                    double2 vf[3], vb[3];
+                    for (int b = 0; b < 3; ++b) { vf[b] = vi[(long)mf * 3 + b]; vb[b] = vi[(long)mb * 3 + b]; }
+                    for (int a = 0; a < 3; ++a) {
+                        double2 sm = make_double2(0, 0);
+                        for (int b = 0; b < 3; ++b) {
+                            double2 p = cmul2(u[a * 3 + b], vf[b]);
+                            double2 q = cconjmul(w[b * 3 + a], vb[b]);  // (U^dag)_{ab} = conj(U_{ba})
+                            sm.x += p.x + q.x;
+                            sm.y += p.y + q.y;
+                        }
+                        acc[i][a].x -= sm.x;
+                        acc[i][a].y -= sm.y;
+                    }
                 }
-                acc[a].x -= s.x;
-                acc[a].y -= s.y;
-            }
         }
-        double2* o = out + tl * tstride_out + kv * vstride_out;
-        if (md.cheb) {
-            const double2* pv = md.prev ? md.prev + tl * md.tsp + kv * vstride_in : nullptr;
-            for (int a = 0; a < 3; ++a) {
-                double2 q = v[(long)m * 3 + a], pr = pv ? pv[(long)m * 3 + a] : make_double2(0.0, 0.0);
-                acc[a] = make_double2(md.c2 * (md.c1 * q.x - acc[a].x) - pr.x, md.c2 * (md.c1 * q.y - acc[a].y) - pr.y);
+#pragma unroll
+        for (int i = 0; i < VPT; ++i)
+            if (i < nk) {
+                double2* o = out + tl * tstride_out + (kv0 + i) * vstride_out;
+                if (md.cheb) {
+                    const double2* pv = md.prev ? md.prev + tl * md.tsp + (kv0 + i) * vstride_in : nullptr;
+                    for (int a = 0; a < 3; ++a) {
+                        double2 q = v[i * vstride_in + (long)m * 3 + a], pr = pv ? pv[(long)m * 3 + a] : make_double2(0.0, 0.0);
+                        acc[i][a] = make_double2(md.c2 * (md.c1 * q.x - acc[i][a].x) - pr.x, md.c2 * (md.c1 * q.y - acc[i][a].y) - pr.y);
+                    }
+                }
+                for (int a = 0; a < 3; ++a) o[(long)m * 3 + a] = acc[i][a];
             }
-        }
-        for (int a = 0; a < 3; ++a) o[(long)m * 3 + a] = acc[a];
         if (md.qd) {
             const double2* pq = md.qd + tl * md.tsqd + (long)m * 3;
-            for (int a = 0; a < 3; ++a) dq += pq[a].x * acc[a].x + pq[a].y * acc[a].y;
+            for (int a = 0; a < 3; ++a) dq += pq[a].x * acc[0][a].x + pq[a].y * acc[0][a].y;
         }
     }
     if (md.qd) {  // uniform over the grid
@@ -92,14 +111,29 @@ __global__ void __launch_bounds__(256) k_neg_lap(const double2* __restrict__ U64
     }
 }
 
+// vectors per thread of a launch over nv vectors
+constexpr int LAP_VPT = 4;
+static hipError_t launch_lap(const double2* U64, const Geo& g, int t0, const double2* in, double2* out, long tsi, long tso,
+                             int nt, int nv, long vsi, long vso, const LapMode& md, hipStream_t s);
+
 int lap_site_blocks(const Geo& g) { return (g.Z * g.Y * g.X + 255) / 256; }
 
 hipError_t launch_neg_lap(const double2* U64, const Geo& g, int t0, const double2* in, double2* out, long tsi, long tso,
                           int nt, hipStream_t s, int nv, long vsi, long vso, const double2* qd, double* part) {
     if (nt <= 0 || nv <= 0) return hipSuccess;
     LapMode md = {0, 0.0, 0.0, nullptr, 0L, qd, tsi, part};
-    hipLaunchKernelGGL(k_neg_lap, dim3((unsigned)lap_site_blocks(g), nv, nt), dim3(256), 0, s, U64, g, t0, in, out, tsi, tso,
-                       vsi, vso, md);
+    return launch_lap(U64, g, t0, in, out, tsi, tso, nt, nv, vsi, vso, md, s);
+}
+
+static hipError_t launch_lap(const double2* U64, const Geo& g, int t0, const double2* in, double2* out, long tsi, long tso,
+                             int nt, int nv, long vsi, long vso, const LapMode& md, hipStream_t s) {
+    if (nv == 1 || md.qd) {  // partials of qd: one vector per thread
+        hipLaunchKernelGGL(k_neg_lap<1>, dim3((unsigned)lap_site_blocks(g), nv, nt), dim3(256), 0, s, U64, g, t0, in, out, tsi,
+                           tso, vsi, vso, nv, md);
+    } else {
+        hipLaunchKernelGGL(k_neg_lap<LAP_VPT>, dim3((unsigned)lap_site_blocks(g), (nv + LAP_VPT - 1) / LAP_VPT, nt), dim3(256),
+                           0, s, U64, g, t0, in, out, tsi, tso, vsi, vso, nv, md);
+    }
     return hipGetLastError();
 }
 
@@ -109,9 +143,7 @@ hipError_t launch_cheb_step(const double2* U64, const Geo& g, int t0, const doub
                             double* part) {
     if (nt <= 0) return hipSuccess;
     LapMode md = {1, c1, c2, prev, tsp, qd, tsqd, part};
-    hipLaunchKernelGGL(k_neg_lap, dim3((unsigned)lap_site_blocks(g), 1, nt), dim3(256), 0, s, U64, g, t0, in, out, tsi, tso, 0L,
-                       0L, md);
-    return hipGetLastError();
+    return launch_lap(U64, g, t0, in, out, tsi, tso, nt, 1, 0L, 0L, md, s);
 }
 
 // Per vector: lambda = Re <y, Ay> (y normalised), then |Ay - lambda y|; one block per vector
@@ -437,9 +469,7 @@ hipError_t launch_cheb_block(const double2* U64, const Geo& g, int t0, const dou
     if (nt <= 0 || kb <= 0) return hipSuccess;
     const long n = 3L * g.Z * g.Y * g.X;
     LapMode md = {1, c1, c2, prev, (long)kb * n, nullptr, 0L, nullptr};
-    hipLaunchKernelGGL(k_neg_lap, dim3((unsigned)lap_site_blocks(g), kb, nt), dim3(256), 0, s, U64, g, t0, in, out,
-                       (long)kb * n, (long)kb * n, n, n, md);
-    return hipGetLastError();
+    return launch_lap(U64, g, t0, in, out, (long)kb * n, (long)kb * n, nt, kb, n, n, md, s);
 }
 
 // Gram partials: part[t][c][i][j] = sum over rows of chunk c of conj(A_i[e]) B_j[e], i, j < kb.
