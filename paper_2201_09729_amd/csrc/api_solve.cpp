@@ -52,6 +52,7 @@ struct Cfg {
     Buf r, p, w, xs, y;              // inner vectors (precision P), half fields
     Buf nr, np, nw, nxs, ny;         // FP16 scales
     Buf part;                        // partial norms
+    Buf tsup;                        // [nrhs][T] timeslice support of B (VecJob::tsup)
     Buf parts;                       // BiCGStab, FP16: partials of (rh, s) from the s step
     Buf bs, bt, brh, nbs, nbt, nbrh;    // BiCGStab: s, t, shadow residual (precision P) and FP16 scales
     Buf bstate;                      // BiCGStab: rho alpha omega beta (complex, per rhs)
@@ -74,6 +75,7 @@ template <int P> struct Tables {
     Buf dvnB, dclov, dconv64, dacc64, dclov0;  // VecJob<P64>
     Buf dconv, dacc, dxpay;                    // VecJob<P>
     Buf dvnE, dfinE;                           // |E|^2 (Schur source) jobs
+    Buf dvnE0, dconv640;                       // pass 0 from x = 0: the same, skipping where B vanishes
     Buf dk1d, dk2d, dk1, dk2cg;                // HopJob<P>
     Buf dfinB, dfinR, dfinI, dfinAB;           // FinJob
     int nresid = 0, nprep = 0, nrecon = 0, nvnB = 0, nclov = 0, nconv = 0, nk = 0, nfin = 0, nresidE = 0, bresidE = 0;
@@ -103,6 +105,7 @@ template <int P> int alloc_cfg(Cfg& c, bool bicg, hipStream_t s) {
     size_t full64 = sizeof(double2) * n * 24 * Vh, half64 = sizeof(double2) * n * 12 * Vh;
     DLMA_TRY(c.B.allocate(full64));
     DLMA_TRY(c.X.allocate(full64));
+    DLMA_TRY(c.tsup.allocate(sizeof(int) * (size_t)c.nrhs * g->geo.T));
     DLMA_TRY(c.R.allocate(full64));
     DLMA_TRY(c.T.allocate(half64));
     DLMA_TRY(c.E.allocate(half64));
@@ -161,7 +164,7 @@ template <int P> float* nrm_of(const Buf& b) { return P == P16 ? b.as<float>() :
 
 template <int P> int build_tables(std::vector<Cfg>& cs, Tables<P>& t, int nb, int sg_in, int win, int nb64, int sg64, hipStream_t s) {
     std::vector<HopJob<P64>> resid, prep, recon, residE, residO, prep0, recon0;
-    std::vector<VecJob<P64>> vnB, clov, conv64, acc64, vnE, clov0;
+    std::vector<VecJob<P64>> vnB, clov, conv64, acc64, vnE, clov0, vnE0, conv640;
     std::vector<VecJob<P>> conv, acc, xpay;
     std::vector<HopJob<P>> k1d, k2d, k1, k2cg, bk1p, bk2v, bk1s, bk2t;
     std::vector<FinJob> finB, finR, finI, finAB, finE;
@@ -172,12 +175,21 @@ template <int P> int build_tables(std::vector<Cfg>& cs, Tables<P>& t, int nb, in
         Gauge* g = c.g;
         int Vh = g->Vh, n = c.nrhs;
         const double2* U64 = g->U64.as<double2>();
+        int* tsup = c.tsup.as<int>();
+        const int vt = g->geo.Z * g->geo.Y * g->geo.Xh, T = g->geo.T;
+        // the support flags of B on a vector job; dil: the job's input vanishes where
+        // t - dil .. t + dil are unflagged
+        auto with_support = [&](VecJob<P64> v, int dil) {
+            v.tsup = tsup; v.tdil = dil; v.vt = vt; v.T = T;
+            return v;
+        };
         for (int par = 0; par < 2; ++par) {
             HopJob<P64> j = hop_job<P64>(g, par, n, nb64);
             j.sg = sg64;
             j.U = U64;
             j.C = g->Cl64[par].as<double2>();
             j.b = full_view(c.B.p, Vh, par);
+            j.tsup = tsup;  // b is read where B is nonzero only
             j.x = full_view(c.X.p, Vh, par);
             j.in = full_view(c.X.p, Vh, 1 - par);
             j.out = full_view(c.R.p, Vh, par);
@@ -197,6 +209,8 @@ template <int P> int build_tables(std::vector<Cfg>& cs, Tables<P>& t, int nb, in
             v.a = full_view(c.B.p, Vh, par);
             v.part = c.part.as<double>() + (size_t)par * c.vnsb;
             v.pstride = 2 * c.vnsb;
+            v.tsup_out = tsup;  // |B|^2 also records where B is nonzero
+            v.vt = vt; v.T = T;
             vnB.push_back(v);
         }
         {   // T = A_oo^-1 R_o
@@ -207,7 +221,7 @@ template <int P> int build_tables(std::vector<Cfg>& cs, Tables<P>& t, int nb, in
             v.C = g->Ci64.as<double2>();
             clov.push_back(v);
             v.a = full_view(c.B.p, Vh, 1);  // first pass from x = 0: R = B
-            clov0.push_back(v);
+            clov0.push_back(with_support(v, 0));
         }
         {   // E = R_e + 1/2 H T
             HopJob<P64> j = hop_job<P64>(g, 0, n, nb64);
@@ -219,6 +233,7 @@ template <int P> int build_tables(std::vector<Cfg>& cs, Tables<P>& t, int nb, in
             j.ca = 1.0; j.ch = 0.5;
             prep.push_back(j);
             j.x = full_view(c.B.p, Vh, 0);
+            j.tsup = tsup;  // E = 0 where B vanishes on t - 1 .. t + 1
             prep0.push_back(j);
         }
         {   // r = p = P(E), xs = 0 ; and accumulate E = xs, X_e += E
@@ -236,10 +251,12 @@ template <int P> int build_tables(std::vector<Cfg>& cs, Tables<P>& t, int nb, in
             v64.Vh = Vh; v64.nrhs = n; v64.nsb = c.vnsb;
             v64.a = half_view<P64>(c.E.p, nullptr, Vh);
             conv64.push_back(v64);
+            conv640.push_back(with_support(v64, 1));
             VecJob<P64> e64 = v64;
             e64.part = c.part.as<double>();
             e64.pstride = c.vnsb;
             vnE.push_back(e64);
+            vnE0.push_back(with_support(e64, 1));
             VecJob<P> a = v;
             a.a = half_view<P>(c.xs.p, nrm_of<P>(c.nxs), Vh);
             acc.push_back(a);
@@ -270,6 +287,7 @@ template <int P> int build_tables(std::vector<Cfg>& cs, Tables<P>& t, int nb, in
             j.active = c.oact;  // E = 0 for the others
             recon.push_back(j);
             j.x = full_view(c.B.p, Vh, 1);
+            j.tsup = tsup;  // d = B_o is read where B is nonzero only
             recon0.push_back(j);
         }
         {   // inner CG stencils
@@ -338,6 +356,8 @@ template <int P> int build_tables(std::vector<Cfg>& cs, Tables<P>& t, int nb, in
     t.bvnB = assign_vec_blocks(vnB); t.bclov = assign_vec_blocks(clov);
     t.bconv = assign_vec_blocks(conv); assign_vec_blocks(conv64); assign_vec_blocks(acc); assign_vec_blocks(acc64);
     t.bvnE = assign_vec_blocks(vnE);
+    assign_vec_blocks(vnE0); assign_vec_blocks(conv640);
+    DLMA_TRY(upload(t.dvnE0, vnE0, s)); DLMA_TRY(upload(t.dconv640, conv640, s));
     t.bxpay = assign_vec_blocks(xpay);
     t.bk1 = assign_blocks(k1d); assign_blocks(k1);
     t.bk2 = assign_blocks(k2d); assign_blocks(k2cg);
@@ -542,6 +562,7 @@ int solve_impl(std::vector<Cfg>& cs, const dlma_solve_opts& o, hipStream_t s) {
         DLMA_HIP(launch_canon_to_eo(c.bcan, c.B.as<double2>(), c.g->geo, c.nrhs, s, o.dagger));
         if (o.use_x0) DLMA_HIP(launch_canon_to_eo(c.xcan, c.X.as<double2>(), c.g->geo, c.nrhs, s, o.dagger));
         else DLMA_HIP(hipMemsetAsync(c.X.p, 0, c.X.n, s));
+        DLMA_HIP(hipMemsetAsync(c.tsup.p, 0, c.tsup.n, s));  // set by the norm of B
     }
     DLMA_HIP(launch_norm<P64>(t.dvnB.template as<VecJob<P64>>(), t.nvnB, t.bvnB, s));
     DLMA_HIP(launch_finish(t.dfinB.template as<FinJob>(), t.nfin, t.bfin, FIN_NORM, s));
@@ -707,10 +728,11 @@ int solve_impl(std::vector<Cfg>& cs, const dlma_solve_opts& o, hipStream_t s) {
             DLMA_HIP(launch_clover_apply64((from_b ? t.dclov0 : t.dclov).template as<VecJob<P64>>(), t.nclov, t.bclov, s));
             DLMA_HIP(launch_hop<P64>(HopCfg{K2, F_NOA, t.nb64}, (from_b ? t.dprep0 : t.dprep).template as<HopJob<P64>>(),
                                      t.nprep, t.bprep, s));
-            DLMA_HIP(launch_norm<P64>(t.dvnE.template as<VecJob<P64>>(), t.nconv, t.bvnE, s));
+            DLMA_HIP(launch_norm<P64>((from_b ? t.dvnE0 : t.dvnE).template as<VecJob<P64>>(), t.nconv, t.bvnE, s));
             DLMA_HIP(launch_finish(t.dfinE.template as<FinJob>(), t.nfin, t.bfin, FIN_NORM, s));
         }
-        DLMA_HIP(launch_conv_from64<P>(t.dconv.template as<VecJob<P>>(), t.nconv, t.bconv, t.dconv64.template as<VecJob<P64>>(), s));
+        DLMA_HIP(launch_conv_from64<P>(t.dconv.template as<VecJob<P>>(), t.nconv, t.bconv,
+                                       (from_b ? t.dconv640 : t.dconv64).template as<VecJob<P64>>(), s));
         for (auto& f : t.hfinI) { f.rel2 = rel * rel; f.maxit = std::max(1, o.maxiter - maxused); }
         for (auto& f : t.hfinAB) f.maxit = std::max(1, o.maxiter - maxused);
         DLMA_HIP(hipMemcpyAsync(t.dfinI.p, t.hfinI.data(), sizeof(FinJob) * t.hfinI.size(), hipMemcpyHostToDevice, s));

@@ -153,6 +153,16 @@ HD Nbr neighbours(const Geo& g, int par, int cb) {
     return o;
 }
 
+// Whether source r may be nonzero at timeslice t, dilated by tdil timeslices either
+// way (periodic); true without support flags.
+HD bool tsup_any(const int* tsup, int T, int r, int t, int tdil) {
+    if (!tsup) return true;
+    const int* f = tsup + (size_t)r * T;
+    int any = f[t];
+    for (int d = 1; d <= tdil; ++d) any |= f[t + d < T ? t + d : t + d - T] | f[t - d >= 0 ? t - d : t - d + T];
+    return any != 0;
+}
+
 // ---------------------------------------------------------------- field views
 
 // A set of nrhs half-lattice spinor fields: element (r, comp, site) at

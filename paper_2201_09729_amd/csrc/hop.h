@@ -62,6 +62,11 @@ template <int P> struct HopJob {
     SF<P> in, x, b, out, r, xs;
     SF<P16> in16;         // F_IN16: hopping input in FP16 storage (grouped words, site scales)
     const double* in16s;  // F_IN16: [nrhs] squared factor of in16
+    // FP64 kernels: timeslice support flags [nrhs][T] of the source B (see VecJob) or
+    // nullptr.  Jobs that read B skip it where it vanishes: b (F_HASB) and d (F_HASD)
+    // on unflagged timeslices, and the pass-0 Schur source (F_NOA, from B_e and
+    // A_oo^-1 B_o) is zero where t - 1 .. t + 1 are all unflagged.
+    const int* tsup;
     const double* alpha;  // [nrhs] (F_CG)
     const int* active;    // [nrhs] or nullptr: inactive right-hand sides are skipped
     double* part;         // partial squared norms (F_NORM / F_CG): part[r * pstride + site block]
@@ -151,6 +156,22 @@ HD void hop_site(const HopJob<P>& J, int cb, int g0, double (&qs)[NB][HOP_NQ_MAX
     for (int j = 0; j < NB; ++j)
 #pragma unroll
         for (int i = 0; i < 24; ++i) acc[j][i] = 0;
+    // timeslice of the site (uniform over the block) for the source-support tests
+    const int tsite = J.tsup ? cb / J.vt : 0;
+    if constexpr (KIND == K2 && (FL & F_NOA) != 0) {
+        // Schur source of a source that vanishes on t - 1 .. t + 1: zero, nothing to load
+        if (J.tsup) {
+            bool any = false;
+#pragma unroll
+            for (int j = 0; j < NB; ++j) any = any || (use[j] && tsup_any(J.tsup, J.g.T, g0 + j, tsite, 1));
+            if (!any) {
+#pragma unroll
+                for (int j = 0; j < NB; ++j)
+                    if (use[j]) store_spinor<P, R>(J.out, Vh, g0 + j, cb, acc[j]);
+                return;
+            }
+        }
+    }
 
     Nbr nb = neighbours(J.g, J.par, cb);
     constexpr bool G5IN = (FL & F_G5IN) != 0;
@@ -171,7 +192,7 @@ HD void hop_site(const HopJob<P>& J, int cb, int g0, double (&qs)[NB][HOP_NQ_MAX
             if (use[j]) {
 #pragma unroll
                 for (int i = 0; i < 24; ++i) acc[j][i] *= ch;
-                if (FL & F_HASD) {
+                if ((FL & F_HASD) && tsup_any(J.tsup, J.g.T, g0 + j, tsite, 0)) {
                     R d[24];
                     load_spinor<P, R>(J.x, Vh, g0 + j, cb, d);
 #pragma unroll
@@ -242,7 +263,7 @@ HD void hop_site(const HopJob<P>& J, int cb, int g0, double (&qs)[NB][HOP_NQ_MAX
 #pragma unroll
         for (int j = 0; j < NB; ++j)
             if (use[j]) {
-                if (FL & F_HASB) {
+                if ((FL & F_HASB) && tsup_any(J.tsup, J.g.T, g0 + j, tsite, 0)) {
                     R bv[24];
                     load_spinor<P, R>(J.b, Vh, g0 + j, cb, bv);
                     const R cbc = (R)J.cb;

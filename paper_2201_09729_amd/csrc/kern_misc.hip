@@ -458,6 +458,11 @@ __global__ void __launch_bounds__(VEC_BS) k_clover_apply64(const VecJob<P64>* jo
     vec_locate(jobs, njob, J, r, cb, sb);
     if (cb >= J->Vh) return;
     double x[24], y[24];
+    if (!tsup_any(J->tsup, J->T, r, J->vt > 0 ? cb / J->vt : 0, J->tdil)) {  // a is zero here
+        for (int i = 0; i < 24; ++i) y[i] = 0.0;
+        store_spinor<P64, double>(J->c, J->Vh, r, cb, y);
+        return;
+    }
     load_spinor<P64, double>(J->a, J->Vh, r, cb, x);
     for (int blk = 0; blk < 2; ++blk) {
         double c[36];
@@ -485,7 +490,8 @@ template <int P> __global__ void __launch_bounds__(VEC_BS) k_conv_from64(const V
     }
     if (cb < J->Vh) {
         double x[24];
-        load_spinor<P64, double>(S->a, J->Vh, r, cb, x);
+        if (tsup_any(S->tsup, S->T, r, S->vt > 0 ? cb / S->vt : 0, S->tdil)) load_spinor<P64, double>(S->a, J->Vh, r, cb, x);
+        else for (int i = 0; i < 24; ++i) x[i] = 0.0;  // the source is zero here
         double n2 = J->s[r];
         double sc = n2 > 0 ? 1.0 / sqrt(n2) : 0.0;
         typename PT<P>::R y[24], z[24];
@@ -562,10 +568,23 @@ template <int P> __global__ void __launch_bounds__(VEC_BS) k_norm(const VecJob<P
     const VecJob<P>* J; int r, cb, sb;
     vec_locate(jobs, njob, J, r, cb, sb);
     double nrm = 0;
-    if (cb < J->Vh) {
+    const int t = (cb < J->Vh && J->vt > 0) ? cb / J->vt : -1;
+    bool nz = false;
+    if (cb < J->Vh && tsup_any(J->tsup, J->T, r, t, J->tdil)) {
         typename PT<P>::R a[24];
         load_spinor<P, typename PT<P>::R>(J->a, J->Vh, r, cb, a);
-        for (int i = 0; i < 24; ++i) nrm += (double)a[i] * (double)a[i];
+        for (int i = 0; i < 24; ++i) {
+            nrm += (double)a[i] * (double)a[i];
+            nz = nz || a[i] != 0;  // NaN counts as nonzero
+        }
+    }
+    if (J->tsup_out) {
+        // record the timeslices where a is nonzero: one atomic per run of lanes of the
+        // wave with a nonzero site on the same timeslice
+        const int lane = (int)threadIdx.x & 63;
+        const int tu = __shfl_up(t, 1, 64);
+        const int nzu = __shfl_up(nz ? 1 : 0, 1, 64);
+        if (nz && t >= 0 && (lane == 0 || tu != t || !nzu)) atomicOr(&J->tsup_out[(size_t)r * J->T + t], 1);
     }
     write_partial<VEC_BS>(nrm, J->part, (long)r * J->pstride + sb);
 }

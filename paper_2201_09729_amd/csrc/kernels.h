@@ -14,6 +14,14 @@ template <int P> struct VecJob {
     const int* active;    // per right-hand side flag or nullptr
     double* part;         // partial squared norms, row stride pstride
     int pstride;
+    // Timeslice support of the source: flag [r][t] = 1 where source r has a nonzero
+    // component on timeslice t (either parity).  k_norm records it (tsup_out); the
+    // pass-0 kernels read it (tsup) and skip the loads of an input known to be zero:
+    // the input vanishes on timeslice t when the flags of t - tdil .. t + tdil are all 0.
+    int* tsup_out;
+    const int* tsup;
+    int tdil;
+    int vt, T;            // sites of one parity per timeslice, timeslices
 };
 constexpr int VEC_BS = 256;
 
