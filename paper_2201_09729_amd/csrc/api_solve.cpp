@@ -53,6 +53,7 @@ struct Cfg {
     Buf nr, np, nw, nxs, ny;         // FP16 scales
     Buf part;                        // partial norms
     Buf tsup;                        // [nrhs][T] timeslice support of B (VecJob::tsup)
+    Buf tdist;                       // [nrhs][T] distance to that support (in_reach), 0 after the first pass
     Buf parts;                       // BiCGStab, FP16: partials of (rh, s) from the s step
     Buf bs, bt, brh, nbs, nbt, nbrh;    // BiCGStab: s, t, shadow residual (precision P) and FP16 scales
     Buf bstate;                      // BiCGStab: rho alpha omega beta (complex, per rhs)
@@ -106,6 +107,7 @@ template <int P> int alloc_cfg(Cfg& c, bool bicg, hipStream_t s) {
     DLMA_TRY(c.B.allocate(full64));
     DLMA_TRY(c.X.allocate(full64));
     DLMA_TRY(c.tsup.allocate(sizeof(int) * (size_t)c.nrhs * g->geo.T));
+    DLMA_TRY(c.tdist.allocate(sizeof(int) * (size_t)c.nrhs * g->geo.T));
     DLMA_TRY(c.R.allocate(full64));
     DLMA_TRY(c.T.allocate(half64));
     DLMA_TRY(c.E.allocate(half64));
@@ -324,6 +326,12 @@ template <int P> int build_tables(std::vector<Cfg>& cs, Tables<P>& t, int nb, in
                 bv.alpha = c.balpha; bv.omega = c.bomega; bv.beta = c.bbeta;
                 bv.active = c.active; bv.part = c.part.as<double>(); bv.pstride = c.vnsb;
                 bv.part_s = c.parts.as<double>();
+                if (P == P16) {
+                    bv.tdist = c.tdist.as<int>();
+                    bv.titer = c.iters;
+                    bv.vt = g->geo.Z * g->geo.Y * g->geo.Xh;
+                    bv.T = g->geo.T;
+                }
                 bvv.push_back(bv);
                 BiFinJob bf = {};
                 bf.nrhs = n; bf.rhs0 = rhs0BF; rhs0BF += n; bf.npart = c.vnsb; bf.nparth = c.hnsb;
@@ -565,6 +573,13 @@ int solve_impl(std::vector<Cfg>& cs, const dlma_solve_opts& o, hipStream_t s) {
         DLMA_HIP(hipMemsetAsync(c.tsup.p, 0, c.tsup.n, s));  // set by the norm of B
     }
     DLMA_HIP(launch_norm<P64>(t.dvnB.template as<VecJob<P64>>(), t.nvnB, t.bvnB, s));
+    // first pass from x = 0 (FP16 BiCGStab): distances to each source's support, for the
+    // reach of the Krylov vectors; otherwise 0 (everything within reach)
+    const bool reach_skip = P == P16 && t.bicg && !o.use_x0;
+    for (auto& c : cs) {
+        if (reach_skip) DLMA_HIP(launch_tdist(c.tsup.as<int>(), c.tdist.as<int>(), c.nrhs, c.g->geo.T, s));
+        else DLMA_HIP(hipMemsetAsync(c.tdist.p, 0, c.tdist.n, s));
+    }
     DLMA_HIP(launch_finish(t.dfinB.template as<FinJob>(), t.nfin, t.bfin, FIN_NORM, s));
     for (auto& c : cs) DLMA_HIP(hipMemcpyAsync(c.bnorm2.data(), c.nrm, sizeof(double) * c.nrhs, hipMemcpyDeviceToHost, s));
     DLMA_HIP(hipStreamSynchronize(s));
@@ -743,6 +758,15 @@ int solve_impl(std::vector<Cfg>& cs, const dlma_solve_opts& o, hipStream_t s) {
             DLMA_HIP(hipMemcpyAsync(t.dbf.p, t.hbf.data(), sizeof(BiFinJob) * t.hbf.size(), hipMemcpyHostToDevice, s));
             DLMA_HIP(launch_bivec<P>(t.dbv.template as<BiVecJob<P>>(), t.nbv, t.bbv, BV_RR, s));
             DLMA_HIP(launch_bifinish(t.dbf.template as<BiFinJob>(), t.nbv, t.bbf, BF_INIT, s));
+        }
+        if (reach_skip) {
+            for (auto& c : cs) {
+                if (from_b) {  // s, which the s step leaves untouched beyond its reach, starts at zero
+                    for (Buf* f : {&c.bs, &c.nbs}) DLMA_HIP(hipMemsetAsync(f->p, 0, f->n, s));
+                } else if (pass == 1) {  // dense from here on: everything within reach
+                    DLMA_HIP(hipMemsetAsync(c.tdist.p, 0, c.tdist.n, s));
+                }
+            }
         }
         std::vector<int> nact(ncfg);
         for (int i = 0; i < ncfg; ++i) nact[i] = (int)std::count(cs[i].hact.begin(), cs[i].hact.end(), 1);

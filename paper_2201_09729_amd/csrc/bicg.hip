@@ -210,7 +210,11 @@ template <int P, int MODE> __global__ void __launch_bounds__(VEC_BS) k_bivec(con
     const bool act = rhs_active(J, r);  // uniform over the block
     double q0 = 0, q1 = 0, q2 = 0;
     if constexpr (P == P16 && (MODE == BV_S || MODE == BV_XR || MODE == BV_P || MODE == BV_SH || MODE == BV_XRP)) {
-        if (act && cb < J.Vh) bivec16<MODE>(J, r, (uint32_t)cb, q0, q1, q2);
+        // first pass: beyond the reach of the outputs everything is zero and stays so
+        constexpr int reach = MODE == BV_SH ? 3 : 5;
+        const bool near = (MODE != BV_SH && MODE != BV_XRP) || cb >= J.Vh ||
+                          in_reach(J.tdist, J.titer, J.T, r, J.tdist ? cb / J.vt : 0, reach);
+        if (act && near && cb < J.Vh) bivec16<MODE>(J, r, (uint32_t)cb, q0, q1, q2);
     } else if constexpr (MODE == BV_SH || MODE == BV_XRP) {
         // the merged iteration exists for FP16 fields only (launch_bivec refuses the others)
     } else if (act && cb < J.Vh) {

@@ -163,6 +163,21 @@ HD bool tsup_any(const int* tsup, int T, int r, int t, int tdil) {
     return any != 0;
 }
 
+// Reach of the first pass's Krylov vectors.  From x = 0 the first inner solve starts
+// on the Schur source, which is nonzero only within 1 timeslice of the source's
+// support, and each application of the Schur operator (two hops) widens that by 2:
+// after k iterations the s of BiCGStab is nonzero only within 3 + 4k timeslices and
+// the updated x, r, p within 5 + 4k.  tdist[r][t] is the distance (periodic) from t
+// to the nearest timeslice where source r is nonzero, or 0 everywhere once the
+// vectors are dense (later passes); the FP16 vector steps skip the sites beyond the
+// reach, whose values are exact zeros.  (The stencils do not: a block that exits
+// early still costs its dispatch and the loads of its decision, about what the
+// skipped work saves.)
+HD bool in_reach(const int* tdist, const int* titer, int T, int r, int t, int c) {
+    if (!tdist) return true;
+    return tdist[(size_t)r * T + t] <= c + 4 * titer[r];
+}
+
 // ---------------------------------------------------------------- field views
 
 // A set of nrhs half-lattice spinor fields: element (r, comp, site) at

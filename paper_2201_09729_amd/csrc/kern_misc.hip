@@ -472,6 +472,25 @@ __global__ void __launch_bounds__(VEC_BS) k_clover_apply64(const VecJob<P64>* jo
     store_spinor<P64, double>(J->c, J->Vh, r, cb, y);
 }
 
+__global__ void __launch_bounds__(256) k_tdist(const int* flags, int* dist, int nrhs, int T) {
+    const int i = blockIdx.x * 256 + (int)threadIdx.x;
+    if (i >= nrhs * T) return;
+    const int r = i / T, t = i - r * T;
+    int best = 1 << 28;
+    for (int u = 0; u < T; ++u)
+        if (flags[(size_t)r * T + u]) {
+            const int d = t > u ? t - u : u - t;
+            best = min(best, min(d, T - d));
+        }
+    dist[i] = best;
+}
+
+hipError_t launch_tdist(const int* flags, int* dist, int nrhs, int T, hipStream_t s) {
+    if (nrhs * T <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_tdist, dim3((unsigned)((nrhs * T + 255) / 256)), dim3(256), 0, s, flags, dist, nrhs, T);
+    return hipGetLastError();
+}
+
 hipError_t launch_clover_apply64(const VecJob<P64>* j, int njob, int nblocks, hipStream_t s) {
     hipLaunchKernelGGL(k_clover_apply64, dim3(nblocks), dim3(VEC_BS), 0, s, j, njob);
     return hipGetLastError();

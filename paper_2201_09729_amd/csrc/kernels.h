@@ -54,6 +54,11 @@ template <int P> struct BiVecJob {
     double* part;
     int pstride;
     double* part_s;  // BV_SH's partials of (rh, s), part_s[(r * 2 + q) * pstride + block] (FP16 path)
+    // first pass, FP16: sites beyond the reach of the step's outputs (in_reach; s: 3,
+    // x/r/p: 5) are skipped; vt = sites of one parity per timeslice
+    const int* tdist;
+    const int* titer;
+    int vt, T;
 };
 enum BiVecMode {
     BV_RR = 0,    // part: (rh, r)                                   NQ = 2 (re, im)
@@ -119,6 +124,9 @@ hipError_t launch_eo_to_canon(const double2* eo, double2* can, const Geo& g, int
 
 // vector kernels (jobs in device memory, total blocks given)
 hipError_t launch_clover_apply64(const VecJob<P64>* j, int njob, int nblocks, hipStream_t s);  // c = C a
+// dist[r][t] = periodic distance from t to the nearest t' with flags[r][t'] != 0
+// (2^28 if there is none), for nrhs x T entries
+hipError_t launch_tdist(const int* flags, int* dist, int nrhs, int T, hipStream_t s);
 template <int P> hipError_t launch_conv_from64(const VecJob<P>* j, int njob, int nblocks, const VecJob<P64>* j64, hipStream_t s);
 template <int P> hipError_t launch_accum_to64(const VecJob<P>* j, const VecJob<P64>* j64, int njob, int nblocks, hipStream_t s);
 template <int P> hipError_t launch_xpay(const VecJob<P>* j, int njob, int nblocks, hipStream_t s);       // b = a + s*b
