@@ -208,6 +208,13 @@ template <int P, int MODE> __global__ void __launch_bounds__(VEC_BS) k_bivec(con
     const int sb = lb - r * J.nsb;
     const int cb = sb * VEC_BS + (int)threadIdx.x;
     const bool act = rhs_active(J, r);  // uniform over the block
+    constexpr int NQ = (MODE == BV_RR || MODE == BV_RV || MODE == BV_SH) ? 2
+                       : ((MODE == BV_TS || MODE == BV_XR) ? 3 : (MODE == BV_XRP ? 1 : 0));
+    double* part = MODE == BV_SH ? J.part_s : J.part;
+    if (!act) {  // the whole block: zero partials, no block sums
+        if ((int)threadIdx.x < NQ) part[((long)r * NQ + (int)threadIdx.x) * J.pstride + sb] = 0.0;
+        return;
+    }
     double q0 = 0, q1 = 0, q2 = 0;
     if constexpr (P == P16 && (MODE == BV_S || MODE == BV_XR || MODE == BV_P || MODE == BV_SH || MODE == BV_XRP)) {
         // first pass: beyond the reach of the outputs everything is zero and stays so
@@ -286,9 +293,6 @@ template <int P, int MODE> __global__ void __launch_bounds__(VEC_BS) k_bivec(con
             store_spinor<P, R>(J.p, J.Vh, r, cb, b);
         }
     }
-    constexpr int NQ = (MODE == BV_RR || MODE == BV_RV || MODE == BV_SH) ? 2
-                       : ((MODE == BV_TS || MODE == BV_XR) ? 3 : (MODE == BV_XRP ? 1 : 0));
-    double* part = MODE == BV_SH ? J.part_s : J.part;
     if (NQ > 0) bi_partial(q0, part, ((long)r * NQ + 0) * J.pstride + sb);
     if (NQ > 1) bi_partial(q1, part, ((long)r * NQ + 1) * J.pstride + sb);
     if (NQ > 2) bi_partial(q2, part, ((long)r * NQ + 2) * J.pstride + sb);
