@@ -204,6 +204,10 @@ template <int P> int build_tables(std::vector<Cfg>& cs, Tables<P>& t, int nb, in
             if (par == 0) {  // with R_o = 0 the even residual is the Schur source E itself
                 HopJob<P64> je = j;
                 je.out = half_view<P64>(c.E.p, nullptr, Vh);
+                if (P == P16) {  // x_e += e of the last inner solve, fused (F_ACCX)
+                    je.in16 = half_view<P16>(c.xs.p, nrm_of<P16>(c.nxs), Vh);
+                    je.in16s = c.enrm;
+                }
                 residE.push_back(je);
             }
             VecJob<P64> v = {};
@@ -624,7 +628,15 @@ int solve_impl(std::vector<Cfg>& cs, const dlma_solve_opts& o, hipStream_t s) {
     // sites: 0 both parities, 1 even (odd partials 0), both for the right-hand sides of
     // the last pass (the others keep their norms); 2 odd sites of every right-hand
     // side, added to the norms held on the host
+    // FP16 inner solves: the accumulation x_e += e of a pass is left to the even-site
+    // residual that starts the next one (F_ACCX); acc_pending marks it as owed
+    bool acc_pending = false;
     auto true_residual = [&](int sites) -> int {
+        if (acc_pending && sites != 1) {  // not reached (the next residual is the even one); kept exact
+            DLMA_HIP(launch_accum_to64<P>(t.dacc.template as<VecJob<P>>(), t.dacc64.template as<VecJob<P64>>(), t.nconv,
+                                          t.bconv, s));
+            acc_pending = false;
+        }
         if (sites == 2) {
             for (auto& c : cs)
                 DLMA_HIP(hipMemset2DAsync(c.part.as<double>(), 2 * sizeof(double) * c.hnsb, 0, sizeof(double) * c.hnsb,
@@ -634,8 +646,9 @@ int solve_impl(std::vector<Cfg>& cs, const dlma_solve_opts& o, hipStream_t s) {
             for (auto& c : cs)  // the odd sites' partial norms are zero
                 DLMA_HIP(hipMemset2DAsync(c.part.as<double>() + c.hnsb, 2 * sizeof(double) * c.hnsb, 0,
                                           sizeof(double) * c.hnsb, c.nrhs, s));
-            DLMA_HIP(launch_hop<P64>(HopCfg{K2, F_HASB | F_NORM, t.nb64}, t.dresidE.template as<HopJob<P64>>(), t.nresidE,
-                                     t.bresidE, s));
+            DLMA_HIP(launch_hop<P64>(HopCfg{K2, F_HASB | F_NORM | (acc_pending ? F_ACCX : 0), t.nb64},
+                                     t.dresidE.template as<HopJob<P64>>(), t.nresidE, t.bresidE, s));
+            acc_pending = false;
         } else if (sites == 2) {
             DLMA_HIP(launch_hop<P64>(HopCfg{K2, F_HASB | F_NORM, t.nb64}, t.dresidO.template as<HopJob<P64>>(), t.nresidO,
                                      t.bresidO, s));
@@ -803,8 +816,9 @@ int solve_impl(std::vector<Cfg>& cs, const dlma_solve_opts& o, hipStream_t s) {
             }
             if (tot == 0) break;
         }
-        // reconstruction
-        DLMA_HIP(launch_accum_to64<P>(t.dacc.template as<VecJob<P>>(), t.dacc64.template as<VecJob<P64>>(), t.nconv, t.bconv, s));
+        // reconstruction (FP16: the even sites' accumulation is fused into the next residual)
+        if (P == P16) acc_pending = true;
+        else DLMA_HIP(launch_accum_to64<P>(t.dacc.template as<VecJob<P>>(), t.dacc64.template as<VecJob<P64>>(), t.nconv, t.bconv, s));
         constexpr int in16 = P == P16 ? F_IN16 : 0;
         if (odd_zero)
             DLMA_HIP(launch_hop<P64>(HopCfg{K1, F_ACCUM | in16, t.nb64}, t.drecon.template as<HopJob<P64>>(), t.nrecon, t.brecon, s));

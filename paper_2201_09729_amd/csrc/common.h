@@ -213,25 +213,45 @@ template <int P, class R> HD void load_spinor(const SF<P>& f, int Vh, int r, int
 // An FP16-stored site widened to FP64 and multiplied by fac: component = binary16
 // value * (scale * fac), where the binary16 value times the FP32 scale is exact in
 // FP64 and (scale * fac) is rounded once.  Every FP64 consumer of the same stored
-// field (the accumulation into x and the odd-site reconstruction) goes through this
-// one function, so all of them see bit-identical values.  The three 16-byte word
-// groups load as one 128-bit access each.
-HD void load_spinor16_f64(const SF<P16>& f, int Vh, int r, int cb, double fac, double s[24]) {
-    const double n = (double)f.nrm[(size_t)r * f.ns + cb] * fac;
+// field (the accumulation into x, whether its own kernel or fused into the next
+// residual, and the odd-site reconstruction) goes through f16_factor and f16_widen,
+// so all of them see bit-identical values.  The 16-byte word groups load as one
+// 128-bit access each.
+HD double f16_factor(const SF<P16>& f, int r, int cb, double fac) { return (double)f.nrm[(size_t)r * f.ns + cb] * fac; }
+HD double f16_widen(uint32_t bits16, double n) { return (double)h_to_f(bits16) * n; }
 #if defined(__HIP_DEVICE_COMPILE__)
-    const __attribute__((address_space(1))) uint4* q = (const __attribute__((address_space(1))) uint4*)(f.v + (size_t)r * f.rs);
+typedef const __attribute__((address_space(1))) uint4* GlobalU4;
 #else
-    const uint4* q = (const uint4*)(f.v + (size_t)r * f.rs);
+typedef const uint4* GlobalU4;
 #endif
+
+HD void load_spinor16_f64(const SF<P16>& f, int Vh, int r, int cb, double fac, double s[24]) {
+    const double n = f16_factor(f, r, cb, fac);
+    const GlobalU4 q = (GlobalU4)(f.v + (size_t)r * f.rs);
 #pragma unroll
     for (int g = 0; g < 3; ++g) {
         const uint4 v = q[(size_t)g * Vh + cb];
         const uint32_t w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            s[8 * g + 2 * k] = (double)h_to_f(w[k] & 0xffffu) * n;
-            s[8 * g + 2 * k + 1] = (double)h_to_f(w[k] >> 16) * n;
+            s[8 * g + 2 * k] = f16_widen(w[k] & 0xffffu, n);
+            s[8 * g + 2 * k + 1] = f16_widen(w[k] >> 16, n);
         }
+    }
+}
+
+// The same for the six components of half blk (spins 2 blk, 2 blk + 1), added to s.
+HD void add_half16_f64(const SF<P16>& f, int Vh, int r, int cb, int blk, double fac, double s[12]) {
+    const double n = f16_factor(f, r, cb, fac);
+    const GlobalU4 q = (GlobalU4)(f.v + (size_t)r * f.rs);
+    // components 6 blk .. 6 blk + 5 lie in word groups blk and blk + 1
+    const uint4 v0 = q[(size_t)blk * Vh + cb], v1 = q[(size_t)(blk + 1) * Vh + cb];
+    const uint32_t w[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
+    const int o = blk == 0 ? 0 : 2;  // first component of the half within the two groups
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        s[2 * k] += f16_widen(w[o + k] & 0xffffu, n);
+        s[2 * k + 1] += f16_widen(w[o + k] >> 16, n);
     }
 }
 

@@ -36,6 +36,7 @@ enum HopFlags {
     F_DOTR = 512,   // K2: partials of sum conj(r) out (re, im), r the job's r field
     F_DOTXH = 1024, // K2, FP16, with F_DOTX: also sum conj(r) out of the stored (rounded) out (re, im)
     F_IN16 = 2048,  // FP64 kernels: the hopping input is the FP16 field in16 times sqrt(in16s[r])
+    F_ACCX = 4096,  // K2, FP64: first x += in16 * sqrt(in16s[r]) (stored), then the operator on it
 };
 
 // Partial sums a stencil launch writes per right-hand side: F_DOTX | F_DOTXH 5,
@@ -104,6 +105,13 @@ template <int P, class R> HD void load_half_spinor(const SF<P>& f, int Vh, int r
 #pragma unroll
         for (int i = 0; i < 12; ++i) s[i] *= n;
     }
+}
+
+template <int P, class R> HD void store_half_spinor(const SF<P>& f, int Vh, int r, int cb, int blk, const R s[12]) {
+    static_assert(P != P16, "FP16 fields use the grouped layout of hop16.h");
+    typename PT<P>::S* b = f.v + (size_t)r * f.rs + (size_t)blk * 6 * Vh + cb;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) stp<P>(b, (size_t)c * Vh, (typename PT<P>::R)s[2 * c], (typename PT<P>::R)s[2 * c + 1]);
 }
 
 // The hopping input of right-hand side r at site cb: the job's field, or with IN16
@@ -241,6 +249,13 @@ HD void hop_site(const HopJob<P>& J, int cb, int g0, double (&qs)[NB][HOP_NQ_MAX
                     for (int i = 12; i < 24; ++i) acc[j][i] = -acc[j][i];
                 }
             }
+        // F_ACCX: the correction of the last inner solve is added to x here (the even
+        // sites' accumulation of the defect correction, fused into the next residual)
+        constexpr bool ACCX = (FL & F_ACCX) != 0;
+        static_assert(!ACCX || P == P64, "the fused accumulation is for the FP64 residual");
+        double facx[NB];
+#pragma unroll
+        for (int j = 0; j < NB; ++j) facx[j] = (ACCX && use[j]) ? sqrt(J.in16s[g0 + j]) : 0.0;
 #pragma unroll
         for (int blk = 0; blk < 2; ++blk) {
             R c[36];
@@ -250,6 +265,10 @@ HD void hop_site(const HopJob<P>& J, int cb, int g0, double (&qs)[NB][HOP_NQ_MAX
                 if (use[j]) {
                     R xv[12], t[12];
                     load_half_spinor<P, R>(J.x, Vh, g0 + j, cb, blk, xv);
+                    if constexpr (ACCX && P == P64) {
+                        add_half16_f64(J.in16, Vh, g0 + j, cb, blk, facx[j], xv);
+                        store_half_spinor<P, R>(J.x, Vh, g0 + j, cb, blk, xv);
+                    }
                     if (FL & F_NOA) {
 #pragma unroll
                         for (int i = 0; i < 12; ++i) t[i] = xv[i];

@@ -41,6 +41,7 @@ hipError_t launch_hop<DLMA_PREC>(const HopCfg& c, const HopJob<DLMA_PREC>* djobs
     // FP64 only: full operator, defect-correction residual, Schur source, reconstruction
     DLMA_HOP_ALLNB(K2, F_G5IN | F_G5OUT)
     DLMA_HOP_ALLNB(K2, F_HASB | F_NORM)
+    DLMA_HOP_ALLNB(K2, F_HASB | F_NORM | F_ACCX)  // even-site residual with the accumulation fused
     DLMA_HOP_ALLNB(K2, F_NOA)
     DLMA_HOP_ALLNB(K1, F_HASD | F_ACCUM)
     DLMA_HOP_ALLNB(K1, F_ACCUM)
