@@ -138,13 +138,16 @@ typedef struct {
     int maxiter;       /* cap on inner CG iterations per right-hand side, all passes together */
     int max_outer;     /* cap on defect-correction passes */
     int prec;          /* DLMA_PREC_* */
-    double inner_tol;  /* relative reduction of the inner residual per pass; 0 = default */
+    double inner_tol;  /* relative reduction of the inner residual per pass; 0 = default
+                          (FP16 1e-3, BF16 1e-2, FP32 1e-5) */
     int rhs_block;     /* right-hand sides per thread in the stencil kernels: 0 = autotune, or 1 .. 4 */
     int use_x0;        /* 1: x holds the start vector on entry; 0: start from x = 0 */
-    int graph_iters;   /* inner CG iterations captured in one hipGraph and replayed between host
-                          convergence checks (replaces check_every); 0 = direct launches.
-                          Direct launches are also used while dlma_profile_enable is on. */
-    int check_every;   /* CG iterations between host convergence checks (>= 1); 0 = default */
+    int graph_iters;   /* inner iterations captured in one hipGraph and replayed at the start of
+                          each pass (replaces check_every); later convergence checks of the pass
+                          follow every 2 iterations.  0 = direct launches.  Direct launches are
+                          also used while dlma_profile_enable is on. */
+    int check_every;   /* direct launches: inner iterations before the first host convergence
+                          check of a pass (>= 1; later checks every 2); 0 = default (8) */
     int dagger;        /* 1: solve D^dag x = b (x = g5 D^-1 g5 b), the adjoint solve of a backward pass */
     int lds_window;    /* FP16 stencils stage their +-x, +-y neighbours through LDS: -1 = autotuned
                           (with rhs_block), 0 = never, 1 = when they fit */
@@ -181,7 +184,9 @@ typedef struct {
  * the odd sites.  After the first reconstruction the odd residual vanishes to FP64
  * rounding, so later passes compute the residual on the even sites; the odd sites
  * of the final x are checked before the solve reports convergence.  Stops per
- * right-hand side when the FP64 true relative residual is <= tol.
+ * right-hand side when the FP64 true relative residual is <= tol.  From x = 0 the
+ * first pass skips work on timeslices where a source and its Krylov vectors are
+ * exactly zero (sources on one timeslice); the results are the same as without.
  *   gs     host array of ngauge handles (1 <= ngauge <= 16)
  *   sets   host array of ngauge rhs sets
  *   stats  host array with one entry per right-hand side (sets in order), or NULL
