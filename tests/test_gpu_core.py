@@ -161,15 +161,17 @@ def test_schur_bench_runs(D):
         assert ms > 0 and by > 0
 
 
-@pytest.mark.parametrize("rhs_block", [1, 2])
-def test_first_pass_skipping_is_exact(D, orc, rhs_block):
+@pytest.mark.parametrize("prec,rhs_block,solver", [("mix_fp16", 1, 1), ("mix_fp16", 2, 1), ("mix_fp16", 2, 0),
+                                                    ("mix_bf16", 2, 1), ("mix_fp32", 3, 1)])
+def test_first_pass_skipping_is_exact(D, orc, prec, rhs_block, solver):
     """From x = 0 the solver skips what it knows to be zero: loads of the source on
-    timeslices where it vanishes, and in the first FP16 BiCGStab pass every block
-    beyond the reach of the Krylov vectors (1 + 4k timeslices around the source after
-    k iterations, and more per stencil).  Starting instead from an explicit x0 = 0
-    skips nothing and takes the same arithmetic, so the solutions must be identical.
-    Sources: a point and a timeslice-local field at t = 3, a field on t = 3 and t = 19,
-    a dense field, a field on t = 0 (support across the periodic boundary) and zero."""
+    timeslices where it vanishes (every precision and inner solver), and in the first
+    FP16 BiCGStab pass the vector steps' sites beyond the reach of the Krylov vectors
+    (3 + 4k and 5 + 4k timeslices around the source after k iterations).  Starting
+    instead from an explicit x0 = 0 skips nothing and takes the same arithmetic, so the
+    solutions must be identical.  Sources: a point and a timeslice-local field at t = 3,
+    a field on t = 3 and t = 19, a dense field, a field on t = 0 (support across the
+    periodic boundary) and zero."""
     dims = (32, 8, 8, 8)
     U = synth.gauge_field(dims, 0.3, 2)
     g = D.dlma_load_gauge(cu(U), 0.120, 1.0)
@@ -181,9 +183,10 @@ def test_first_pass_skipping_is_exact(D, orc, rhs_block):
     b[3] = r[2]
     b[4, 0] = r[3, 0]
     bg = cu(b)
-    opts = D.default_opts(tol=1e-10, prec="mix_fp16", rhs_block=rhs_block, maxiter=4000)
+    print("first-pass skipping", prec, rhs_block, solver, flush=True)
+    opts = D.default_opts(tol=1e-10, prec=prec, rhs_block=rhs_block, maxiter=4000, inner_solver=solver)
     (x1,), s1 = D.dlma_solve([g], [bg], opts=opts)
-    opts0 = D.default_opts(tol=1e-10, prec="mix_fp16", rhs_block=rhs_block, maxiter=4000, use_x0=1)
+    opts0 = D.default_opts(tol=1e-10, prec=prec, rhs_block=rhs_block, maxiter=4000, inner_solver=solver, use_x0=1)
     (x0,), s0 = D.dlma_solve([g], [bg], xs=[torch.zeros_like(bg)], opts=opts0)
     assert torch.equal(x1, x0)
     assert [(a["outer"], a["inner_iters"], a["converged"]) for a in s1] == \
