@@ -592,6 +592,16 @@ HD void hop_site16(const HopJob<P16>& J, int cb, int g0, bool valid, const Windo
                     }
                 }
         }
+        // F_DOTR: r is the shadow residual, one field for every right-hand side (its view
+        // has RHS stride 0): loaded once per site, not once per right-hand side.  (With
+        // F_DOTXH the same hoisting pushes the kernel past its register budget.)
+        uint32_t rw[12];
+        float nr = 0.f;
+        if (FL & F_DOTR) {
+            const F16Field rf = f16_field(J.r, J.g.Vh, 0);
+            nr = wldf(rf.n, lo, 0);  // cached: one field for every RHS
+            load_words(rf, s16, G16, rw);
+        }
 #pragma unroll
         for (int j = 0; j < NB; ++j)
             if (use[j]) {
@@ -651,19 +661,15 @@ HD void hop_site16(const HopJob<P16>& J, int cb, int g0, bool valid, const Windo
                     }
                     if (FL & F_DOTXH) {  // sum conj(r) out of the stored out, r (the shadow residual) at the own site
                         const F16Field rf = f16_field(J.r, J.g.Vh, g0 + j);
-                        const float nr = wldf(rf.n, lo, 0);  // cached: one field for every RHS
-                        uint32_t rw[12];
-                        load_words(rf, s16, G16, rw);
+                        const float nrh = wldf(rf.n, lo, 0);  // cached: one field for every RHS
+                        uint32_t rwh[12];
+                        load_words(rf, s16, G16, rwh);
                         float re, im;
-                        dot16(rw, ow, re, im);
-                        qs[j][3] = (double)re * ((double)nr * om);
-                        qs[j][4] = (double)im * ((double)nr * om);
+                        dot16(rwh, ow, re, im);
+                        qs[j][3] = (double)re * ((double)nrh * om);
+                        qs[j][4] = (double)im * ((double)nrh * om);
                     }
-                    if (FL & F_DOTR) {  // sum conj(r) out, r (the shadow residual) read at the own site
-                        const F16Field rf = f16_field(J.r, J.g.Vh, g0 + j);
-                        const float nr = wldf(rf.n, lo, 0);  // cached: one field for every RHS
-                        uint32_t rw[12];
-                        load_words(rf, s16, G16, rw);
+                    if (FL & F_DOTR) {  // sum conj(r) out, r (the shadow residual) at the own site
                         float re = 0.f, im = 0.f;
 #pragma unroll
                         for (int c = 0; c < 12; ++c) {
