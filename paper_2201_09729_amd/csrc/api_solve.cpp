@@ -467,7 +467,14 @@ template <int P> int cg_iteration(std::vector<Cfg>& cs, Tables<P>& t, int nb, co
 // three separate updates.
 constexpr int bicg_dotx_flags(int P) { return P == P16 ? (F_DOTX | F_DOTXH) : F_DOTX; }
 
-template <int P> int bicg_iteration(std::vector<Cfg>& cs, Tables<P>& t, int nb, const std::vector<int>& nact, hipStream_t s) {
+// Timeslice windows of the four stencil launches of one iteration (K1 of p, K2 for v,
+// K1 of s, K2 for t; twn = 0: every timeslice).  Used by the first pass of a single
+// configuration while its Krylov vectors have not reached every timeslice.
+struct IterWin { int tw0[4], twn[4]; };
+
+template <int P>
+int bicg_iteration(std::vector<Cfg>& cs, Tables<P>& t, int nb, const std::vector<int>& nact, hipStream_t s,
+                   const IterWin* w = nullptr) {
     constexpr int FX = bicg_dotx_flags(P);
     double b1 = 0, b2v = 0, b2t = 0;
     if (Profiler::get().on)
@@ -478,12 +485,28 @@ template <int P> int bicg_iteration(std::vector<Cfg>& cs, Tables<P>& t, int nb, 
         }
     const BiVecJob<P>* bv = t.dbv.template as<BiVecJob<P>>();
     const BiFinJob* bf = t.dbf.template as<BiFinJob>();
-    DLMA_TRY(hop_launch<P>(HopCfg{K1, 0, nb, t.wn}, t.dbk1p.p, t.nk, t.bk1, KC_K1, b1, s));
-    DLMA_TRY(hop_launch<P>(HopCfg{K2, F_DOTR, nb, t.wn}, t.dbk2v.p, t.nk, t.bk2, KC_K2V, b2v, s));
+    // a windowed launch covers fewer blocks (and bytes); a windowed K2 leaves the partial
+    // sums of the other site blocks unwritten, so they are cleared first
+    auto launch = [&](int i, int kind, int flags, const Buf& jobs, int nblk, int kc, double bytes) -> int {
+        HopCfg hc{kind, flags, nb, t.wn};
+        if (w && w->twn[i] > 0) {
+            Cfg& c = cs[0];
+            const int T = c.g->geo.T;
+            hc.tw0 = w->tw0[i];
+            hc.twn = w->twn[i];
+            nblk = hop_window_blocks(c.g->geo, c.nrhs, nb, w->twn[i]);
+            bytes *= (double)w->twn[i] / T;
+            if (hop_nq(flags) > 0)
+                DLMA_HIP(hipMemsetAsync(c.part.p, 0, sizeof(double) * (size_t)c.nrhs * hop_nq(flags) * c.hnsb, s));
+        }
+        return hop_launch<P>(hc, jobs.p, t.nk, nblk, kc, bytes, s);
+    };
+    DLMA_TRY(launch(0, K1, 0, t.dbk1p, t.bk1, KC_K1, b1));
+    DLMA_TRY(launch(1, K2, F_DOTR, t.dbk2v, t.bk2, KC_K2V, b2v));
     DLMA_HIP(launch_bifinish(bf, t.nbv, t.bbf, BF_ALPHA, s));
     DLMA_HIP(launch_bivec<P>(bv, t.nbv, t.bbv, P == P16 ? BV_SH : BV_S, s));
-    DLMA_TRY(hop_launch<P>(HopCfg{K1, 0, nb, t.wn}, t.dbk1s.p, t.nk, t.bk1, KC_K1, b1, s));
-    DLMA_TRY(hop_launch<P>(HopCfg{K2, FX, nb, t.wn}, t.dbk2t.p, t.nk, t.bk2, KC_K2T, b2t, s));
+    DLMA_TRY(launch(2, K1, 0, t.dbk1s, t.bk1, KC_K1, b1));
+    DLMA_TRY(launch(3, K2, FX, t.dbk2t, t.bk2, KC_K2T, b2t));
     if (P == P16) {
         DLMA_HIP(launch_bifinish(bf, t.nbv, t.bbf, BF_OMBETA, s));
         DLMA_HIP(launch_bivec<P>(bv, t.nbv, t.bbv, BV_XRP, s));
@@ -586,7 +609,34 @@ int solve_impl(std::vector<Cfg>& cs, const dlma_solve_opts& o, hipStream_t s) {
     }
     DLMA_HIP(launch_finish(t.dfinB.template as<FinJob>(), t.nfin, t.bfin, FIN_NORM, s));
     for (auto& c : cs) DLMA_HIP(hipMemcpyAsync(c.bnorm2.data(), c.nrm, sizeof(double) * c.nrhs, hipMemcpyDeviceToHost, s));
+    // One configuration: the shortest periodic arc [arc0, arc0 + arcn) of timeslices that
+    // holds every source's support.  While the first pass's Krylov vectors have not left
+    // its neighbourhood, its stencils launch over that neighbourhood only (IterWin).
+    std::vector<int> hsup;
+    if (reach_skip && cs.size() == 1) {
+        hsup.resize((size_t)cs[0].nrhs * cs[0].g->geo.T);
+        DLMA_HIP(hipMemcpyAsync(hsup.data(), cs[0].tsup.p, sizeof(int) * hsup.size(), hipMemcpyDeviceToHost, s));
+    }
     DLMA_HIP(hipStreamSynchronize(s));
+    int arc0 = 0, arcn = 0;
+    if (!hsup.empty()) {
+        const int T = cs[0].g->geo.T;
+        std::vector<char> any(T, 0);
+        for (int r = 0; r < cs[0].nrhs; ++r)
+            for (int tt = 0; tt < T; ++tt) any[tt] |= hsup[(size_t)r * T + tt] != 0;
+        // the longest run of empty timeslices (periodic); the arc is the rest
+        int best = -1, bstart = 0;
+        for (int tt = 0; tt < T; ++tt) {
+            if (any[tt] || any[(tt + T - 1) % T] == 0) continue;  // runs start after a flagged timeslice
+            int len = 0;
+            while (len < T && !any[(tt + len) % T]) ++len;
+            if (len > best) { best = len; bstart = tt; }
+        }
+        if (best > 0) {  // otherwise every timeslice holds a source (or none does)
+            arc0 = (bstart + best) % T;
+            arcn = T - best;
+        }
+    }
     bool nan = false;
     for (auto& c : cs) {
         std::vector<double> abs2(c.nrhs);
@@ -778,10 +828,14 @@ int solve_impl(std::vector<Cfg>& cs, const dlma_solve_opts& o, hipStream_t s) {
             DLMA_HIP(launch_bivec<P>(t.dbv.template as<BiVecJob<P>>(), t.nbv, t.bbv, BV_RR, s));
             DLMA_HIP(launch_bifinish(t.dbf.template as<BiFinJob>(), t.nbv, t.bbf, BF_INIT, s));
         }
+        const bool windowed = from_b && arcn > 0;
         if (reach_skip) {
             for (auto& c : cs) {
-                if (from_b) {  // s, which the s step leaves untouched beyond its reach, starts at zero
+                if (from_b) {  // what the skipped sites and blocks leave untouched starts at zero:
+                    // s (the s step), and with windowed stencils also y, v and t
                     for (Buf* f : {&c.bs, &c.nbs}) DLMA_HIP(hipMemsetAsync(f->p, 0, f->n, s));
+                    if (windowed)
+                        for (Buf* f : {&c.y, &c.ny, &c.w, &c.nw, &c.bt, &c.nbt}) DLMA_HIP(hipMemsetAsync(f->p, 0, f->n, s));
                 } else if (pass == 1) {  // dense from here on: everything within reach
                     DLMA_HIP(hipMemsetAsync(c.tdist.p, 0, c.tdist.n, s));
                 }
@@ -789,6 +843,24 @@ int solve_impl(std::vector<Cfg>& cs, const dlma_solve_opts& o, hipStream_t s) {
         }
         std::vector<int> nact(ncfg);
         for (int i = 0; i < ncfg; ++i) nact[i] = (int)std::count(cs[i].hact.begin(), cs[i].hact.end(), 1);
+        // First pass, one configuration: while K1 of p has not reached every timeslice,
+        // iteration k launches its stencils over the sources' arc widened by their reach
+        // (2 + 4k, 3 + 4k, 4 + 4k, 5 + 4k timeslices for K1 of p, K2 for v, K1 of s, K2 for
+        // t); the vector steps skip site by site (in_reach).  These iterations run as
+        // direct launches before the replays.
+        if (windowed) {
+            const int T = cs[0].g->geo.T;
+            for (int k = 0;; ++k) {
+                IterWin w;
+                for (int i = 0; i < 4; ++i) {
+                    const int rho = 2 + i + 4 * k, W = arcn + 2 * rho;
+                    w.tw0[i] = W < T ? ((arc0 - rho) % T + T) % T : 0;
+                    w.twn[i] = W < T ? W : 0;
+                }
+                if (w.twn[0] == 0) break;
+                DLMA_TRY(bicg_iteration<P>(cs, t, nb, nact, s, &w));
+            }
+        }
         // inner CG
         if (use_graph && !ig.exec) DLMA_TRY(capture_iterations<P>(cs, t, nb, nact, check, ig));
         for (bool first = true;; first = false) {

@@ -376,7 +376,7 @@ template <int P, int NB> constexpr int hop_min_waves() { return (P == P16 && NB 
 // (NB * wn_cap * 52 bytes); a job stages its window only if it fits.
 template <int P, int NB, int KIND, int FL, int BS>
 __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(hop_min_waves<P, NB>())))
-hop_kernel(const HopJob<P>* __restrict__ jobs, int njob, int wn_cap) {
+hop_kernel(const HopJob<P>* __restrict__ jobs, int njob, int wn_cap, int tw0, int twn) {
     const int bid = blockIdx.x;
     int jb = 0;
     while (jb + 1 < njob && bid >= jobs[jb + 1].blk0) ++jb;
@@ -394,7 +394,10 @@ hop_kernel(const HopJob<P>* __restrict__ jobs, int njob, int wn_cap) {
     const int xcd = lb & 7;
     const int k = lb >> 3;
     const int T = J.g.T;
-    const int tl = xcd * T / 8, nt = (xcd + 1) * T / 8 - tl;
+    // the launch covers every timeslice (twn = 0) or the window tw0 .. tw0 + twn - 1
+    // (periodic; one job only): a first-pass launch whose input vanishes elsewhere
+    const int Tw = twn > 0 ? twn : T;
+    const int tl = xcd * Tw / 8, nt = (xcd + 1) * Tw / 8 - tl;
     if (nt == 0) return;  // more XCDs than timeslices
     const int SG = (J.sg > 0 && J.sg < J.G) ? J.sg : J.G;
     const int per = J.nbt * nt * SG;
@@ -406,7 +409,8 @@ hop_kernel(const HopJob<P>* __restrict__ jobs, int njob, int wn_cap) {
     const int q = kk / sge;
     const int gi = si * SG + (kk - q * sge);
     const int s = q / nt;
-    const int t = tl + (q - s * nt);
+    const int tw = tl + (q - s * nt);
+    const int t = twn > 0 ? (tw0 + tw < T ? tw0 + tw : tw0 + tw - T) : tw;
     const int sb = t * J.nbt + s;
     const int sx = s * BS + (int)threadIdx.x;  // site within the timeslice
     const int cb = t * J.vt + sx;

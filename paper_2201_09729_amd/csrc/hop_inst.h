@@ -8,7 +8,7 @@ namespace dlma {
 #define DLMA_HOP_CASE(KIND, FL, NB)                                                                   \
     if (c.kind == (KIND) && c.flags == (FL) && c.nb == (NB)) {                                      \
         hipLaunchKernelGGL((hop_kernel<DLMA_PREC, NB, KIND, (FL), HOP_BS>), dim3(nblocks), dim3(HOP_BS), \
-                           hop_window_bytes(NB, wn), s, djobs, njob, wn);                            \
+                           hop_window_bytes(NB, wn), s, djobs, njob, wn, c.tw0, c.twn);              \
         return hipGetLastError();                                                                    \
     }
 

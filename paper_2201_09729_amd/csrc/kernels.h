@@ -96,7 +96,10 @@ hipError_t launch_bifinish(const BiFinJob* j, int njob, int nblocks, int mode, h
 
 // wn: LDS window sites per right-hand side of the launch's FP16 jobs (the largest
 // HopJob::wn among them; 0 = none, and always 0 for other precisions)
-struct HopCfg { int kind, flags, nb, wn = 0; };
+// wn: LDS window sites of the FP16 stencils.  tw0, twn: the launch covers timeslices
+// tw0 .. tw0 + twn - 1 (periodic) of its single job; twn = 0: every timeslice (the
+// block count is then that of assign_blocks, else hop_window_blocks).
+struct HopCfg { int kind, flags, nb, wn = 0, tw0 = 0, twn = 0; };
 constexpr int HOP_BS = 128;
 
 // Dynamic LDS of an FP16 stencil launch: per right-hand side and window site, three

@@ -122,6 +122,11 @@ template <int P> HopJob<P> hop_job(const Gauge* g, int par, int nrhs, int nb, bo
 }
 
 // assign consecutive workgroup ranges; returns the total number of workgroups
+// workgroups of a stencil launch of one job restricted to twn timeslices (HopCfg)
+inline int hop_window_blocks(const Geo& g, int nrhs, int nb, int twn) {
+    return 8 * ceil_div(twn, 8) * ceil_div(g.Z * g.Y * g.Xh, HOP_BS) * ceil_div(nrhs, nb);
+}
+
 template <int P> int assign_blocks(std::vector<HopJob<P>>& jobs) {
     int b = 0;
     for (auto& j : jobs) {

@@ -161,29 +161,42 @@ def test_schur_bench_runs(D):
         assert ms > 0 and by > 0
 
 
-@pytest.mark.parametrize("prec,rhs_block,solver", [("mix_fp16", 1, 1), ("mix_fp16", 2, 1), ("mix_fp16", 2, 0),
-                                                    ("mix_bf16", 2, 1), ("mix_fp32", 3, 1)])
-def test_first_pass_skipping_is_exact(D, orc, prec, rhs_block, solver):
+@pytest.mark.parametrize("prec,rhs_block,solver,layout", [
+    ("mix_fp16", 1, 1, "mixed"), ("mix_fp16", 2, 1, "mixed"), ("mix_fp16", 2, 0, "mixed"),
+    ("mix_bf16", 2, 1, "mixed"), ("mix_fp32", 3, 1, "mixed"),
+    ("mix_fp16", 2, 1, "local"), ("mix_fp16", 1, 1, "local"), ("mix_fp16", 2, 1, "single")])
+def test_first_pass_skipping_is_exact(D, orc, prec, rhs_block, solver, layout):
     """From x = 0 the solver skips what it knows to be zero: loads of the source on
-    timeslices where it vanishes (every precision and inner solver), and in the first
-    FP16 BiCGStab pass the vector steps' sites beyond the reach of the Krylov vectors
-    (3 + 4k and 5 + 4k timeslices around the source after k iterations).  Starting
-    instead from an explicit x0 = 0 skips nothing and takes the same arithmetic, so the
-    solutions must be identical.  Sources: a point and a timeslice-local field at t = 3,
-    a field on t = 3 and t = 19, a dense field, a field on t = 0 (support across the
-    periodic boundary) and zero."""
+    timeslices where it vanishes (every precision and inner solver); in the first FP16
+    BiCGStab pass the vector steps' sites beyond the reach of the Krylov vectors (3 + 4k
+    and 5 + 4k timeslices around the source after k iterations); and, when no source is
+    dense, the first pass's stencil launches cover only the sources' arc widened by
+    their reach.  Starting instead from an explicit x0 = 0 skips nothing and takes the
+    same arithmetic, so the solutions must be identical.  Sources ("mixed"): a point
+    and a timeslice-local field at t = 3, a field on t = 3 and t = 19, a dense field, a
+    field on t = 0 (support across the periodic boundary) and zero; "local": the dense
+    one replaced by a field on t = 5 (the arc then wraps through t = 0); "single": every
+    source on t = 7, as distillation and wall sources are."""
     dims = (32, 8, 8, 8)
     U = synth.gauge_field(dims, 0.3, 2)
     g = D.dlma_load_gauge(cu(U), 0.120, 1.0)
     b = np.zeros((6,) + dims + (4, 3), dtype=np.complex128)
-    b[0] = synth.point_source(dims, (3, 1, 2, 5), 2, 1)[0]
     r = synth.random_spinor(dims, 4, 33)
-    b[1, 3] = r[0, 3]
-    b[2, 3], b[2, 19] = r[1, 3], r[1, 19]
-    b[3] = r[2]
-    b[4, 0] = r[3, 0]
+    if layout == "single":
+        b[0] = synth.point_source(dims, (7, 1, 2, 5), 2, 1)[0]
+        for i in range(4):
+            b[i + 1, 7] = r[i, 7]
+    else:
+        b[0] = synth.point_source(dims, (3, 1, 2, 5), 2, 1)[0]
+        b[1, 3] = r[0, 3]
+        b[2, 3], b[2, 19] = r[1, 3], r[1, 19]
+        if layout == "mixed":
+            b[3] = r[2]
+        else:
+            b[3, 5] = r[2, 5]
+        b[4, 0] = r[3, 0]
     bg = cu(b)
-    print("first-pass skipping", prec, rhs_block, solver, flush=True)
+    print("first-pass skipping", prec, rhs_block, solver, layout, flush=True)
     opts = D.default_opts(tol=1e-10, prec=prec, rhs_block=rhs_block, maxiter=4000, inner_solver=solver)
     (x1,), s1 = D.dlma_solve([g], [bg], opts=opts)
     opts0 = D.default_opts(tol=1e-10, prec=prec, rhs_block=rhs_block, maxiter=4000, inner_solver=solver, use_x0=1)
