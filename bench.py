@@ -690,8 +690,14 @@ def summarize(args):
     pid = PREC_ID[prec]
 
     def hop_name(kc, nb):
+        """The full kernel name of the class as rocprofv3 prints it (matched on the
+        template arguments, whatever the parameter list)."""
         kind, fl = ktemplate(kc, prec)
-        return "void dlma::hop_kernel<%d, %d, %d, %d, 128>(dlma::HopJob<%d> const*, int, int)" % (pid, nb, kind, fl, pid)
+        head = "void dlma::hop_kernel<%d, %d, %d, %d, 128>(" % (pid, nb, kind, fl)
+        for nm in step_ms:
+            if nm.startswith(head):
+                return nm
+        return head
 
     by_name = {r["Name"]: r for r in stats}
     nb = args.rhs_block
