@@ -138,8 +138,8 @@ def main():
         dist_scan(args)
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build runs the whole hot path on a single MI355X "
-              "(multi-GPU sharding is design only).", file=sys.stderr)
+        print("bench.py measures one GPU only: the library runs the whole hot path on a single MI355X "
+              "and has no multi-GPU sharding.", file=sys.stderr)
         sys.exit(2)
 
     import torch

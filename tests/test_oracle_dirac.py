@@ -208,7 +208,7 @@ def test_mass_derivative_of_solution(orc, small_system):
 
 
 def test_true_residual_vs_dense(orc, small_system):
-    """The checker of every solve test: |b - D x|_2 / |b|_2 per right-hand side, in
+    """The residual every solve test asserts on: |b - D x|_2 / |b|_2 per right-hand side, in
     FP64 and not squared (the reading of the 1e-10 residual), against the dense 4^4
     operator.  Right-hand sides of very different norms, so that a reduction over the
     wrong axes, a normalisation by |x| or a missing square root fails."""
